@@ -1,0 +1,593 @@
+"""Pins of the CPU oracle against what mathematics fixes independently of it:
+closed forms, invariants, exact solutions and brute force on tiny inputs.
+
+Each test names the part of the oracle a plausible mistake would break."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2608_19273_amd import inputs as I
+
+import exact_riemann
+
+
+def adv_batch(grid, p, a, form="f", kappa=0.0, N=1, seed=5, h=1):
+    dim = len(grid)
+    n0 = grid[0] * p
+    dx = 1.0 / n0
+    aa = list(a) + [0.0] * (3 - len(a))
+    b = I.make_uniform_batch(grid, p, h, "adv_f" if form == "f" else "adv_b", aa + [kappa], N, dx)
+    b.state = I.uniform(seed, b.total_cells * N, -1.0, 1.0)
+    return b
+
+
+# ---------------------------------------------------------------- halo ----
+
+
+def test_halo_fill_brute_force_fig2_shape():
+    """p=3, h=1, K=3 (the paper's Fig. 2 instance) in 2D and a 3D variant:
+    every face-halo value equals the neighbour's interior value at the wrapped
+    index; edges and corners are NaN."""
+    for dim, grid in ((2, (3, 1)), (3, (3, 1, 1))):
+        b = adv_batch(grid, 3, [1.0] * dim, N=2, seed=9)
+        blocks = oracle.halo_blocks(b)
+        p, h = 3, 1
+        interior = [b.patch_view(b.state, k) for k in range(b.K)]  # [N, (z,) y, x]
+        for k in range(b.K):
+            blk = blocks[k]  # [(z,) y, x, N] with halo
+            it = np.ndindex(*(p + 2 * h,) * dim)
+            for idx in it:
+                ii = [i - h for i in idx[::-1]]  # x, y, (z)
+                outside = [d for d in range(dim) if not (0 <= ii[d] < p)]
+                val = blk[idx]
+                if not outside:
+                    exp = interior[k][(slice(None),) + tuple(idx[j] - h for j in range(dim))]
+                    np.testing.assert_array_equal(val, exp)
+                elif len(outside) > 1:
+                    assert np.all(np.isnan(val))
+                else:
+                    d = outside[0]
+                    side = 0 if ii[d] < 0 else 1
+                    nb = b.nbr[k, 2 * d + side]
+                    jj = list(ii)
+                    jj[d] = ii[d] % p
+                    exp = interior[nb][(slice(None),) + tuple(jj[::-1])]
+                    np.testing.assert_array_equal(val, exp)
+
+
+def test_halo_fill_wide_halo_self_periodic():
+    """h=3 on a 4^3 self-periodic patch: halo index i maps to i mod p."""
+    b = adv_batch((1, 1, 1), 4, [1, 0, 0], N=1, h=3)
+    b.nbr = I.self_periodic(1, 3)
+    blk = oracle.halo_blocks(b)[0][..., 0]  # [z, y, x]
+    q = b.patch_view(b.state, 0)[0]
+    for x in range(-3, 7):
+        np.testing.assert_array_equal(blk[3:7, 3:7, x + 3], q[:, :, x % 4])
+        np.testing.assert_array_equal(blk[x + 3, 3:7, 3:7], q[x % 4, :, :])
+
+
+# ------------------------------------------------------- T1 exact shift ----
+
+
+@pytest.mark.parametrize("form", ["f", "b"])
+@pytest.mark.parametrize("dim,axis,sign", [(2, 0, 1), (2, 1, -1), (3, 2, 1), (3, 0, -1)])
+def test_exact_shift_cfl1(form, dim, axis, sign):
+    """Linear advection at CFL 1 along one axis moves the data by exactly one
+    cell per step (Rusanov = upwind; the non-conservative midpoint form gives
+    the same scheme).  Pins the Rusanov flux, the NCP convention, the CFL rule
+    and the periodic halo wrap across patches."""
+    grid = (2, 2) if dim == 2 else (2, 2, 2)
+    p = 4
+    a = [0.0] * dim
+    a[axis] = float(sign)
+    b = adv_batch(grid, p, a, form=form)
+    n = 3
+    q, dts, _ = oracle.fv_step(b, cfl=1.0, n_steps=n)
+    g0 = b.to_global(b.state, grid)[0]
+    g1 = b.to_global(q, grid)[0]
+    ax = dim - 1 - axis
+    np.testing.assert_allclose(g1, np.roll(g0, sign * n, axis=ax), rtol=0, atol=1e-14)
+    # p_total steps bring the data back
+    q, _, _ = oracle.fv_step(b, cfl=1.0, n_steps=grid[axis] * p)
+    np.testing.assert_allclose(q, b.state, rtol=0, atol=1e-13)
+
+
+# ---------------------------------------------- T2 closed form (any CFL) ----
+
+
+@pytest.mark.parametrize("form", ["f", "b"])
+@pytest.mark.parametrize("dim", [2, 3])
+def test_upwind_symbol_closed_form(form, dim):
+    """At any CFL the scheme is the unsplit first-order upwind scheme whose
+    Fourier symbol per step is 1 - sum_d |c_d| (1 - e^{-+ i theta_d}) - kappa dt.
+    Applying it by DFT to the IC gives the oracle's result to roundoff.  Pins
+    the flux, the dt rule, the direction bookkeeping and the source term."""
+    grid = (3, 2) if dim == 2 else (2, 2, 2)
+    p = 4
+    a = [0.7, -0.4, 0.3][:dim]
+    kappa = 0.8
+    b = adv_batch(grid, p, a, form=form, kappa=kappa, seed=21)
+    n = 5
+    cfl = 0.6
+    q, dts, _ = oracle.fv_step(b, cfl=cfl, n_steps=n)
+    dx = float(b.dx[0])
+    dt = cfl / sum(abs(x) / dx for x in a)
+    np.testing.assert_allclose(dts, dt, rtol=1e-15)
+    g0 = b.to_global(b.state, grid)[0]
+    shape = g0.shape  # [(Z,) Y, X]
+    G = np.fft.fftn(g0)
+    sym = np.ones(shape, dtype=complex) * (1.0 - kappa * dt)
+    for d in range(dim):
+        ax = dim - 1 - d
+        th = 2 * np.pi * np.fft.fftfreq(shape[ax])
+        c = a[d] * dt / dx
+        shift = np.exp(-1j * th) if a[d] > 0 else np.exp(1j * th)
+        s = -abs(c) * (1.0 - shift)
+        sh = [1] * dim
+        sh[ax] = shape[ax]
+        sym = sym + s.reshape(sh)
+    exact = np.real(np.fft.ifftn(G * sym ** n))
+    np.testing.assert_allclose(b.to_global(q, grid)[0], exact, rtol=0, atol=1e-13)
+
+
+def test_relaxation_source_uniform():
+    """uniform q with S = -kappa q: q^{n+1} = (1 - kappa dt) q^n exactly in
+    closed form (pins the source sign and the dt factor)."""
+    b = adv_batch((2, 2), 4, [0.5, 0.25], kappa=2.0)
+    b.state[:] = 3.0
+    q, dts, _ = oracle.fv_step(b, cfl=0.5, n_steps=4)
+    dt = dts[0]
+    np.testing.assert_allclose(q, 3.0 * (1 - 2.0 * dt) ** 4, rtol=1e-15)
+
+
+# --------------------------------------------------- T3 free stream -------
+
+
+def test_free_stream_euler_bitwise():
+    b = I.config0(n_patch=2, p=8)
+    g = 1.4
+    b.state = b.from_global(np.stack([np.full((16, 16), v) for v in
+                                      I.euler_prim_to_state(1.3, [0.4, -0.2], 0.9, g)]), (2, 2))
+    q, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=3)
+    np.testing.assert_array_equal(q, b.state)
+
+
+def test_free_stream_srhd_bitwise():
+    b = I.config3(grid=(2, 1, 1), p=4)
+    cons, _ = I.srhd_prim_to_cons(np.array([0.7]), np.array([0.3]), np.array([-0.2]), np.array([0.5]),
+                                  np.array([0.9]), 5.0 / 3.0)
+    b.state = np.tile(np.repeat(cons[:, 0], 64), 2)
+    q, _, st = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    np.testing.assert_array_equal(q, b.state)
+    assert st.c2p_fail == 0
+
+
+def test_free_stream_linsym_fd():
+    b = I.config2(n_patches=8, N=6, sizes=np.array([4, 8, 4, 4, 8, 4, 4, 4], np.int32))
+    for k in range(b.K):
+        v = b.patch_view(b.state, k)
+        v[:] = np.arange(1, 7)[:, None, None, None] * 0.37
+    q, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
+    np.testing.assert_allclose(q, b.state, rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------- T4 conservation ------
+
+
+def test_conservation_euler_random():
+    b = I.config0(n_patch=2, p=8)
+    rng = I.uniform(77, b.state.size, 0.9, 1.1)
+    g = b.to_global(b.state, (2, 2))
+    g = g * rng.reshape(g.shape)
+    b.state = b.from_global(g, (2, 2))
+    q, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=10)
+    for v in range(4):
+        s0 = math.fsum(b.to_global(b.state, (2, 2))[v].ravel())
+        s1 = math.fsum(b.to_global(q, (2, 2))[v].ravel())
+        scale = math.fsum(np.abs(b.to_global(b.state, (2, 2))[v]).ravel())
+        assert abs(s1 - s0) <= 1e-14 * scale
+
+
+def test_conservation_srhd_random():
+    b = I.config3(grid=(2, 2, 1), p=4, seed=13)
+    q, _, st = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    for v in range(5):
+        a0 = b.to_global(b.state, (2, 2, 1))[v]
+        a1 = b.to_global(q, (2, 2, 1))[v]
+        assert abs(math.fsum(a1.ravel()) - math.fsum(a0.ravel())) <= 1e-13 * math.fsum(np.abs(a0).ravel())
+
+
+# ------------------------------------------------- T5 entropy wave --------
+
+
+def _entropy_wave_error(npatch, p=8, T=0.1):
+    b = I.config0(n_patch=npatch, p=p)
+    n = npatch * p
+    dx = 1.0 / n
+    nsteps = int(round(T / (0.4 * dx)))
+    q, dts, _ = oracle.fv_step(b, dt_fixed=T / nsteps, n_steps=nsteps)
+    g = b.to_global(q, (npatch, npatch))
+    rho, mx, my, E = g
+    u, v = mx / rho, my / rho
+    pr = 0.4 * (E - 0.5 * (mx * mx + my * my) / rho)
+    x = (np.arange(n) + 0.5) * dx
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    exact = 1.0 + 0.2 * np.sin(2 * np.pi * (X - 0.5 * T)) * np.sin(2 * np.pi * (Y - 0.3 * T))
+    return np.mean(np.abs(rho - exact)), u, v, pr
+
+
+def test_entropy_wave_config0():
+    """Rusanov keeps u and p uniform for a contact wave (every conserved
+    update is a multiple of (1, u, v, |u|^2/2)); the density error converges
+    at first order."""
+    errs = []
+    for npatch in (4, 8, 16):
+        e, u, v, pr = _entropy_wave_error(npatch)
+        np.testing.assert_allclose(u, 0.5, atol=1e-13)
+        np.testing.assert_allclose(v, 0.3, atol=1e-13)
+        np.testing.assert_allclose(pr, 1.0, atol=1e-13)
+        errs.append(e)
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 1.6 < r1 < 2.4 and 1.7 < r2 < 2.3, errs
+
+
+def test_config0_dt_formula():
+    """dt = cfl / sum_d(Lambda_d / dx) with Lambda_d = max |u_d| + c."""
+    b = I.config0()
+    dt, lam = oracle.cfl_dt(b, cfl=0.4)
+    g = b.to_global(b.state, (8, 8))
+    c = np.sqrt(1.4 * 1.0 / g[0])
+    lx, ly = np.max(0.5 + c), np.max(0.3 + c)
+    np.testing.assert_allclose(lam[:2], [lx, ly], rtol=1e-14)
+    np.testing.assert_allclose(dt, 0.4 / (lx * 64 + ly * 64), rtol=1e-14)
+
+
+# ------------------------------------------------------------ T6 Sod ------
+
+
+def _sod(nx_patch, p=8, T=0.2):
+    """double Sod tube on the periodic [0,2] x [0, p dx]; compare on [0,1]."""
+    n = nx_patch * p
+    dx = 2.0 / n
+    b = I.make_uniform_batch((nx_patch, 1), p, 1, "euler", [1.4], 4, dx)
+    x = (np.arange(n) + 0.5) * dx
+    left = (x < 0.5) | (x >= 1.5)
+    rho = np.where(left, 1.0, 0.125)
+    pr = np.where(left, 1.0, 0.1)
+    R = np.repeat(rho[None, :], p, 0)
+    P = np.repeat(pr[None, :], p, 0)
+    Z = np.zeros_like(R)
+    b.state = b.from_global(np.stack(I.euler_prim_to_state(R, [Z, Z], P, 1.4)), (nx_patch, 1))
+    t = 0.0
+    q = b.state
+    while t < T - 1e-14:
+        dt, _ = oracle.cfl_dt(b, q, cfl=0.4)
+        dt = min(dt, T - t)
+        q, _, _ = oracle.fv_step(b, q, dt_fixed=dt, n_steps=1)
+        t += dt
+    g = b.to_global(q, (nx_patch, 1))[0][0]  # density row
+    sel = x < 1.0
+    ex = exact_riemann.sample((x[sel] - 0.5) / T, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)[0]
+    return np.mean(np.abs(g[sel] - ex))
+
+
+@pytest.mark.slow
+def test_sod_against_exact_riemann():
+    ps, us = exact_riemann.star_state(1.0, 0.0, 1.0, 0.125, 0.0, 0.1)
+    assert abs(ps - 0.30313) < 1e-5 and abs(us - 0.92745) < 1e-5
+    e1 = _sod(16)
+    e2 = _sod(32)
+    assert e1 < 0.04 and e2 < e1
+    order = math.log2(e1 / e2)
+    assert 0.4 < order < 1.1, (e1, e2, order)
+
+
+# ------------------------------------------- T7 FD4 + KO6 + RK4 -----------
+
+
+def _linsym_small(N=5, seed=3, p=8, npatch=(2, 1, 1), B=None):
+    if B is None:
+        Bs, rhos = I.linsym_matrices(seed, N)
+    else:
+        Bs, rhos = B
+    n0 = npatch[0] * p
+    b = I.make_uniform_batch(npatch, p, 3, "linsym", I.linsym_params(Bs, rhos), N, 1.0 / n0)
+    return b, Bs, rhos
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.1])
+def test_fd4_ko6_rk4_plane_wave_closed_form(sigma):
+    """A plane wave along x on an eigenvector r of B_x: each step multiplies
+    it by R(z) = 1 + z + z^2/2 + z^3/6 + z^4/24 with
+    z = dt [-i lam (8 sin t - sin 2t)/(6 dx) - sigma sin^6(t/2)/dx].
+    Pins D4, the KO sign and scale, the RK4 tableau and B.grad Q."""
+    N = 5
+    b, Bs, rhos = _linsym_small(N=N)
+    lamv, vecs = np.linalg.eigh(Bs[0])
+    j = 3
+    lam, r = lamv[j], vecs[:, j]
+    n = b.p[0] * 2  # cells along x
+    dx = float(b.dx[0])
+    kwave = 3
+    theta = 2 * np.pi * kwave / n
+    xi = np.arange(n)
+    g = np.zeros((N, 8, 8, n))
+    g[:] = (r[:, None] * np.cos(theta * xi)[None, :])[:, None, None, :]
+    b.state = b.from_global(g, (2, 1, 1))
+    nsteps = 6
+    q, dts = oracle.fd_step(b, cfl=0.5, sigma=sigma, n_steps=nsteps)
+    dt = dts[0]
+    np.testing.assert_allclose(dt, 0.5 / (sum(rhos) / dx), rtol=1e-15)
+    z = dt * (-1j * lam * (8 * np.sin(theta) - np.sin(2 * theta)) / (6 * dx) - sigma * np.sin(theta / 2) ** 6 / dx)
+    R = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    ex = np.real(R ** nsteps * np.exp(1j * theta * xi))
+    got = b.to_global(q, (2, 1, 1))
+    np.testing.assert_allclose(got, (r[:, None] * ex[None, :])[:, None, None, :] * np.ones((1, 8, 8, 1)),
+                               rtol=0, atol=2e-14)
+
+
+def test_fd_energy_nonincreasing():
+    """Symmetric constant B with a skew-adjoint D4 conserves ||Q||^2 in the
+    semi-discrete limit, KO only removes energy and RK4 damps below its
+    stability limit: the discrete energy must not grow (and must shrink with
+    sigma > 0)."""
+    b, Bs, rhos = _linsym_small(N=6, seed=8, p=8)
+    b.state = I.uniform(3, b.state.size, -1, 1)
+    e0 = np.sum(b.state ** 2)
+    q1, _ = oracle.fd_step(b, sigma=0.0, n_steps=3)
+    q2, _ = oracle.fd_step(b, sigma=0.1, n_steps=3)
+    e1, e2 = np.sum(q1 ** 2), np.sum(q2 ** 2)
+    assert e1 <= e0 * (1 + 1e-13)
+    assert e2 < e1
+
+
+def test_fd_forward_euler_stage_count():
+    """rk_stages=1 is Q + dt R(Q): on a plane wave the factor is 1 + z."""
+    N = 3
+    b, Bs, rhos = _linsym_small(N=N, seed=4)
+    lamv, vecs = np.linalg.eigh(Bs[0])
+    lam, r = lamv[0], vecs[:, 0]
+    n = 16
+    theta = 2 * np.pi * 2 / n
+    xi = np.arange(n)
+    g = np.zeros((N, 8, 8, n)) + (r[:, None] * np.cos(theta * xi))[:, None, None, :]
+    b.state = b.from_global(g, (2, 1, 1))
+    q, dts = oracle.fd_step(b, sigma=0.1, rk_stages=1, n_steps=1)
+    dx = float(b.dx[0])
+    z = dts[0] * (-1j * lam * (8 * np.sin(theta) - np.sin(2 * theta)) / (6 * dx) - 0.1 * np.sin(theta / 2) ** 6 / dx)
+    ex = np.real((1 + z) * np.exp(1j * theta * xi))
+    np.testing.assert_allclose(b.to_global(q, (2, 1, 1))[:, 3, 4, :], r[:, None] * ex[None, :], atol=1e-14)
+
+
+def test_fd_flux_form_matches_ncp_form_for_advection():
+    """For linear advection F = a q and B = a give the same FD4 scheme
+    (D4 is linear), pinning the flux-differencing branch."""
+    bf = adv_batch((2, 1, 1), 8, [0.6, 0.2, -0.3], form="f", h=3)
+    bb = adv_batch((2, 1, 1), 8, [0.6, 0.2, -0.3], form="b", h=3)
+    qf, _ = oracle.fd_step(bf, cfl=0.5, sigma=0.05, n_steps=2)
+    qb, _ = oracle.fd_step(bb, cfl=0.5, sigma=0.05, n_steps=2)
+    np.testing.assert_allclose(qf, qb, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------ T9 con2prim -------
+
+
+def test_input_prim2cons_matches_oracle():
+    rho, vx, vy, vz, eps = I.srhd_primitives(5, 2000)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, 5 / 3)
+    prim = np.stack([rho, vx, vy, vz, p])
+    np.testing.assert_allclose(oracle.srhd_prim2cons(prim), cons, rtol=2e-15)
+
+
+def test_con2prim_round_trip():
+    """prim -> cons -> prim over the config-3 distribution.  The recovered
+    pressure is limited by the conditioning eps_mach W^2 / eps of the
+    cancellation in f, not by the iteration."""
+    n = 20000
+    rho, vx, vy, vz, eps = I.srhd_primitives(11, n)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, 5 / 3)
+    prim, it, st, nfail, _ = oracle.con2prim(cons)
+    assert nfail == 0 and np.all(st == 0)
+    rel = np.abs(prim[4] - p) / p
+    W2 = 1.0 / (1 - (vx ** 2 + vy ** 2 + vz ** 2))
+    assert rel.max() < 1e-10
+    well = W2 / eps < 1e3
+    assert rel[well].max() < 1e-12
+    np.testing.assert_allclose(prim[0], rho, rtol=1e-10)
+    for i, v in enumerate((vx, vy, vz)):
+        np.testing.assert_allclose(prim[1 + i], v, rtol=0, atol=1e-12)
+    assert 4 <= it.mean() <= 9 and it.max() <= 20
+
+
+def test_con2prim_high_precision_root():
+    """recovered p against a 40-digit root of the same (rounded) conserved
+    inputs."""
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 40
+    rho, vx, vy, vz, eps = I.srhd_primitives(12, 60)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, 5 / 3)
+    prim, it, st, nfail, _ = oracle.con2prim(cons)
+    G = mp.mpf(5) / 3
+    for c in range(60):
+        D, Sx, Sy, Sz, tau = (mp.mpf(float(x)) for x in cons[:, c])
+        E = tau + D
+        s2 = Sx * Sx + Sy * Sy + Sz * Sz
+
+        def f(pp):
+            return (G - 1) * (E - s2 / (E + pp) - D * mp.sqrt(1 - s2 / (E + pp) ** 2)) - pp
+
+        root = mp.findroot(f, mp.mpf(float(p[c])))
+        W2 = 1 / (1 - (vx[c] ** 2 + vy[c] ** 2 + vz[c] ** 2))
+        bound = max(1e-13, 4e-16 * W2 / eps[c] * 4)
+        assert abs(float((mp.mpf(float(prim[4, c])) - root) / root)) < bound
+
+
+def test_con2prim_derivative_and_bracket():
+    rho, vx, vy, vz, eps = I.srhd_primitives(13, 300)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, 5 / 3)
+    G = 5 / 3
+    for c in range(300):
+        D, Sx, Sy, Sz, tau = cons[:, c]
+        E = tau + D
+        s = math.sqrt(Sx * Sx + Sy * Sy + Sz * Sz)
+        lo, hi = max(s - E, 0.0), (G - 1) * tau
+        assert lo < p[c] <= hi * (1 + 1e-14)
+        fl, _ = oracle.c2p_residual(cons[:, c], G, lo)
+        fh, _ = oracle.c2p_residual(cons[:, c], G, hi)
+        assert fl >= 0 >= fh
+        x = 0.5 * (p[c] + hi) if hi > p[c] else p[c]
+        hstep = 1e-6 * x
+        f1, d = oracle.c2p_residual(cons[:, c], G, x)
+        fp, _ = oracle.c2p_residual(cons[:, c], G, x + hstep)
+        fm, _ = oracle.c2p_residual(cons[:, c], G, x - hstep)
+        assert abs((fp - fm) / (2 * hstep) - d) <= 1e-5 * abs(d) + 1e-8
+        assert -1.0 <= d < -1.0 / 3.0 + 1e-12 or d < 0
+
+
+def test_con2prim_special_cases():
+    # v = 0: p_hi is the root, zero iterations
+    cons, p = I.srhd_prim_to_cons(np.array([2.0]), np.zeros(1), np.zeros(1), np.zeros(1), np.array([0.7]), 5 / 3)
+    prim, it, st, nfail, _ = oracle.con2prim(cons)
+    assert it[0] == 0 and st[0] == 0
+    np.testing.assert_allclose(prim[4], p, rtol=1e-15)
+    # bad inputs: tau <= 0, D <= 0, NaN
+    bad = np.array([[1.0, 0.1, 0, 0, -0.1], [-1.0, 0, 0, 0, 1.0], [np.nan, 0, 0, 0, 1.0]]).T
+    _, it, st, nfail, _ = oracle.con2prim(bad)
+    assert nfail == 3 and np.all(st == 2)
+    # max_iter 0 from the plain guess of a moving cell: not converged
+    cons, p = I.srhd_prim_to_cons(np.array([1.0]), np.array([0.6]), np.zeros(1), np.zeros(1), np.array([0.01]), 5 / 3)
+    _, it, st, nfail, _ = oracle.con2prim(cons, maxit=0)
+    assert st[0] == 1 and nfail == 1
+    # a guess at the root converges in <= 1 update; a NaN guess = plain guess
+    prim, it, st, _, _ = oracle.con2prim(cons, p_guess=p)
+    assert it[0] <= 1 and st[0] == 0
+    _, it2, _, _, _ = oracle.con2prim(cons, p_guess=np.array([np.nan]))
+    _, it3, _, _, _ = oracle.con2prim(cons)
+    assert it2[0] == it3[0]
+
+
+def test_fp32_storage_rounding():
+    b = I.config0(n_patch=2, p=8)
+    b.state = b.state.astype(np.float32).astype(np.float64)
+    q, _, _ = oracle.fv_step(b, n_steps=2, round_fp32=True)
+    np.testing.assert_array_equal(q, q.astype(np.float32).astype(np.float64))
+    q64, _, _ = oracle.fv_step(b, n_steps=2)
+    assert np.max(np.abs(q - q64)) < 1e-6
+
+
+# ------------------------------------------------- direction bookkeeping ----
+
+
+def test_euler3d_axis_permutation_invariance():
+    """Permuting the axes (and the momentum components with them) of a random
+    3D Euler state permutes the result: a wrong direction index in the flux or
+    eigenvalue breaks it."""
+    grid = (2, 2, 2)
+    p = 4
+    b = I.make_uniform_batch(grid, p, 1, "euler", [1.4], 5, 1.0 / 8)
+    n = 8
+    rho = I.uniform(31, n ** 3, 0.8, 1.2).reshape(n, n, n)
+    vel = [I.uniform(32 + i, n ** 3, -0.3, 0.3).reshape(n, n, n) for i in range(3)]
+    pr = I.uniform(35, n ** 3, 0.8, 1.2).reshape(n, n, n)
+    g = np.stack(I.euler_prim_to_state(rho, vel, pr, 1.4))  # [5, Z, Y, X]
+    b.state = b.from_global(g, grid)
+    q0, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    # swap x <-> z: array axes (Z, Y, X) -> (X, Y, Z), momentum x <-> z
+    gp = g[[0, 3, 2, 1, 4]].transpose(0, 3, 2, 1)
+    bp = b.copy()
+    bp.state = b.from_global(np.ascontiguousarray(gp), grid)
+    q1, _, _ = oracle.fv_step(bp, cfl=0.4, n_steps=2)
+    r0 = b.to_global(q0, grid)
+    r1 = b.to_global(q1, grid)[[0, 3, 2, 1, 4]].transpose(0, 3, 2, 1)
+    np.testing.assert_allclose(r1, r0, rtol=0, atol=1e-14)
+
+
+def test_srhd_eigenvalue_closed_forms():
+    """Uniform SRHD state moving along x: the x speeds are the relativistic
+    sums (v + c_s)/(1 + v c_s); transverse ones are
+    c_s sqrt((1 - v^2)/(1 - v^2 c_s^2))."""
+    Gam = 5.0 / 3.0
+    rho, v, eps = 0.8, 0.6, 0.4
+    b = I.config3(grid=(1, 1, 1), p=2)
+    cons, p = I.srhd_prim_to_cons(np.array([rho]), np.array([v]), np.zeros(1), np.zeros(1),
+                                  np.array([eps]), Gam)
+    b.state = np.repeat(cons[:, 0], 8)
+    dt, lam = oracle.cfl_dt(b, cfl=1.0)
+    pr = p[0]
+    h = 1 + eps + pr / rho
+    cs = math.sqrt(Gam * pr / (rho * h))
+    np.testing.assert_allclose(lam[0], (v + cs) / (1 + v * cs), rtol=1e-13)
+    tr = cs * math.sqrt((1 - v * v) / (1 - v * v * cs * cs))
+    np.testing.assert_allclose(lam[1:], [tr, tr], rtol=1e-13)
+
+
+def test_srhd_contact_keeps_v_and_p():
+    """A relativistic contact (uniform v and p, varying density) is an exact
+    solution; every conserved quantity and flux is affine in rho at fixed v, p,
+    so the Rusanov update keeps v and p uniform (up to the con2prim tolerance).
+    Pins the structure of the SRHD flux."""
+    Gam = 5.0 / 3.0
+    grid = (2, 2, 1)
+    pp = 4
+    b = I.config3(grid=grid, p=pp)
+    n = (8, 8, 4)
+    rho = I.uniform(41, 8 * 8 * 4, 0.5, 2.0).reshape(4, 8, 8)
+    v = (0.3, -0.2, 0.1)
+    pres = 0.7
+    eps = pres / ((Gam - 1) * rho)
+    cons, _ = I.srhd_prim_to_cons(rho, *(np.full_like(rho, x) for x in v), eps, Gam)
+    b.state = b.from_global(cons, grid)
+    q, _, st = oracle.fv_step(b, cfl=0.4, n_steps=3)
+    assert st.c2p_fail == 0
+    out = b.to_global(q, grid).reshape(5, -1)
+    prim, _, _, _, _ = oracle.con2prim(out)
+    np.testing.assert_allclose(prim[4], pres, rtol=1e-11)
+    for i in range(3):
+        np.testing.assert_allclose(prim[1 + i], v[i], rtol=0, atol=1e-12)
+
+
+@pytest.mark.parametrize("axis", [1, 2])
+def test_fd_plane_wave_other_axes(axis):
+    """The closed-form plane wave of the FD step along y and along z."""
+    N = 4
+    grid = [1, 1, 1]
+    grid[axis] = 2
+    b, Bs, rhos = _linsym_small(N=N, seed=6, npatch=tuple(grid))
+    b.dx[:] = 1.0 / 16
+    lamv, vecs = np.linalg.eigh(Bs[axis])
+    lam, r = lamv[1], vecs[:, 1]
+    n = 16
+    theta = 2 * np.pi * 3 / n
+    xi = np.arange(n)
+    shape = [N, 8, 8, 8]
+    shape[3 - axis] = n
+    prof = np.cos(theta * xi)
+    bshape = [1, 1, 1]
+    bshape[2 - axis] = n
+    g = r[:, None, None, None] * prof.reshape(bshape)[None] * np.ones(shape)
+    b.state = b.from_global(g, tuple(grid))
+    q, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=3)
+    dx = 1.0 / 16
+    z = dts[0] * (-1j * lam * (8 * np.sin(theta) - np.sin(2 * theta)) / (6 * dx) - 0.1 * np.sin(theta / 2) ** 6 / dx)
+    R = 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+    ex = np.real(R ** 3 * np.exp(1j * theta * xi))
+    exg = r[:, None, None, None] * ex.reshape(bshape)[None] * np.ones(shape)
+    np.testing.assert_allclose(b.to_global(q, tuple(grid)), exg, rtol=0, atol=2e-14)
+
+
+def test_fd_patch_permutation_invariance():
+    """Independent periodic patches: shuffling the batch order permutes the
+    per-patch results and changes nothing else (the step size is global)."""
+    b = I.config2(n_patches=8, N=5, sizes=np.array([4, 8, 4, 4, 8, 4, 8, 4], np.int32))
+    q, _ = oracle.fd_step(b, n_steps=1)
+    perm = np.array([5, 2, 7, 0, 1, 6, 3, 4])
+    bp = b.copy()
+    bp.p = b.p[perm]
+    bp.dx = b.dx[perm]
+    bp.nbr = I.self_periodic(8, 3)
+    bp.state = np.concatenate([b.patch_view(b.state, k).reshape(-1) for k in perm])
+    qp, _ = oracle.fd_step(bp, n_steps=1)
+    for j, k in enumerate(perm):
+        np.testing.assert_array_equal(bp.patch_view(qp, j), b.patch_view(q, k))
