@@ -1,0 +1,267 @@
+/*
+ * patchhip.h -- C ABI of the MI355X (gfx950) patch-batch library.
+ *
+ * The library advances K Cartesian patches ("cells" of an adaptive mesh, each
+ * carrying a p^d sub-grid read with a halo of width h) of a first-order
+ * hyperbolic system
+ *
+ *     dQ/dt + div F(Q) + B(Q) . grad Q = S(Q)            (paper Sec. I, Eq. (1))
+ *
+ * concurrently by one explicit time step: the batched cell kernel
+ * K~_{dt,K} of paper Sec. II (Eq. (2) and the batching paragraph after it).
+ * Two schemes are provided: a first-order Rusanov finite-volume step (the
+ * composition example of Sec. II-A, Eq. (3)) and a fourth-order central
+ * finite-difference step with Kreiss-Oliger dissipation and classical RK4
+ * (the FD4 scheme of Sec. IV).  Special-relativistic hydrodynamics adds a
+ * per-cell conservative-to-primitive Newton solve (a term that solves a
+ * nonlinear problem internally, Sec. II-A last paragraph), optionally seeded
+ * by a small bfloat16 MLP trained with the library's own kernels.
+ *
+ * Conventions (all entry points)
+ *   - Every function returns pb_status.  No C++ exception and no abort ever
+ *     crosses this boundary.  Argument checks run on the host before any HIP
+ *     call, so PB_EINVAL is reported without touching the GPU.
+ *   - pb_last_error() returns a thread-local text for the last failure.
+ *   - Device buffers (state, workspace, con2prim arrays, MLP data) are owned
+ *     by the caller and must stay allocated while a batch uses them.  The
+ *     library owns the pb_batch / pb_mlp objects and their small device
+ *     tables, released by the matching destroy call.
+ *   - Work is enqueued asynchronously on the caller's stream (hipStream_t
+ *     passed as void*; NULL = the null stream).  Host synchronisation happens
+ *     only where a host output is requested (dt_last_host, stats, weights).
+ *
+ * State layout in HBM ("patch-blocked structure of arrays")
+ *   patch k with p_k cells per direction owns cells [off_k, off_k + p_k^d),
+ *   off_k = sum_{j<k} p_j^d; unknown v of local cell c sits at element
+ *       off_k * N + v * p_k^d + c,        c = (z * p_k + y) * p_k + x,
+ *   x fastest.  Elements are double (PB_STORE_FP64) or float (PB_STORE_FP32:
+ *   arithmetic stays double, every stored value is rounded to nearest even).
+ */
+#ifndef PATCHHIP_H
+#define PATCHHIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PB_OK = 0,
+    PB_EINVAL = -1,        /* bad argument; nothing was enqueued */
+    PB_ENOMEM = -2,        /* a library-owned allocation failed */
+    PB_EHIP = -3,          /* a HIP runtime call failed (text in pb_last_error) */
+    PB_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+} pb_status;
+
+typedef enum {
+    PB_PDE_ADVECTION_F = 0, /* N = 1, F_d = a_d q, S = -kappa q.
+                               params: a_x, a_y, a_z, kappa */
+    PB_PDE_ADVECTION_B = 1, /* N = 1, B_d = a_d (non-conservative form), S = -kappa q.
+                               params: a_x, a_y, a_z, kappa */
+    PB_PDE_EULER = 2,       /* compressible Euler, ideal gas, N = dim + 2,
+                               Q = (rho, m, E).  params: gamma */
+    PB_PDE_LINSYM = 3,      /* linear symmetric system, F = S = 0, constant B_d,
+                               N = 58.  params: rho_x, rho_y, rho_z (spectral
+                               radii), B_x, B_y, B_z (each N*N, row-major) */
+    PB_PDE_SRHD = 4,        /* special-relativistic hydrodynamics, dim = 3,
+                               N = 5, Q = (D, S_x, S_y, S_z, tau).
+                               params: Gamma, con2prim tol, con2prim max_iter */
+} pb_pde;
+
+typedef enum { PB_STORE_FP64 = 0, PB_STORE_FP32 = 1 } pb_storage;
+
+typedef struct {
+    int32_t dim;              /* 2 or 3 */
+    int32_t n_patches;        /* K >= 1 */
+    const int32_t *p;         /* host [K]: cells per direction of each patch */
+    const double *dx;         /* host [K]: cell width of each patch (> 0) */
+    const int32_t *neighbor;  /* host [K][2*dim]: face neighbours in the order
+                                 -x,+x,-y,+y(,-z,+z); a patch may name itself
+                                 (periodic on itself).  p of a neighbour must
+                                 equal p of the patch. */
+    int32_t halo;             /* h: >= 1 for the FV step, >= 3 for FD4 + KO6 */
+    int32_t pde;              /* pb_pde */
+    const double *pde_params; /* host, copied at create */
+    int64_t n_pde_params;
+    int32_t n_unknowns;       /* N */
+    int32_t storage;          /* pb_storage */
+    void *state;              /* device: the state, in the layout above */
+    void *state_alt;          /* device: second buffer of the same size (the
+                                 steps ping-pong between the two) */
+    void *workspace;          /* device: pb_workspace_size() bytes, 256-aligned */
+    size_t workspace_bytes;
+    void *stream;             /* hipStream_t; not owned */
+} pb_batch_desc;
+
+typedef struct pb_batch pb_batch;
+
+typedef struct {
+    int64_t steps;               /* steps taken since create / reset */
+    int64_t nonfinite_units;     /* work units that produced a NaN/Inf value */
+    int64_t c2p_cells;           /* con2prim cell solves (SRHD) */
+    int64_t c2p_failures;        /* cells that did not converge / bad input */
+    int64_t c2p_iterations;      /* total Newton updates */
+    int64_t c2p_fallbacks;       /* learned guesses redone from the plain guess */
+    int32_t c2p_max_iterations;  /* largest per-cell count seen */
+    int32_t current;             /* 0: result in state, 1: in state_alt */
+    double last_dt;              /* step size of the most recent step */
+} pb_stats;
+
+/* Workspace bytes the batch described by `desc` needs (host-only). */
+pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes);
+
+/*
+ * Validate `desc`, copy its host tables and upload the patch table (the
+ * patch sizes, cell offsets, cell widths and face neighbours of paper
+ * Sec. II: K patches of p^d cells with a halo of h, p^ = p + 2h).  The
+ * descriptor's device pointers are stored, not copied.  Initialises the
+ * workspace on `stream`.
+ */
+pb_status patch_batch_create(const pb_batch_desc *desc, pb_batch **out);
+pb_status patch_batch_destroy(pb_batch *b);
+
+/* Declare `state` (which = 0) or `state_alt` (1) to hold the current state,
+ * e.g. after the caller uploaded new data; clears the counters. */
+pb_status pb_batch_reset(pb_batch *b, int32_t which);
+
+/* Statistics; synchronises the batch stream. */
+pb_status pb_batch_stats(pb_batch *b, pb_stats *out);
+
+/*
+ * n_steps Rusanov finite-volume steps (paper Sec. II-A, Eq. (3): source,
+ * face fluxes from the two adjacent cell values, update).  Per face along d:
+ *   s = max(lambda_d(Q_L), lambda_d(Q_R)),
+ *   F* = (F_d(Q_L) + F_d(Q_R))/2 - s (Q_R - Q_L)/2,
+ *   D  = B_d((Q_L + Q_R)/2) (Q_R - Q_L)/2 added to both cells,
+ * Q_i <- Q_i - dt/dx sum_d [(F*_{+} - F*_{-}) + (D_{+} + D_{-})] + dt S(Q_i).
+ * dt_fixed > 0 fixes dt; otherwise dt = cfl / sum_d (Lambda_d / dx_min),
+ * Lambda_d the maximal |speed| along d over all cells of the current state,
+ * computed on the device (no host round trip between steps).
+ * use_graph != 0 captures the n_steps launches once into a HIP graph and
+ * replays it on later calls with the same n_steps.
+ * dt_last_host (nullable): receives the last step's dt (synchronises).
+ * Supported: ADVECTION_F/B (N = 1), EULER, SRHD; 1 <= p <= 16; halo >= 1.
+ */
+pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_steps,
+                          int32_t use_graph, double *dt_last_host);
+
+/*
+ * n_steps of fourth-order central differences with sixth-order
+ * Kreiss-Oliger dissipation (Kreiss & Oliger 1973, named in paper Sec. I)
+ * and rk_stages = 4 (classical RK4) or 1 (forward Euler) stages with a halo
+ * refresh before each stage (paper Sec. II: RK schemes call the cell update
+ * several times with Butcher-tableau step sizes plus neighbour
+ * synchronisation):
+ *   R(Q) = sum_d ( -D4_d F_d - B_d D4_d Q + KO6_d Q ) + S(Q),
+ *   D4 u = [(u_-2 - u_+2) + 8 (u_+1 - u_-1)] / (12 dx),
+ *   KO6 u = sigma/(64 dx) [(u_-3 + u_+3) - 6 (u_-2 + u_+2) + 15 (u_-1 + u_+1) - 20 u_0].
+ * Patches must be periodic on themselves (neighbor = self), so one
+ * persistent launch per stage sweeps all patches from a cost-ordered work
+ * list.  dt as in fv_rusanov_step (Lambda_d = spectral radius of B_d).
+ * Needs 2 extra state-sized buffers in the workspace.
+ * Supported: LINSYM (N = 58, dim 3, halo >= 3, p in {4, 8, 16}), FP64.
+ */
+pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko,
+                     int32_t rk_stages, int32_t n_steps, int32_t use_graph,
+                     double *dt_last_host);
+
+/* ----------------------------------------------------------------- SRHD -- */
+
+typedef struct pb_mlp pb_mlp;
+
+/* con2prim guess modes */
+typedef enum { PB_GUESS_PLAIN = 0, PB_GUESS_LEARNED = 1, PB_GUESS_WARM = 2 } pb_guess;
+
+/*
+ * Conservative-to-primitive recovery of special-relativistic hydrodynamics
+ * (ideal gas, p = (Gamma-1) rho eps) by a bracketed FP64 Newton iteration on
+ * the pressure.  With E = tau + D, s = |S|:
+ *   f(p)  = (Gamma-1)[E - s^2/(E+p) - D sqrt(1 - s^2/(E+p)^2)] - p,
+ *   f'(p) = (Gamma-1) v^2 (1 - D W/(E+p)) - 1,    root in (max(s-E,0), (Gamma-1) tau].
+ * Converged when |f| <= tol (Gamma-1)(E+p); one polishing Newton step follows.
+ * cons:   device, SoA [5][n] doubles (D, S_x, S_y, S_z, tau).
+ * prim:   device, SoA [5][n] doubles (rho, v_x, v_y, v_z, p), written.
+ * guess:  PB_GUESS_PLAIN: p0 = (Gamma-1) tau.  PB_GUESS_LEARNED: p0 from
+ *         `mlp` (must be non-NULL).  PB_GUESS_WARM: p0 = p_prev[i].
+ *         A learned/warm start that fails is redone from the plain guess.
+ * p_prev: device [n] doubles (WARM only, else NULL).
+ * iters:  device [n] int32 Newton updates per cell (nullable).
+ * status: device [n] int32: 0 ok, 1 not converged, 2 bad input (nullable).
+ * counters: device, 8 int64 accumulated (nullable):
+ *         [0] failures, [1] total iterations, [2] fallbacks, [3] max iterations.
+ */
+pb_status con2prim(const void *cons, void *prim, int64_t n, double gamma, double tol,
+                   int32_t max_iter, int32_t guess, const pb_mlp *mlp, const void *p_prev,
+                   void *iters, void *status, void *counters, void *stream);
+
+/* How fv_rusanov_step seeds the SRHD con2prim (default PB_GUESS_PLAIN). */
+pb_status pb_batch_set_c2p_guess(pb_batch *b, int32_t guess, const pb_mlp *mlp);
+
+/* ------------------------------------------------------------------ MLP -- */
+/*
+ * The learned con2prim guess: an MLP 5 -> 64 -> 64 -> 1 with ReLU.  Weights
+ * and activations are bfloat16 (round to nearest even), products accumulate
+ * in FP32 on the matrix cores, biases are FP32, the output stays FP32.
+ * Features of a conserved state (all scale-free, since p/E depends only on
+ * D/E and |S|/E):
+ *   x = [log(D/E), |S|/E, log(1 - |S|/E), log(tau/E), (|S|/E)^2],
+ * standardised with the stored mean/std; the target is y = log(p/E),
+ * standardised with mu_y, sigma_y: p0 = E exp(mu_y + sigma_y yhat).
+ * Training (FP32 master weights, Adam) runs on the device with the library's
+ * own forward, backward and update kernels.
+ */
+#define PB_MLP_IN 5
+#define PB_MLP_HID 64
+#define PB_MLP_NPARAM (PB_MLP_HID * PB_MLP_IN + PB_MLP_HID + PB_MLP_HID * PB_MLP_HID + PB_MLP_HID + PB_MLP_HID + 1)
+
+/* Parameter vector order (FP32, PB_MLP_NPARAM values):
+ * W1[64][5], b1[64], W2[64][64], b2[64], W3[64], b3 -- then normalisation
+ * (not trained): x_mean[5], x_std[5], y_mean, y_std  (12 values) */
+#define PB_MLP_NNORM 12
+
+pb_status pb_mlp_create(pb_mlp **out);
+pb_status pb_mlp_destroy(pb_mlp *m);
+/* host <-> library copies of the FP32 master parameters and normalisation */
+pb_status pb_mlp_set_params(pb_mlp *m, const float *params, const float *norm);
+pb_status pb_mlp_get_params(pb_mlp *m, float *params, float *norm);
+/* yhat for n feature rows: x device [n][5] FP32 (raw, unstandardised features),
+ * y device [n] FP32 */
+pb_status pb_mlp_forward(const pb_mlp *m, const void *x, void *y, int64_t n, void *stream);
+/* gradient of the mean squared error (1/n) sum (yhat - t)^2 over n rows
+ * w.r.t. the parameters: t device [n] FP32 (standardised target),
+ * grad device [PB_MLP_NPARAM] FP32 (overwritten), loss device [1] FP32 */
+pb_status pb_mlp_grad(const pb_mlp *m, const void *x, const void *t, int64_t n, void *grad,
+                      void *loss, void *stream);
+/* one Adam step on a batch: grad + update of the FP32 master weights and their
+ * bfloat16 copies.  step is the 1-based Adam step counter. */
+pb_status pb_mlp_train_step(pb_mlp *m, const void *x, const void *t, int64_t n, float lr,
+                            float beta1, float beta2, float eps, int32_t step, void *loss,
+                            void *stream);
+
+/* ---------------------------------------------------------- measurement -- */
+
+/* on != 0: record a HIP event pair on the batch stream around every step
+ * kernel launch (FV step kernel; FD stage kernel) of later eager calls. */
+pb_status pb_batch_profile(pb_batch *b, int32_t on);
+/* Sum of the recorded launch durations (ms) and the number of launches since
+ * the last read; synchronises the batch stream and clears the record. */
+pb_status pb_batch_profile_read(pb_batch *b, double *total_ms, int64_t *launches);
+
+/* --------------------------------------------------------------- tuning -- */
+
+typedef struct {
+    int32_t fv_slab;          /* FV: z-planes per work-group (0 = default) */
+    int32_t fv_xcd_remap;     /* FV: 1 = group consecutive patches per XCD */
+    int32_t fd_block;         /* FD: reserved */
+} pb_tuning;
+
+pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
+
+const char *pb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PATCHHIP_H */

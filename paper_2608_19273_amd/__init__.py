@@ -1,0 +1,252 @@
+"""MI355X (gfx950) patch-batch library: Python binding of the C ABI declared
+in include/patchhip.h.
+
+This module only marshals arguments.  Every step of the update runs in the
+HIP kernels of libpatchhip.so; PyTorch provides device memory and the stream.
+If the shared library is missing, every entry point raises PbError (there is
+no fallback path).
+
+Module-level functions carry the C names (patch_batch_create,
+fv_rusanov_step, fd_ko_step, con2prim, pb_mlp_*); `PatchBatch` and `Mlp`
+wrap them with torch-owned buffers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpatchhip.so")
+
+PB_OK, PB_EINVAL, PB_ENOMEM, PB_EHIP, PB_EUNSUPPORTED = 0, -1, -2, -3, -4
+STATUS = {0: "PB_OK", -1: "PB_EINVAL", -2: "PB_ENOMEM", -3: "PB_EHIP", -4: "PB_EUNSUPPORTED"}
+PDE = {"adv_f": 0, "adv_b": 1, "euler": 2, "linsym": 3, "srhd": 4}
+STORAGE = {"fp64": 0, "fp32": 1}
+GUESS = {"plain": 0, "learned": 1, "warm": 2}
+MLP_IN, MLP_HID = 5, 64
+MLP_NPARAM = MLP_HID * MLP_IN + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_HID + 1
+MLP_NNORM = 12
+
+
+class PbError(RuntimeError):
+    def __init__(self, what, status, text=""):
+        super().__init__(f"{what}: {STATUS.get(status, status)}: {text}")
+        self.status = status
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_patches", C.c_int32), ("p", C.POINTER(C.c_int32)),
+                ("dx", C.POINTER(C.c_double)), ("neighbor", C.POINTER(C.c_int32)), ("halo", C.c_int32),
+                ("pde", C.c_int32), ("pde_params", C.POINTER(C.c_double)), ("n_pde_params", C.c_int64),
+                ("n_unknowns", C.c_int32), ("storage", C.c_int32), ("state", C.c_void_p),
+                ("state_alt", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("steps", C.c_int64), ("nonfinite_units", C.c_int64), ("c2p_cells", C.c_int64),
+                ("c2p_failures", C.c_int64), ("c2p_iterations", C.c_int64), ("c2p_fallbacks", C.c_int64),
+                ("c2p_max_iterations", C.c_int32), ("current", C.c_int32), ("last_dt", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Tuning(C.Structure):
+    _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_block", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpatchhip.so (raises PbError if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise PbError("load", PB_EUNSUPPORTED,
+                          f"{LIB_PATH} is not built (python -m paper_2608_19273_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp, dp = C.c_void_p, C.POINTER(C.c_double)
+        L.pb_last_error.restype = C.c_char_p
+        L.pb_workspace_size.argtypes = [C.POINTER(BatchDesc), C.POINTER(C.c_size_t)]
+        L.patch_batch_create.argtypes = [C.POINTER(BatchDesc), C.POINTER(vp)]
+        L.patch_batch_destroy.argtypes = [vp]
+        L.pb_batch_reset.argtypes = [vp, C.c_int32]
+        L.pb_batch_stats.argtypes = [vp, C.POINTER(Stats)]
+        L.pb_batch_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.pb_batch_set_c2p_guess.argtypes = [vp, C.c_int32, vp]
+        L.pb_batch_profile.argtypes = [vp, C.c_int32]
+        L.pb_batch_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.fv_rusanov_step.argtypes = [vp, C.c_double, C.c_double, C.c_int32, C.c_int32, dp]
+        L.fd_ko_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32, dp]
+        L.con2prim.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32, vp, vp,
+                               vp, vp, vp, vp]
+        L.pb_mlp_create.argtypes = [C.POINTER(vp)]
+        L.pb_mlp_destroy.argtypes = [vp]
+        fp = C.POINTER(C.c_float)
+        L.pb_mlp_set_params.argtypes = [vp, fp, fp]
+        L.pb_mlp_get_params.argtypes = [vp, fp, fp]
+        L.pb_mlp_forward.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.pb_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
+        L.pb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
+                                        C.c_int32, vp, vp]
+        for name in ("pb_workspace_size", "patch_batch_create", "patch_batch_destroy", "pb_batch_reset",
+                     "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_set_c2p_guess", "pb_batch_profile",
+                     "pb_batch_profile_read", "fv_rusanov_step",
+                     "fd_ko_step", "con2prim", "pb_mlp_create", "pb_mlp_destroy", "pb_mlp_set_params",
+                     "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_grad", "pb_mlp_train_step"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().pb_last_error().decode()
+
+
+def _check(rc, what):
+    if rc != PB_OK:
+        raise PbError(what, rc, last_error())
+
+
+# ---------------------------------------------------------------- C names --
+
+
+def pb_workspace_size(desc: BatchDesc) -> int:
+    n = C.c_size_t(0)
+    _check(lib().pb_workspace_size(C.byref(desc), C.byref(n)), "pb_workspace_size")
+    return int(n.value)
+
+
+def patch_batch_create(desc: BatchDesc):
+    h = C.c_void_p()
+    _check(lib().patch_batch_create(C.byref(desc), C.byref(h)), "patch_batch_create")
+    return h
+
+
+def patch_batch_destroy(h):
+    _check(lib().patch_batch_destroy(h), "patch_batch_destroy")
+
+
+def fv_rusanov_step(h, cfl=0.4, dt_fixed=0.0, n_steps=1, use_graph=False, want_dt=False):
+    dt = C.c_double(0.0)
+    _check(lib().fv_rusanov_step(h, cfl, dt_fixed, n_steps, int(use_graph), C.byref(dt) if want_dt else None),
+           "fv_rusanov_step")
+    return dt.value if want_dt else None
+
+
+def fd_ko_step(h, cfl=0.5, dt_fixed=0.0, sigma_ko=0.1, rk_stages=4, n_steps=1, use_graph=False, want_dt=False):
+    dt = C.c_double(0.0)
+    _check(lib().fd_ko_step(h, cfl, dt_fixed, sigma_ko, rk_stages, n_steps, int(use_graph),
+                            C.byref(dt) if want_dt else None), "fd_ko_step")
+    return dt.value if want_dt else None
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def con2prim(cons, prim, gamma=5.0 / 3.0, tol=1e-12, max_iter=50, guess="plain", mlp=None, p_prev=None,
+             iters=None, status=None, counters=None):
+    """cons, prim: torch float64 device tensors [5, n]; optional torch outputs."""
+    n = cons.shape[-1]
+    _check(lib().con2prim(_ptr(cons), _ptr(prim), n, gamma, tol, max_iter, GUESS[guess],
+                          None if mlp is None else mlp.handle, _ptr(p_prev), _ptr(iters), _ptr(status),
+                          _ptr(counters), _stream()), "con2prim")
+
+
+# -------------------------------------------------------------- wrappers --
+
+
+class PatchBatch:
+    """A patch batch whose state lives in two torch device buffers."""
+
+    def __init__(self, batch, storage="fp64", device="cuda", state=None):
+        import torch
+        self.batch = batch
+        self.storage = storage
+        self.dtype = torch.float64 if storage == "fp64" else torch.float32
+        self.device = torch.device(device)
+        n = batch.total_cells * batch.n_unknowns
+        self.bufs = [torch.empty(n, dtype=self.dtype, device=self.device),
+                     torch.empty(n, dtype=self.dtype, device=self.device)]
+        src = batch.state if state is None else state
+        self.bufs[0].copy_(torch.from_numpy(np.ascontiguousarray(src)).to(self.dtype))
+        self._p = np.ascontiguousarray(batch.p, dtype=np.int32)
+        self._dx = np.ascontiguousarray(batch.dx, dtype=np.float64)
+        self._nbr = np.ascontiguousarray(batch.nbr, dtype=np.int32).reshape(-1)
+        self._prm = np.ascontiguousarray(batch.params, dtype=np.float64)
+        self.desc = BatchDesc(batch.dim, batch.K, self._p.ctypes.data_as(C.POINTER(C.c_int32)),
+                              self._dx.ctypes.data_as(C.POINTER(C.c_double)),
+                              self._nbr.ctypes.data_as(C.POINTER(C.c_int32)), batch.halo, PDE[batch.pde],
+                              self._prm.ctypes.data_as(C.POINTER(C.c_double)), self._prm.size,
+                              batch.n_unknowns, STORAGE[storage], self.bufs[0].data_ptr(),
+                              self.bufs[1].data_ptr(), None, 0, _stream())
+        ws = pb_workspace_size(self.desc)
+        self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) & ~255
+        self.desc.workspace = aligned
+        self.desc.workspace_bytes = ws
+        self.handle = patch_batch_create(self.desc)
+
+    def close(self):
+        if self.handle:
+            patch_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def fv_rusanov_step(self, cfl=0.4, dt_fixed=0.0, n_steps=1, use_graph=False, want_dt=False):
+        return fv_rusanov_step(self.handle, cfl, dt_fixed, n_steps, use_graph, want_dt)
+
+    def fd_ko_step(self, cfl=0.5, dt_fixed=0.0, sigma_ko=0.1, rk_stages=4, n_steps=1, use_graph=False,
+                   want_dt=False):
+        return fd_ko_step(self.handle, cfl, dt_fixed, sigma_ko, rk_stages, n_steps, use_graph, want_dt)
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().pb_batch_stats(self.handle, C.byref(s)), "pb_batch_stats")
+        return s.as_dict()
+
+    def current(self):
+        return self.bufs[self.stats()["current"]]
+
+    def download(self) -> np.ndarray:
+        return self.current().double().cpu().numpy()
+
+    def reset(self, state=None):
+        import torch
+        if state is not None:
+            self.bufs[0].copy_(torch.from_numpy(np.ascontiguousarray(state)).to(self.dtype))
+        _check(lib().pb_batch_reset(self.handle, 0), "pb_batch_reset")
+
+    def set_tuning(self, fv_slab=0, fv_xcd_remap=1):
+        t = Tuning(fv_slab, fv_xcd_remap, 0)
+        _check(lib().pb_batch_set_tuning(self.handle, C.byref(t)), "pb_batch_set_tuning")
+
+    def profile(self, on=True):
+        _check(lib().pb_batch_profile(self.handle, int(on)), "pb_batch_profile")
+
+    def profile_read(self):
+        """(total ms, launches) of the step kernels recorded since the last read"""
+        ms = C.c_double(0.0)
+        n = C.c_int64(0)
+        _check(lib().pb_batch_profile_read(self.handle, C.byref(ms), C.byref(n)), "pb_batch_profile_read")
+        return ms.value, n.value
+
+    def set_c2p_guess(self, guess="plain", mlp=None):
+        _check(lib().pb_batch_set_c2p_guess(self.handle, GUESS[guess], None if mlp is None else mlp.handle),
+               "pb_batch_set_c2p_guess")

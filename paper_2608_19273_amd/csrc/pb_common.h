@@ -1,0 +1,147 @@
+// pb_common.h -- internal declarations shared by the library's translation
+// units (host runtime and HIP kernels).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/patchhip.h"
+
+namespace pb {
+
+constexpr int kWave = 64;
+constexpr int kFvThreads = 256;   // one 16x16 plane per work-group
+constexpr int kFvPmax = 16;
+
+// One patch as the kernels see it (48 bytes, 16-aligned).
+struct alignas(16) PatchDev {
+    long long off;   // first cell of the patch (cells, not elements)
+    int p;           // cells per direction
+    int nbr[6];      // face neighbours -x,+x,-y,+y,-z,+z
+    int pad;
+    double inv_dx;   // 1 / dx
+};
+static_assert(sizeof(PatchDev) == 48, "PatchDev layout");
+
+// Control block at the start of the workspace (256 bytes).
+struct Ctrl {
+    double dt[2];                       // step sizes, ping-ponged by step parity
+    unsigned long long lam[3];          // running max of lambda_d (IEEE bits, >= 0)
+    unsigned int done;                  // work units finished in the current launch
+    unsigned int queue;                 // FD work-list head
+    unsigned long long nonfinite;       // units that produced NaN/Inf
+    unsigned long long c2p_cells;
+    unsigned long long c2p_fail;
+    unsigned long long c2p_iters;
+    unsigned long long c2p_fallback;
+    unsigned int c2p_maxit;
+    unsigned int pad0;
+    double last_dt;
+    unsigned long long pad[19];
+};
+static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
+
+// thread-local error text
+void set_error(const std::string &msg);
+pb_status hip_fail(hipError_t e, const char *what);
+
+#define PB_HIP(call)                                          \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return ::pb::hip_fail(e_, #call); \
+    } while (0)
+
+// ------------------------------------------------------------ device utils
+
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
+__device__ __forceinline__ unsigned long long dbits(double v)
+{
+    return (unsigned long long)__double_as_longlong(v);
+}
+
+// Work-group order -> unit order such that the units one XCD runs (the
+// hardware deals work-groups round-robin over the 8 XCDs) are consecutive:
+// neighbouring patches then share that XCD's L2 for their halo reads.
+__device__ __forceinline__ int xcd_remap(int bid, int n)
+{
+    const int q = n >> 3, r = n & 7;
+    const int x = bid & 7, j = bid >> 3;
+    return x * q + (x < r ? x : r) + j;
+}
+
+}  // namespace pb
+
+// ------------------------------------------------------------------------
+// Host runtime object (defined here so that every translation unit of the
+// library can read it).
+struct pb_batch {
+    int dim = 0, K = 0, N = 0, h = 0, pde = 0, storage = 0;
+    std::vector<int> p;
+    std::vector<double> dx;
+    std::vector<int> nbr;
+    std::vector<double> params;
+    void *state[2] = {nullptr, nullptr};
+    int cur = 0;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    long long total_cells = 0;
+    double dxmin = 0.0;
+    int pmax = 0;
+    bool uniform_p = true;
+    pb::PatchDev *d_patches = nullptr;
+    int *d_order = nullptr;          // FD: cost-ordered work list
+    long long steps = 0;
+    double last_dt_host = 0.0;
+    // tuning
+    int fv_slab = 0;
+    int fv_xcd_remap = 1;
+    // SRHD guess mode
+    int guess = PB_GUESS_PLAIN;
+    const pb_mlp *mlp = nullptr;
+    // graph cache
+    struct GraphEntry {
+        int kind, n_steps, parity_cur;
+        double key0, key1, key2;
+        int key3;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t capture_stream = nullptr;
+    int last_slot = 0;
+    // per-launch event timing of the step kernels (eager mode only)
+    bool profiling = false;
+    int prof_n = 0;
+    std::vector<hipEvent_t> prof_ev[2];
+};
+
+namespace pb {
+// workspace sub-ranges (byte offsets), from the batch description
+struct WsLayout {
+    size_t ctrl = 0;       // Ctrl
+    size_t pres = 0;       // SRHD: pressure per cell (double)
+    size_t yA = 0, yB = 0; // FD: stage buffers
+    size_t total = 0;
+};
+WsLayout ws_layout(int pde, long long total_cells, int N, int storage);
+
+// launchers (implemented in the kernel translation units)
+pb_status launch_fv_lambda(pb_batch *b, const void *q, double cfl, hipStream_t s);
+pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, double dt_fixed,
+                         double cfl, hipStream_t s);
+pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt, double cfl,
+                          hipStream_t s);
+pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y,
+                          void *ynext, void *acc, int slot, double dt_fixed, double sigma,
+                          hipStream_t s);
+pb_status launch_fd_lambda(pb_batch *b, double cfl, hipStream_t s);
+pb_status launch_ctrl_init(pb_batch *b, hipStream_t s);
+}  // namespace pb

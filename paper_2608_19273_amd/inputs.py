@@ -226,17 +226,22 @@ def fourier_field(seed: int, coords, lengths, n_modes: int = 8, kmax: int = 4) -
     kidx = splitmix64(substream(seed, 1), n_modes) % np.uint64(nk ** 3 - 1)
     kidx = kidx.astype(np.int64)
     kidx = np.where(kidx >= (nk ** 3 - 1) // 2, kidx + 1, kidx)  # skip k = 0
-    out = 0.0
+    nz, ny, nx = len(coords[2]), len(coords[1]), len(coords[0])
+    out = np.zeros((nz, ny, nx))
+    tmp = np.empty((nz, ny, nx))
     asum = 0.0
     for m in range(n_modes):
         kk = [int(kidx[m] % nk) - kmax, int((kidx[m] // nk) % nk) - kmax, int(kidx[m] // nk ** 2) - kmax]
         A = r[3 * m]
         phi = 2 * np.pi * r[3 * m + 1]
-        ph = phi
-        ph = ph + (2 * np.pi * kk[2] / lengths[2]) * coords[2][:, None, None]
-        ph = ph + (2 * np.pi * kk[1] / lengths[1]) * coords[1][None, :, None]
-        ph = ph + (2 * np.pi * kk[0] / lengths[0]) * coords[0][None, None, :]
-        out = out + A * np.sin(ph)
+        # sin(u(z) + w(y, x)) = sin u cos w + cos u sin w, evaluated separably
+        u = phi + (2 * np.pi * kk[2] / lengths[2]) * coords[2]
+        w = ((2 * np.pi * kk[1] / lengths[1]) * coords[1])[:, None] + \
+            ((2 * np.pi * kk[0] / lengths[0]) * coords[0])[None, :]
+        np.multiply((A * np.sin(u))[:, None, None], np.cos(w)[None], out=tmp)
+        out += tmp
+        np.multiply((A * np.cos(u))[:, None, None], np.sin(w)[None], out=tmp)
+        out += tmp
         asum += A
     return out / asum
 
