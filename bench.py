@@ -156,6 +156,25 @@ def main():
         "nonfinite_units": st["nonfinite_units"],
     }
     B.close()
+    # attainable streaming bandwidth: the library's plain copy kernel, 512 MiB
+    # read + 512 MiB written per launch (also the known-traffic reference for
+    # the profiler's byte counters)
+    src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    pb.pb_stream_copy(src, dst)
+    torch.cuda.synchronize()
+    c0 = torch.cuda.Event(enable_timing=True)
+    c1 = torch.cuda.Event(enable_timing=True)
+    reps = 5
+    c0.record()
+    for _ in range(reps):
+        pb.pb_stream_copy(src, dst)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 8 * reps / (c0.elapsed_time(c1) / 1e3) / 1e9
+    result["roofline"]["attainable_copy_GBs"] = copy_gbs
+    result["roofline"]["frac_of_attainable"] = achieved / copy_gbs
+    del src, dst
     if not args.no_cpu:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

@@ -249,6 +249,11 @@ pb_status pb_batch_profile(pb_batch *b, int32_t on);
  * the last read; synchronises the batch stream and clears the record. */
 pb_status pb_batch_profile_read(pb_batch *b, double *total_ms, int64_t *launches);
 
+/* Plain streaming copy of `bytes` (multiple of 32, 32-byte aligned device
+ * pointers) on `stream`: the attainable-bandwidth reference for the kernels'
+ * roofline (reads `bytes`, writes `bytes`). */
+pb_status pb_stream_copy(const void *src, void *dst, size_t bytes, void *stream);
+
 /* --------------------------------------------------------------- tuning -- */
 
 typedef struct {

@@ -81,6 +81,7 @@ def lib():
         L.pb_batch_profile.argtypes = [vp, C.c_int32]
         L.pb_batch_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
         L.fv_rusanov_step.argtypes = [vp, C.c_double, C.c_double, C.c_int32, C.c_int32, dp]
+        L.pb_stream_copy.argtypes = [vp, vp, C.c_size_t, vp]
         L.fd_ko_step.argtypes = [vp, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32, C.c_int32, dp]
         L.con2prim.argtypes = [vp, vp, C.c_int64, C.c_double, C.c_double, C.c_int32, C.c_int32, vp, vp,
                                vp, vp, vp, vp]
@@ -95,7 +96,7 @@ def lib():
                                         C.c_int32, vp, vp]
         for name in ("pb_workspace_size", "patch_batch_create", "patch_batch_destroy", "pb_batch_reset",
                      "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_set_c2p_guess", "pb_batch_profile",
-                     "pb_batch_profile_read", "fv_rusanov_step",
+                     "pb_batch_profile_read", "pb_stream_copy", "fv_rusanov_step",
                      "fd_ko_step", "con2prim", "pb_mlp_create", "pb_mlp_destroy", "pb_mlp_set_params",
                      "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_grad", "pb_mlp_train_step"):
             getattr(L, name).restype = C.c_int
@@ -161,6 +162,13 @@ def con2prim(cons, prim, gamma=5.0 / 3.0, tol=1e-12, max_iter=50, guess="plain",
     _check(lib().con2prim(_ptr(cons), _ptr(prim), n, gamma, tol, max_iter, GUESS[guess],
                           None if mlp is None else mlp.handle, _ptr(p_prev), _ptr(iters), _ptr(status),
                           _ptr(counters), _stream()), "con2prim")
+
+
+def pb_stream_copy(src, dst):
+    """device copy src -> dst (torch tensors, same byte size) with the
+    library's streaming kernel"""
+    n = src.numel() * src.element_size()
+    _check(lib().pb_stream_copy(_ptr(src), _ptr(dst), n, _stream()), "pb_stream_copy")
 
 
 # -------------------------------------------------------------- wrappers --

@@ -24,13 +24,15 @@ pb_status hip_fail(hipError_t e, const char *what)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-WsLayout ws_layout(int pde, long long total_cells, int N, int storage)
+WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K)
 {
     WsLayout L;
     size_t o = 0;
     L.ctrl = o;
     o += sizeof(Ctrl);
     o = align256(o);
+    L.part = o;
+    o = align256(o + (size_t)3 * (size_t)max_units(K) * sizeof(double));
     if (pde == PB_PDE_SRHD) {
         L.pres = o;
         o = align256(o + (size_t)total_cells * sizeof(double));
@@ -121,7 +123,7 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
     if (need_buffers) {
         if (!d->state || !d->state_alt) { set_error("state and state_alt are required"); return PB_EINVAL; }
         if (d->state == d->state_alt) { set_error("state and state_alt must differ"); return PB_EINVAL; }
-        const WsLayout L = ws_layout(d->pde, cells, N, d->storage);
+        const WsLayout L = ws_layout(d->pde, cells, N, d->storage, d->n_patches);
         if (!d->workspace) { set_error("workspace is required"); return PB_EINVAL; }
         if (((uintptr_t)d->workspace & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PB_EINVAL; }
         if (d->workspace_bytes < L.total) {
@@ -162,7 +164,7 @@ static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sig
 {
     int cur = *cur_io;
     pb_status st;
-    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage);
+    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
     void *yA = b->ws + L.yA, *yB = b->ws + L.yB;
     if (!(dt_fixed > 0.0))
         if ((st = launch_fd_lambda(b, cfl, s)) != PB_OK) return st;
@@ -201,7 +203,7 @@ pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes)
     long long cells = 0;
     pb_status st = validate(desc, false, &cells, nullptr, nullptr);
     if (st != PB_OK) return st;
-    *bytes = ws_layout(desc->pde, cells, desc->n_unknowns, desc->storage).total;
+    *bytes = ws_layout(desc->pde, cells, desc->n_unknowns, desc->storage, desc->n_patches).total;
     return PB_OK;
 }
 

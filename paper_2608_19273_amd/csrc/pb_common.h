@@ -127,11 +127,14 @@ namespace pb {
 // workspace sub-ranges (byte offsets), from the batch description
 struct WsLayout {
     size_t ctrl = 0;       // Ctrl
+    size_t part = 0;       // per-unit partial maxima of the speeds [3][units]
     size_t pres = 0;       // SRHD: pressure per cell (double)
     size_t yA = 0, yB = 0; // FD: stage buffers
     size_t total = 0;
 };
-WsLayout ws_layout(int pde, long long total_cells, int N, int storage);
+WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K);
+// largest number of work units any launch uses (partials are sized for it)
+inline long long max_units(int K) { return (long long)K * kFvPmax; }
 
 // launchers (implemented in the kernel translation units)
 pb_status launch_fv_lambda(pb_batch *b, const void *q, double cfl, hipStream_t s);

@@ -50,12 +50,24 @@ __device__ __forceinline__ void cell_speeds(const Ph &ph, const double *q, const
     if (DIM == 3) lm[2] = fmax(lm[2], ph.template eig<2>(q, a));
 }
 
-// work-group max of lm[0..DIM) -> atomicMax into ctrl->lam; the last
-// work-group of the launch writes dt = cfl / sum_d(Lambda_d / dx_min) into
-// ctrl->dt[slot_out] and clears the accumulators for the next launch.
+// Largest speeds of a freshly written cell, for the next step's dt only: the
+// aux evaluation uses the reciprocal / rsqrt estimates refined by Newton
+// steps (a max over cells needs no correctly rounded quotient).
+template <class Ph, int DIM>
+__device__ __forceinline__ void cell_speeds_fast(const Ph &ph, const double *q, double *lm)
+{
+    constexpr int AA = Ph::A > 0 ? Ph::A : 1;
+    double a[AA], e[1] = {0.0};
+    ph.aux_fast(q, e, a);
+    cell_speeds<Ph, DIM>(ph, q, a, lm);
+}
+
+// Work-group max of lm[0..DIM) stored as this unit's partial (plain stores,
+// no atomics and no fence: the kernel boundary makes them visible to the
+// reduction kernel that follows).  Layout: part[d * n_units + unit].
 template <int DIM>
-__device__ __forceinline__ void finish_lambda(Ctrl *ctrl, const double *lm, int n_units, int slot_out,
-                                              double cfl, double dxmin)
+__device__ __forceinline__ void store_partial(double *__restrict__ part, const double *lm, int unit,
+                                              int n_units)
 {
     __shared__ double red[3][kFvThreads / kWave];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
@@ -65,43 +77,80 @@ __device__ __forceinline__ void finish_lambda(Ctrl *ctrl, const double *lm, int 
         if (lane == 0) red[d][w] = m;
     }
     __syncthreads();
-    if (t == 0) {
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) {
-            double m = red[d][0];
-            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[d][i]);
-            atomicMax(&ctrl->lam[d], dbits(m));
-        }
-        __threadfence();
-        const unsigned prev = atomicAdd(&ctrl->done, 1u);
-        if (prev == (unsigned)n_units - 1u) {
-            __threadfence();
-            double den = 0.0;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-                const double L = __longlong_as_double((long long)atomicAdd(&ctrl->lam[d], 0ull));
-                den += L / dxmin;
-            }
-            const double dt = cfl / den;
-            ctrl->dt[slot_out] = dt;
-            ctrl->last_dt = dt;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) atomicExch(&ctrl->lam[d], 0ull);
-            atomicExch(&ctrl->done, 0u);
-        }
+    if (t < DIM) {
+        double m = red[t][0];
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[t][i]);
+        part[(long long)t * n_units + unit] = m;
     }
 }
 
 }  // namespace
 
+#ifndef PB_FV_NTLOAD
+#define PB_FV_NTLOAD 0
+#endif
+
+// raw (storage-type) values of one cell: N unknowns plus the extra input
+template <class Ph, typename T>
+struct RawCell {
+    T q[Ph::N];
+    double e;
+};
+
+template <class Ph, typename T>
+__device__ __forceinline__ void issue_load(const T *__restrict__ q, const double *__restrict__ ex,
+                                           long long off, long long C, long long c, RawCell<Ph, T> &r)
+{
+    const T *base = q + off * Ph::N + c;
+#pragma unroll
+#if PB_FV_NTLOAD
+    for (int v = 0; v < Ph::N; ++v) r.q[v] = __builtin_nontemporal_load(base + (long long)v * C);
+#else
+    for (int v = 0; v < Ph::N; ++v) r.q[v] = base[(long long)v * C];
+#endif
+    if (Ph::E) r.e = ex[off + c];
+}
+
+template <class Ph, typename T>
+__device__ __forceinline__ void unpack(const RawCell<Ph, T> &r, double *q, double *e)
+{
+#pragma unroll
+    for (int v = 0; v < Ph::N; ++v) q[v] = (double)r.q[v];
+    e[0] = Ph::E ? r.e : 0.0;
+}
+
+#ifndef PB_FV_NTLOAD
+#define PB_FV_NTLOAD 0
+#endif
+#ifndef PB_FV_WPE
+#define PB_FV_WPE 0
+#endif
+#if PB_FV_WPE
+#define PB_FV_ATTR __attribute__((amdgpu_waves_per_eu(PB_FV_WPE)))
+#else
+#define PB_FV_ATTR
+#endif
+
+template <class Ph, int D>
+__device__ __forceinline__ void phys_flux_or_zero(const Ph &ph, const double *q, const double *a, double *F)
+{
+    if (Ph::kFlux) {
+        ph.template flux<D>(q, a, F);
+    } else {
+#pragma unroll
+        for (int v = 0; v < Ph::N; ++v) F[v] = 0.0;
+    }
+}
+
 template <class Ph, int DIM, typename T, bool kLam>
-__global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
+__global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
     const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
-    Ctrl *__restrict__ ctrl, int slot_in, double dt_fixed, double cfl, double dxmin, Ph ph)
+    Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in, double dt_fixed, Ph ph)
 {
-    constexpr int N = Ph::N, A = Ph::A, W = N + A;
+    constexpr int N = Ph::N, A = Ph::A, W = N + A, AA = A > 0 ? A : 1;
     constexpr int PH = kFvPmax + 2;
+    constexpr int DZ = DIM == 3 ? 2 : 1;   // z direction index (unused in 2D)
     __shared__ double lds[2][W][PH * PH];
 
     const int t = threadIdx.x;
@@ -118,36 +167,95 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     const int z1 = (DIM == 3) ? min(p, z0 + slab) : 1;
     // a slab can start beyond the last plane of a patch smaller than the
     // batch maximum: such a unit only takes part in the reductions
-    const bool active = (z0 < p) && t < p * p;
+    const bool work = z0 < p;
+    const bool active = work && t < p * p;
     const int x = active ? t % p : 0, y = active ? t / p : 0;
     const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot_in];
-    const double r = dt * P.inv_dx;
+    const double hr_ = 0.5 * dt * P.inv_dx;   // the face sums below are doubled
     const int li = (y + 1) * PH + (x + 1);
 
-    double qc[N], ac[A > 0 ? A : 1], qn[N], an[A > 0 ? A : 1], fzl[N], dzl[N], e[1];
+    // face-halo cell of each plane: wave w serves side w (-x, +x, -y, +y),
+    // so the extra loads and aux evaluations spread over all four waves
+    const int side = t >> 6, j = t & 63;
+    const bool halo = work && j < p;
+    int hsrc = 0, hdst = 0;
+    long long hoff = 0;
+    if (halo) {
+        int hx, hy, sx, sy;
+        if (side == 0)      { hx = -1; hy = j;  sx = p - 1; sy = j;     hoff = onb[0]; }
+        else if (side == 1) { hx = p;  hy = j;  sx = 0;     sy = j;     hoff = onb[1]; }
+        else if (side == 2) { hx = j;  hy = -1; sx = j;     sy = p - 1; hoff = onb[2]; }
+        else                { hx = j;  hy = p;  sx = j;     sy = 0;     hoff = onb[3]; }
+        hsrc = sy * p + sx;
+        hdst = (hy + 1) * PH + (hx + 1);
+    }
+    const long long cxy = (long long)y * p + x;
+    const long long pp = (long long)p * p;
+
+    // per thread: this plane (qc, ac), its z flux and speed (fzc, lzc), the
+    // doubled flux and fluctuation of the lower z face (fs2l, dn2l)
+    double qc[N], ac[AA], fzc[N], fs2l[N], dn2l[N], e[1];
+    double lzc = 0.0;
     double lm[3] = {0.0, 0.0, 0.0};
     bool bad = false;
+    // two-deep prefetch rings (raw storage-type values): the own column for
+    // planes z+1, z+2 and the halo cell for planes z, z+1
+    RawCell<Ph, T> rnA, rnB, hrA, hrB;
+
+    auto own_plane_off = [&](int zz) -> long long { return zz >= p ? onb[5] : P.off; };
+    auto own_plane_c = [&](int zz) -> long long { return (zz >= p ? zz - p : zz) * pp + cxy; };
 
     if (active) {
-        load_cell<Ph>(qin, ex, P.off, C, ((long long)z0 * p + y) * p + x, qc, e);
-        ph.aux(qc, e, ac);
+        RawCell<Ph, T> rc;
+        issue_load<Ph>(qin, ex, P.off, C, z0 * pp + cxy, rc);
         if (DIM == 3) {
-            double qm[N], am[A > 0 ? A : 1];
+            RawCell<Ph, T> rm;
             const long long om = (z0 == 0) ? onb[4] : P.off;
             const int zm = (z0 == 0) ? p - 1 : z0 - 1;
-            load_cell<Ph>(qin, ex, om, C, ((long long)zm * p + y) * p + x, qm, e);
+            issue_load<Ph>(qin, ex, om, C, zm * pp + cxy, rm);
+            issue_load<Ph>(qin, ex, own_plane_off(z0 + 1), C, own_plane_c(z0 + 1), rnA);
+            if (z0 + 1 < z1) issue_load<Ph>(qin, ex, own_plane_off(z0 + 2), C, own_plane_c(z0 + 2), rnB);
+            double qm[N], am[AA], fzm[N];
+            unpack<Ph>(rm, qm, e);
             ph.aux(qm, e, am);
-            rusanov_face<Ph, (DIM == 3 ? 2 : 1)>(ph, qm, am, qc, ac, fzl, dzl);
+            phys_flux_or_zero<Ph, DZ>(ph, qm, am, fzm);
+            unpack<Ph>(rc, qc, e);
+            ph.aux(qc, e, ac);
+            phys_flux_or_zero<Ph, DZ>(ph, qc, ac, fzc);
+            lzc = ph.template eig<DZ>(qc, ac);
+            rusanov_face2<Ph, DZ>(ph, qm, fzm, ph.template eig<DZ>(qm, am), qc, fzc, lzc, fs2l, dn2l);
+        } else {
+            unpack<Ph>(rc, qc, e);
+            ph.aux(qc, e, ac);
         }
     }
+    if (halo) {
+        issue_load<Ph>(qin, ex, hoff, C, z0 * pp + hsrc, hrA);
+        if (z0 + 1 < z1) issue_load<Ph>(qin, ex, hoff, C, (z0 + 1) * pp + hsrc, hrB);
+    }
 
-    for (int z = z0; z < z1; ++z) {
+    // one plane: consumes rn (own plane z+1) and hr (halo of plane z), then
+    // refills them with planes z+3 and z+2
+    auto plane = [&](int z, RawCell<Ph, T> &rn, RawCell<Ph, T> &hr) {
         double(*buf)[PH * PH] = lds[z & 1];
+        double qn[N], an[AA], fzn[N];
+        double lzn = 0.0;
         if (DIM == 3 && active) {
-            const long long on = (z + 1 == p) ? onb[5] : P.off;
-            const int zn = (z + 1 == p) ? 0 : z + 1;
-            load_cell<Ph>(qin, ex, on, C, ((long long)zn * p + y) * p + x, qn, e);
+            unpack<Ph>(rn, qn, e);
+            if (z + 2 < z1) issue_load<Ph>(qin, ex, own_plane_off(z + 3), C, own_plane_c(z + 3), rn);
             ph.aux(qn, e, an);
+            phys_flux_or_zero<Ph, DZ>(ph, qn, an, fzn);
+            lzn = ph.template eig<DZ>(qn, an);
+        }
+        if (halo) {
+            double hq[N], ha[AA];
+            unpack<Ph>(hr, hq, e);
+            if (z + 2 < z1) issue_load<Ph>(qin, ex, hoff, C, (z + 2) * pp + hsrc, hr);
+            ph.aux(hq, e, ha);
+#pragma unroll
+            for (int v = 0; v < N; ++v) buf[v][hdst] = hq[v];
+#pragma unroll
+            for (int a = 0; a < A; ++a) buf[N + a][hdst] = ha[a];
         }
         if (active) {
 #pragma unroll
@@ -155,64 +263,35 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
 #pragma unroll
             for (int a = 0; a < A; ++a) buf[N + a][li] = ac[a];
         }
-        if (t < 4 * p) {
-            // face-halo cell of this plane, gathered from the face neighbour
-            const int side = t / p, j = t - side * p;
-            int hx, hy, sx, sy;
-            long long o;
-            if (side == 0)      { hx = -1; hy = j;  sx = p - 1; sy = j;     o = onb[0]; }
-            else if (side == 1) { hx = p;  hy = j;  sx = 0;     sy = j;     o = onb[1]; }
-            else if (side == 2) { hx = j;  hy = -1; sx = j;     sy = p - 1; o = onb[2]; }
-            else                { hx = j;  hy = p;  sx = j;     sy = 0;     o = onb[3]; }
-            double hq[N], ha[A > 0 ? A : 1];
-            load_cell<Ph>(qin, ex, o, C, ((long long)z * p + sy) * p + sx, hq, e);
-            ph.aux(hq, e, ha);
-            const int hi = (hy + 1) * PH + (hx + 1);
-#pragma unroll
-            for (int v = 0; v < N; ++v) buf[v][hi] = hq[v];
-#pragma unroll
-            for (int a = 0; a < A; ++a) buf[N + a][hi] = ha[a];
-        }
         __syncthreads();
         if (active) {
-            double acc[N];
+            double acc2[N];
 #pragma unroll
-            for (int v = 0; v < N; ++v) acc[v] = 0.0;
-            double qs[N], as[A > 0 ? A : 1], F0[N], D0[N], F1[N], D1[N];
-            // x faces
+            for (int v = 0; v < N; ++v) acc2[v] = 0.0;
+            {
+                double qL[N], aL[AA], qR[N], aR[AA];
 #pragma unroll
-            for (int v = 0; v < N; ++v) qs[v] = buf[v][li - 1];
+                for (int v = 0; v < N; ++v) { qL[v] = buf[v][li - 1]; qR[v] = buf[v][li + 1]; }
 #pragma unroll
-            for (int a = 0; a < A; ++a) as[a] = buf[N + a][li - 1];
-            rusanov_face<Ph, 0>(ph, qs, as, qc, ac, F0, D0);
+                for (int a = 0; a < A; ++a) { aL[a] = buf[N + a][li - 1]; aR[a] = buf[N + a][li + 1]; }
+                rusanov_pair2<Ph, 0>(ph, qL, aL, qc, ac, qR, aR, acc2);
+            }
+            {
+                double qL[N], aL[AA], qR[N], aR[AA];
 #pragma unroll
-            for (int v = 0; v < N; ++v) qs[v] = buf[v][li + 1];
+                for (int v = 0; v < N; ++v) { qL[v] = buf[v][li - PH]; qR[v] = buf[v][li + PH]; }
 #pragma unroll
-            for (int a = 0; a < A; ++a) as[a] = buf[N + a][li + 1];
-            rusanov_face<Ph, 0>(ph, qc, ac, qs, as, F1, D1);
-#pragma unroll
-            for (int v = 0; v < N; ++v) acc[v] += (F1[v] - F0[v]) + (D1[v] + D0[v]);
-            // y faces
-#pragma unroll
-            for (int v = 0; v < N; ++v) qs[v] = buf[v][li - PH];
-#pragma unroll
-            for (int a = 0; a < A; ++a) as[a] = buf[N + a][li - PH];
-            rusanov_face<Ph, 1>(ph, qs, as, qc, ac, F0, D0);
-#pragma unroll
-            for (int v = 0; v < N; ++v) qs[v] = buf[v][li + PH];
-#pragma unroll
-            for (int a = 0; a < A; ++a) as[a] = buf[N + a][li + PH];
-            rusanov_face<Ph, 1>(ph, qc, ac, qs, as, F1, D1);
-#pragma unroll
-            for (int v = 0; v < N; ++v) acc[v] += (F1[v] - F0[v]) + (D1[v] + D0[v]);
-            // z faces: lower one carried from the previous plane
+                for (int a = 0; a < A; ++a) { aL[a] = buf[N + a][li - PH]; aR[a] = buf[N + a][li + PH]; }
+                rusanov_pair2<Ph, 1>(ph, qL, aL, qc, ac, qR, aR, acc2);
+            }
             if (DIM == 3) {
-                rusanov_face<Ph, (DIM == 3 ? 2 : 1)>(ph, qc, ac, qn, an, F1, D1);
+                double fs2u[N], dn2u[N];
+                rusanov_face2<Ph, DZ>(ph, qc, fzc, lzc, qn, fzn, lzn, fs2u, dn2u);
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                    acc[v] += (F1[v] - fzl[v]) + (D1[v] + dzl[v]);
-                    fzl[v] = F1[v];
-                    dzl[v] = D1[v];
+                    acc2[v] += (fs2u[v] - fs2l[v]) + (dn2u[v] + dn2l[v]);
+                    fs2l[v] = fs2u[v];
+                    dn2l[v] = dn2u[v];
                 }
             }
             double S[N];
@@ -223,39 +302,40 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
                 for (int v = 0; v < N; ++v) S[v] = 0.0;
             }
             double qw[N];
-            T *dst = qout + P.off * N + ((long long)z * p + y) * p + x;
+            T *dst = qout + P.off * N + z * pp + cxy;
 #pragma unroll
             for (int v = 0; v < N; ++v) {
-                const double nv = qc[v] - r * acc[v] + dt * S[v];
+                const double nv = qc[v] - hr_ * acc2[v] + dt * S[v];
                 const T st = (T)nv;
-                dst[(long long)v * C] = st;
+                __builtin_nontemporal_store(st, dst + (long long)v * C);
                 qw[v] = (double)st;
                 bad |= !isfinite(qw[v]);
             }
-            if (kLam) {
-                double aw[A > 0 ? A : 1];
-                ph.aux(qw, e, aw);
-                cell_speeds<Ph, DIM>(ph, qw, aw, lm);
-            }
+            if (kLam) cell_speeds_fast<Ph, DIM>(ph, qw, lm);
         }
         if (DIM == 3) {
 #pragma unroll
-            for (int v = 0; v < N; ++v) qc[v] = qn[v];
+            for (int v = 0; v < N; ++v) { qc[v] = qn[v]; fzc[v] = fzn[v]; }
 #pragma unroll
             for (int a = 0; a < A; ++a) ac[a] = an[a];
+            lzc = lzn;
         }
+    };
+
+    for (int z = z0; z < z1; z += 2) {
+        plane(z, rnA, hrA);
+        if (z + 1 < z1) plane(z + 1, rnB, hrB);
     }
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
-    if (kLam) finish_lambda<DIM>(ctrl, lm, n_units, slot_in ^ 1, cfl, dxmin);
+    if (kLam) store_partial<DIM>(part, lm, unit, n_units);
 }
 
 // Largest speeds of the current state (first step of a call in CFL mode):
-// one work-group per patch, dt written into ctrl->dt[0].
+// one work-group per patch, partial maxima per patch.
 template <class Ph, int DIM, typename T>
 __global__ __launch_bounds__(kFvThreads) void fv_lambda_kernel(const T *__restrict__ q,
                                                                const PatchDev *__restrict__ patches,
-                                                               int n_units, Ctrl *__restrict__ ctrl,
-                                                               double cfl, double dxmin, Ph ph)
+                                                               double *__restrict__ part, Ph ph)
 {
     constexpr int N = Ph::N, A = Ph::A;
     const PatchDev P = patches[blockIdx.x];
@@ -269,7 +349,36 @@ __global__ __launch_bounds__(kFvThreads) void fv_lambda_kernel(const T *__restri
         ph.aux(qc, e, ac);
         cell_speeds<Ph, DIM>(ph, qc, ac, lm);
     }
-    finish_lambda<DIM>(ctrl, lm, n_units, 0, cfl, dxmin);
+    store_partial<DIM>(part, lm, blockIdx.x, gridDim.x);
+}
+
+// dt from the partial maxima: Lambda_d = max over units, then
+// dt = cfl / sum_d (Lambda_d / dx_min), written to ctrl->dt[slot].  One
+// work-group; the max is exact, so the result does not depend on the order.
+__global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restrict__ part, int n_units, int dim,
+                                                         Ctrl *__restrict__ ctrl, int slot, double cfl,
+                                                         double dxmin)
+{
+    __shared__ double red[3][1024 / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    for (int d = 0; d < dim; ++d) {
+        double m = 0.0;
+        for (int i = t; i < n_units; i += blockDim.x) m = fmax(m, part[(long long)d * n_units + i]);
+        m = wave_max(m);
+        if (lane == 0) red[d][w] = m;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double den = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            double m = red[d][0];
+            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[d][i]);
+            den += m / dxmin;
+        }
+        const double dt = cfl / den;
+        ctrl->dt[slot] = dt;
+        ctrl->last_dt = dt;
+    }
 }
 
 __global__ void ctrl_init_kernel(Ctrl *ctrl)
@@ -292,25 +401,32 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     const int n_slabs = (DIM == 3) ? (b->pmax + slab - 1) / slab : 1;
     const int n_units = b->K * n_slabs;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
+    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    double *part = reinterpret_cast<double *>(b->ws + L.part);
     const T *qi = static_cast<const T *>(qin);
     T *qo = static_cast<T *>(qout);
-    const double *ex = Ph::E ? reinterpret_cast<const double *>(b->ws + ws_layout(b->pde, b->total_cells, b->N, b->storage).pres)
+    const double *ex = Ph::E ? reinterpret_cast<const double *>(b->ws + L.pres)
                              : nullptr;
     if constexpr (Ph::E > 0) {  // SRHD: dt comes from the con2prim pass
         hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
-                           ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, slot_in,
-                           dt_fixed, cfl, b->dxmin, ph);
+                           ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
+                           slot_in, dt_fixed, ph);
     } else {
         if (dt_fixed > 0.0)
             hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi,
-                               qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, slot_in,
-                               dt_fixed, cfl, b->dxmin, ph);
+                               qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
+                               slot_in, dt_fixed, ph);
         else
             hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, true>), dim3(n_units), dim3(kFvThreads), 0, s, qi,
-                               qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, slot_in,
-                               dt_fixed, cfl, b->dxmin, ph);
+                               qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
+                               slot_in, dt_fixed, ph);
     }
     PB_HIP(hipGetLastError());
+    if (!(dt_fixed > 0.0) && Ph::E == 0) {
+        hipLaunchKernelGGL(dt_reduce_kernel, dim3(1), dim3(1024), 0, s, part, n_units, DIM, ctrl, slot_in ^ 1,
+                           cfl, b->dxmin);
+        PB_HIP(hipGetLastError());
+    }
     return PB_OK;
 }
 
@@ -318,8 +434,12 @@ template <class Ph, int DIM, typename T>
 pb_status launch_lambda_typed(pb_batch *b, const Ph &ph, const void *q, double cfl, hipStream_t s)
 {
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
+    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    double *part = reinterpret_cast<double *>(b->ws + L.part);
     hipLaunchKernelGGL((fv_lambda_kernel<Ph, DIM, T>), dim3(b->K), dim3(kFvThreads), 0, s,
-                       static_cast<const T *>(q), b->d_patches, b->K, ctrl, cfl, b->dxmin, ph);
+                       static_cast<const T *>(q), b->d_patches, part, ph);
+    PB_HIP(hipGetLastError());
+    hipLaunchKernelGGL(dt_reduce_kernel, dim3(1), dim3(1024), 0, s, part, b->K, DIM, ctrl, 0, cfl, b->dxmin);
     PB_HIP(hipGetLastError());
     return PB_OK;
 }

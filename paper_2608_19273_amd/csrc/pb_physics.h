@@ -21,7 +21,39 @@
 
 #include <hip/hip_runtime.h>
 
+#ifndef PB_FASTDIV
+#define PB_FASTDIV 0
+#endif
+
 namespace pb {
+
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (error within an ulp or two of the correctly rounded quotient; x finite, nonzero).
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(a) from the hardware reciprocal-square-root estimate refined by
+// Goldschmidt/Newton steps; a <= 0, inf and NaN take the library path.
+__device__ __forceinline__ double root(double a)
+{
+    if (!(a > 0.0 && a < 1e300)) return sqrt(a);
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    const double d = fma(-g, g, a);
+    return fma(d, h, g);
+}
 
 // Linear advection, conservative form: F_d = a_d q, S = -kappa q.
 struct AdvF {
@@ -30,6 +62,7 @@ struct AdvF {
     double a[3];
     double kappa;
     __device__ __forceinline__ void aux(const double *, const double *, double *) const {}
+    __device__ __forceinline__ void aux_fast(const double *, const double *, double *) const {}
     template <int D> __device__ __forceinline__ double eig(const double *, const double *) const
     {
         return fabs(a[D]);
@@ -52,6 +85,7 @@ struct AdvB {
     double a[3];
     double kappa;
     __device__ __forceinline__ void aux(const double *, const double *, double *) const {}
+    __device__ __forceinline__ void aux_fast(const double *, const double *, double *) const {}
     template <int D> __device__ __forceinline__ double eig(const double *, const double *) const
     {
         return fabs(a[D]);
@@ -80,13 +114,31 @@ struct Euler {
     double gamma;
     __device__ __forceinline__ void aux(const double *q, const double *, double *a) const
     {
+#if PB_FASTDIV
+        const double ir = recip(q[0]);
+#else
         const double ir = 1.0 / q[0];
+#endif
         double m2 = q[1] * q[1] + q[2] * q[2];
         if (DIM == 3) m2 += q[3] * q[3];
         const double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * m2 * ir);
         a[0] = ir;
         a[1] = p;
+#if PB_FASTDIV
+        a[2] = root(gamma * p * ir);
+#else
         a[2] = sqrt(gamma * p * ir);
+#endif
+    }
+    __device__ __forceinline__ void aux_fast(const double *q, const double *, double *a) const
+    {
+        const double ir = recip(q[0]);
+        double m2 = q[1] * q[1] + q[2] * q[2];
+        if (DIM == 3) m2 += q[3] * q[3];
+        const double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * m2 * ir);
+        a[0] = ir;
+        a[1] = p;
+        a[2] = root(gamma * p * ir);
     }
     template <int D> __device__ __forceinline__ double eig(const double *q, const double *a) const
     {
@@ -137,6 +189,7 @@ struct Srhd {
             a[4 + d] = fmax(fabs(lp), fabs(lm));
         }
     }
+    __device__ __forceinline__ void aux_fast(const double *q, const double *e, double *a) const { aux(q, e, a); }
     template <int D> __device__ __forceinline__ double eig(const double *, const double *a) const
     {
         return a[4 + D];
@@ -182,6 +235,62 @@ __device__ __forceinline__ void rusanov_face(const Ph &ph, const double *qL, con
     } else {
 #pragma unroll
         for (int v = 0; v < N; ++v) Dn[v] = 0.0;
+    }
+}
+
+// Both faces of a cell along D at once, times two:
+//   2 [(F*_{+} - F*_{-}) + (Dn_{+} + Dn_{-})]
+//   = (F(R) - F(L)) - s_{+} (Q_R - Q) + s_{-} (Q - Q_L)
+//     + B(mid_{+}) (Q_R - Q) + B(mid_{-}) (Q - Q_L),
+// with s_{+-} the Rusanov speeds of the two faces.  F(Q) of the cell itself
+// cancels, so only the two neighbours' fluxes are evaluated.
+template <class Ph, int D>
+__device__ __forceinline__ void rusanov_pair2(const Ph &ph, const double *qL, const double *aL,
+                                              const double *q, const double *a, const double *qR,
+                                              const double *aR, double *acc2)
+{
+    constexpr int N = Ph::N;
+    const double l0 = ph.template eig<D>(q, a);
+    const double sp = fmax(l0, ph.template eig<D>(qR, aR));
+    const double sm = fmax(l0, ph.template eig<D>(qL, aL));
+    if (Ph::kFlux) {
+        double FL[N], FR[N];
+        ph.template flux<D>(qL, aL, FL);
+        ph.template flux<D>(qR, aR, FR);
+#pragma unroll
+        for (int v = 0; v < N; ++v) acc2[v] += (FR[v] - FL[v]) - sp * (qR[v] - q[v]) + sm * (q[v] - qL[v]);
+    } else {
+#pragma unroll
+        for (int v = 0; v < N; ++v) acc2[v] += sm * (q[v] - qL[v]) - sp * (qR[v] - q[v]);
+    }
+    if (Ph::kNcp) {
+        double o0[N], o1[N];
+        ph.template ncp<D>(qL, q, o0);
+        ph.template ncp<D>(q, qR, o1);
+#pragma unroll
+        for (int v = 0; v < N; ++v) acc2[v] += o1[v] + o0[v];
+    }
+}
+
+// Twice the Rusanov face flux between L and R along D, given the two
+// physical fluxes and speeds (used for the z faces, whose fluxes are carried
+// from plane to plane), and twice the midpoint fluctuation, kept apart because
+// the flux enters the two cells with opposite signs and the fluctuation with
+// the same sign:  2 F* = F_L + F_R - s (Q_R - Q_L),  2 Dn = B(mid)(Q_R - Q_L).
+template <class Ph, int D>
+__device__ __forceinline__ void rusanov_face2(const Ph &ph, const double *qL, const double *FL,
+                                              double lL, const double *qR, const double *FR,
+                                              double lR, double *Fs2, double *Dn2)
+{
+    constexpr int N = Ph::N;
+    const double s = fmax(lL, lR);
+#pragma unroll
+    for (int v = 0; v < N; ++v) Fs2[v] = (FL[v] + FR[v]) - s * (qR[v] - qL[v]);
+    if (Ph::kNcp) {
+        ph.template ncp<D>(qL, qR, Dn2);
+    } else {
+#pragma unroll
+        for (int v = 0; v < N; ++v) Dn2[v] = 0.0;
     }
 }
 

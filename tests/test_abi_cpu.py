@@ -45,16 +45,22 @@ def desc_for(b, state=1, alt=2, ws=256, ws_bytes=1 << 40, storage=0, **over):
 
 
 def test_workspace_size_layout():
+    def a256(v):
+        return (v + 255) // 256 * 256
+
+    def part(K):  # per-unit partial maxima [3][16 K] doubles
+        return a256(3 * 16 * K * 8)
+
     b = I.config0()
     d, keep = desc_for(b)
-    assert pb.pb_workspace_size(d) == 256  # control block only
+    assert pb.pb_workspace_size(d) == 256 + part(b.K)
     b3 = I.config3(grid=(2, 2, 1), p=4)
     d, keep = desc_for(b3)
-    assert pb.pb_workspace_size(d) == 256 + ((b3.total_cells * 8 + 255) // 256) * 256
+    assert pb.pb_workspace_size(d) == 256 + part(b3.K) + a256(b3.total_cells * 8)
     b2 = I.config2(n_patches=8, N=58, sizes=np.array([4] * 8, np.int32))
     d, keep = desc_for(b2)
-    per = ((b2.total_cells * 58 * 8 + 255) // 256) * 256
-    assert pb.pb_workspace_size(d) == 256 + 2 * per
+    per = a256(b2.total_cells * 58 * 8)
+    assert pb.pb_workspace_size(d) == 256 + part(b2.K) + 2 * per
 
 
 @pytest.mark.parametrize("field,value,msg", [
