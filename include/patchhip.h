@@ -206,7 +206,8 @@ pb_status pb_batch_set_c2p_guess(pb_batch *b, int32_t guess, const pb_mlp *mlp);
  * in FP32 on the matrix cores, biases are FP32, the output stays FP32.
  * Features of a conserved state (all scale-free, since p/E depends only on
  * D/E and |S|/E):
- *   x = [log(D/E), |S|/E, log(1 - |S|/E), log(tau/E), (|S|/E)^2],
+ *   x = [log(D/E), |S|/E, log(1 - |S|/E), log(tau/E), log((tau (tau + 2D) - |S|^2)/E^2)]
+ * (the last is log((E^2 - D^2 - |S|^2)/E^2), which measures the internal energy),
  * standardised with the stored mean/std; the target is y = log(p/E),
  * standardised with mu_y, sigma_y: p0 = E exp(mu_y + sigma_y yhat).
  * Training (FP32 master weights, Adam) runs on the device with the library's
@@ -226,6 +227,9 @@ pb_status pb_mlp_destroy(pb_mlp *m);
 /* host <-> library copies of the FP32 master parameters and normalisation */
 pb_status pb_mlp_set_params(pb_mlp *m, const float *params, const float *norm);
 pb_status pb_mlp_get_params(pb_mlp *m, float *params, float *norm);
+/* raw features (the five values listed above, unstandardised) of n conserved
+ * states: cons device SoA [5][n] doubles, x device [n][5] FP32 */
+pb_status pb_mlp_features(const void *cons, void *x, int64_t n, void *stream);
 /* yhat for n feature rows: x device [n][5] FP32 (raw, unstandardised features),
  * y device [n] FP32 */
 pb_status pb_mlp_forward(const pb_mlp *m, const void *x, void *y, int64_t n, void *stream);

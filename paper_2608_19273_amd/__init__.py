@@ -91,6 +91,7 @@ def lib():
         L.pb_mlp_set_params.argtypes = [vp, fp, fp]
         L.pb_mlp_get_params.argtypes = [vp, fp, fp]
         L.pb_mlp_forward.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.pb_mlp_features.argtypes = [vp, vp, C.c_int64, vp]
         L.pb_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.pb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                                         C.c_int32, vp, vp]
@@ -98,7 +99,7 @@ def lib():
                      "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_set_c2p_guess", "pb_batch_profile",
                      "pb_batch_profile_read", "pb_stream_copy", "fv_rusanov_step",
                      "fd_ko_step", "con2prim", "pb_mlp_create", "pb_mlp_destroy", "pb_mlp_set_params",
-                     "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_grad", "pb_mlp_train_step"):
+                     "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_features", "pb_mlp_grad", "pb_mlp_train_step"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -172,6 +173,72 @@ def pb_stream_copy(src, dst):
 
 
 # -------------------------------------------------------------- wrappers --
+
+
+class Mlp:
+    """The learned con2prim guess network (library-owned device parameters)."""
+
+    def __init__(self, params=None, norm=None):
+        h = C.c_void_p()
+        _check(lib().pb_mlp_create(C.byref(h)), "pb_mlp_create")
+        self.handle = h
+        if params is not None:
+            self.set_params(params, norm)
+
+    def close(self):
+        if self.handle:
+            lib().pb_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params, norm):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        nn = np.ascontiguousarray(norm, dtype=np.float32)
+        assert p.size == MLP_NPARAM and nn.size == MLP_NNORM
+        fp = C.POINTER(C.c_float)
+        _check(lib().pb_mlp_set_params(self.handle, p.ctypes.data_as(fp), nn.ctypes.data_as(fp)),
+               "pb_mlp_set_params")
+
+    def get_params(self):
+        p = np.zeros(MLP_NPARAM, np.float32)
+        nn = np.zeros(MLP_NNORM, np.float32)
+        fp = C.POINTER(C.c_float)
+        _check(lib().pb_mlp_get_params(self.handle, p.ctypes.data_as(fp), nn.ctypes.data_as(fp)),
+               "pb_mlp_get_params")
+        return p, nn
+
+    def forward(self, x):
+        """x: torch float32 device [n, 5] raw features -> torch [n]"""
+        import torch
+        y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+        _check(lib().pb_mlp_forward(self.handle, _ptr(x), _ptr(y), x.shape[0], _stream()), "pb_mlp_forward")
+        return y
+
+    def grad(self, x, t):
+        import torch
+        g = torch.empty(MLP_NPARAM, dtype=torch.float32, device=x.device)
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+        _check(lib().pb_mlp_grad(self.handle, _ptr(x), _ptr(t), x.shape[0], _ptr(g), _ptr(loss), _stream()),
+               "pb_mlp_grad")
+        return g, loss
+
+    def train_step(self, x, t, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
+        _check(lib().pb_mlp_train_step(self.handle, _ptr(x), _ptr(t), x.shape[0], lr, beta1, beta2, eps, step,
+                                       _ptr(loss), _stream()), "pb_mlp_train_step")
+
+
+def pb_mlp_features(cons):
+    """cons: torch float64 device [5, n] -> raw features torch float32 [n, 5]"""
+    import torch
+    n = cons.shape[-1]
+    x = torch.empty((n, MLP_IN), dtype=torch.float32, device=cons.device)
+    _check(lib().pb_mlp_features(_ptr(cons), _ptr(x), n, _stream()), "pb_mlp_features")
+    return x
 
 
 class PatchBatch:

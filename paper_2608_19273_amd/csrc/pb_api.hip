@@ -32,7 +32,7 @@ WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K)
     o += sizeof(Ctrl);
     o = align256(o);
     L.part = o;
-    o = align256(o + (size_t)3 * (size_t)max_units(K) * sizeof(double));
+    o = align256(o + (size_t)8 * (size_t)max_units(K) * sizeof(double));
     if (pde == PB_PDE_SRHD) {
         L.pres = o;
         o = align256(o + (size_t)total_cells * sizeof(double));
@@ -294,6 +294,7 @@ pb_status pb_batch_reset(pb_batch *b, int32_t which)
     if (which != 0 && which != 1) { set_error("which must be 0 or 1"); return PB_EINVAL; }
     b->cur = which;
     b->steps = 0;
+    b->pres_valid = false;
     return launch_ctrl_init(b, b->stream);
 }
 

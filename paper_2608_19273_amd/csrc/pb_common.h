@@ -107,6 +107,7 @@ struct pb_batch {
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
+    bool pres_valid = false;         // SRHD: the workspace holds a previous pressure
     // graph cache
     struct GraphEntry {
         int kind, n_steps, parity_cur;
@@ -127,7 +128,7 @@ namespace pb {
 // workspace sub-ranges (byte offsets), from the batch description
 struct WsLayout {
     size_t ctrl = 0;       // Ctrl
-    size_t part = 0;       // per-unit partial maxima of the speeds [3][units]
+    size_t part = 0;       // per-unit partials [8][units]: speeds (3), con2prim stats (5)
     size_t pres = 0;       // SRHD: pressure per cell (double)
     size_t yA = 0, yB = 0; // FD: stage buffers
     size_t total = 0;
@@ -147,4 +148,6 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
                           hipStream_t s);
 pb_status launch_fd_lambda(pb_batch *b, double cfl, hipStream_t s);
 pb_status launch_ctrl_init(pb_batch *b, hipStream_t s);
+pb_status launch_dt_reduce(pb_batch *b, const double *part, int n_units, int dim, int slot, double cfl, bool want_dt,
+                           bool want_stats, hipStream_t s);
 }  // namespace pb

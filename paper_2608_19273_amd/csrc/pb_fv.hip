@@ -353,31 +353,56 @@ __global__ __launch_bounds__(kFvThreads) void fv_lambda_kernel(const T *__restri
 }
 
 // dt from the partial maxima: Lambda_d = max over units, then
-// dt = cfl / sum_d (Lambda_d / dx_min), written to ctrl->dt[slot].  One
-// work-group; the max is exact, so the result does not depend on the order.
+// dt = cfl / sum_d (Lambda_d / dx_min), written to ctrl->dt[slot].  With
+// stats, rows 3..7 of the partials (con2prim iterations, failures, largest
+// iteration count, fallbacks, cells) are folded into the control block.
+// One work-group; maxima are exact and the sums are of integers held exactly
+// in doubles, so the result does not depend on the order.
 __global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restrict__ part, int n_units, int dim,
                                                          Ctrl *__restrict__ ctrl, int slot, double cfl,
-                                                         double dxmin)
+                                                         double dxmin, int want_dt, int want_stats)
 {
-    __shared__ double red[3][1024 / kWave];
+    __shared__ double red[8][1024 / kWave];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-    for (int d = 0; d < dim; ++d) {
+    const int rows = want_stats ? 8 : dim;
+    for (int r = 0; r < rows; ++r) {
+        if (r >= dim && r < 3) continue;
+        const bool mx = r < 3 || r == 5;
         double m = 0.0;
-        for (int i = t; i < n_units; i += blockDim.x) m = fmax(m, part[(long long)d * n_units + i]);
-        m = wave_max(m);
-        if (lane == 0) red[d][w] = m;
+        for (int i = t; i < n_units; i += blockDim.x) {
+            const double v = part[(long long)r * n_units + i];
+            m = mx ? fmax(m, v) : m + v;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double u = __shfl_xor(m, o, kWave);
+            m = mx ? fmax(m, u) : m + u;
+        }
+        if (lane == 0) red[r][w] = m;
     }
     __syncthreads();
     if (t == 0) {
-        double den = 0.0;
-        for (int d = 0; d < dim; ++d) {
-            double m = red[d][0];
-            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[d][i]);
-            den += m / dxmin;
+        double tot[8];
+        for (int r = 0; r < rows; ++r) {
+            if (r >= dim && r < 3) continue;
+            const bool mx = r < 3 || r == 5;
+            double m = red[r][0];
+            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = mx ? fmax(m, red[r][i]) : m + red[r][i];
+            tot[r] = m;
         }
-        const double dt = cfl / den;
-        ctrl->dt[slot] = dt;
-        ctrl->last_dt = dt;
+        if (want_dt) {
+            double den = 0.0;
+            for (int d = 0; d < dim; ++d) den += tot[d] / dxmin;
+            const double dt = cfl / den;
+            ctrl->dt[slot] = dt;
+            ctrl->last_dt = dt;
+        }
+        if (want_stats) {
+            ctrl->c2p_iters += (unsigned long long)tot[3];
+            ctrl->c2p_fail += (unsigned long long)tot[4];
+            if ((unsigned)tot[5] > ctrl->c2p_maxit) ctrl->c2p_maxit = (unsigned)tot[5];
+            ctrl->c2p_fallback += (unsigned long long)tot[6];
+            ctrl->c2p_cells += (unsigned long long)tot[7];
+        }
     }
 }
 
@@ -423,9 +448,8 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     }
     PB_HIP(hipGetLastError());
     if (!(dt_fixed > 0.0) && Ph::E == 0) {
-        hipLaunchKernelGGL(dt_reduce_kernel, dim3(1), dim3(1024), 0, s, part, n_units, DIM, ctrl, slot_in ^ 1,
-                           cfl, b->dxmin);
-        PB_HIP(hipGetLastError());
+        pb_status st = launch_dt_reduce(b, part, n_units, DIM, slot_in ^ 1, cfl, true, false, s);
+        if (st != PB_OK) return st;
     }
     return PB_OK;
 }
@@ -439,9 +463,8 @@ pb_status launch_lambda_typed(pb_batch *b, const Ph &ph, const void *q, double c
     hipLaunchKernelGGL((fv_lambda_kernel<Ph, DIM, T>), dim3(b->K), dim3(kFvThreads), 0, s,
                        static_cast<const T *>(q), b->d_patches, part, ph);
     PB_HIP(hipGetLastError());
-    hipLaunchKernelGGL(dt_reduce_kernel, dim3(1), dim3(1024), 0, s, part, b->K, DIM, ctrl, 0, cfl, b->dxmin);
-    PB_HIP(hipGetLastError());
-    return PB_OK;
+    (void)ctrl;
+    return launch_dt_reduce(b, part, b->K, DIM, 0, cfl, true, false, s);
 }
 
 // dispatch on (pde, dim, storage); F is a generic lambda taking (phys, dim tag, T tag)
@@ -506,6 +529,16 @@ pb_status launch_fv_lambda(pb_batch *b, const void *q, double cfl, hipStream_t s
             return launch_lambda_typed<Ph, DIM, T>(b, ph, q, cfl, s);
         }
     });
+}
+
+pb_status launch_dt_reduce(pb_batch *b, const double *part, int n_units, int dim, int slot, double cfl, bool want_dt,
+                           bool want_stats, hipStream_t s)
+{
+    if (!want_dt && !want_stats) return PB_OK;
+    hipLaunchKernelGGL(dt_reduce_kernel, dim3(1), dim3(1024), 0, s, part, n_units, dim, reinterpret_cast<Ctrl *>(b->ws),
+                       slot, cfl, b->dxmin, want_dt ? 1 : 0, want_stats ? 1 : 0);
+    PB_HIP(hipGetLastError());
+    return PB_OK;
 }
 
 pb_status launch_ctrl_init(pb_batch *b, hipStream_t s)

@@ -1,0 +1,110 @@
+"""GPU parity of the SRHD path: standalone con2prim and the SRHD Rusanov step
+(con2prim pass + fused FV kernel) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2608_19273_amd as pb
+from paper_2608_19273_amd import inputs as I
+
+from gpu_helpers import announce, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+GAM = 5.0 / 3.0
+
+
+def gpu_c2p(cons, guess="plain", p_prev=None, maxit=50, mlp=None):
+    torch = need_gpu()
+    c = torch.from_numpy(np.ascontiguousarray(cons)).cuda()
+    n = cons.shape[1]
+    prim = torch.empty((5, n), dtype=torch.float64, device="cuda")
+    it = torch.empty(n, dtype=torch.int32, device="cuda")
+    st = torch.empty(n, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(8, dtype=torch.int64, device="cuda")
+    pp = None if p_prev is None else torch.from_numpy(np.ascontiguousarray(p_prev)).cuda()
+    pb.con2prim(c, prim, GAM, 1e-12, maxit, guess=guess, mlp=mlp, p_prev=pp, iters=it, status=st, counters=cnt)
+    torch.cuda.synchronize()
+    return prim.cpu().numpy(), it.cpu().numpy(), st.cpu().numpy(), cnt.cpu().numpy()
+
+
+def cond_bound(cons, p):
+    """conditioning of the pressure recovery, eps_mach W^2 / eps (the
+    cancellation in f), floored at 1e-12"""
+    rho, vx, vy, vz, pr = oracle.con2prim(cons)[0]
+    v2 = vx * vx + vy * vy + vz * vz
+    W2 = 1.0 / (1.0 - v2)
+    eps = pr / ((GAM - 1) * rho)
+    return np.maximum(1e-12, 8 * 2.2e-16 * W2 / eps)
+
+
+def test_con2prim_plain_parity():
+    announce("con2prim plain")
+    n = 200000
+    rho, vx, vy, vz, eps = I.srhd_primitives(21, n)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, GAM)
+    g, git, gst, cnt = gpu_c2p(cons)
+    o, oit, ost, nfail, _ = oracle.con2prim(cons)
+    assert np.all(gst == 0) and nfail == 0
+    rel = np.abs(g[4] - o[4]) / o[4]
+    assert np.all(rel <= cond_bound(cons, p))
+    np.testing.assert_allclose(g[0], o[0], rtol=1e-10)
+    np.testing.assert_allclose(g[1:4], o[1:4], rtol=0, atol=1e-12)
+    assert np.mean(git == oit) > 0.99 and np.max(np.abs(git - oit)) <= 1
+    assert cnt[1] == git.sum() and cnt[3] == git.max() and cnt[0] == 0
+
+
+def test_con2prim_special_cases():
+    announce("con2prim special cases")
+    bad = np.array([[1.0, 0.1, 0, 0, -0.1], [-1.0, 0, 0, 0, 1.0], [np.nan, 0, 0, 0, 1.0]]).T
+    _, it, st, cnt = gpu_c2p(bad)
+    assert np.all(st == 2) and cnt[0] == 3
+    cons, p = I.srhd_prim_to_cons(np.array([1.0, 2.0]), np.array([0.6, 0.0]), np.zeros(2), np.zeros(2),
+                                  np.array([0.01, 0.7]), GAM)
+    _, it, st, _ = gpu_c2p(cons, maxit=0)
+    assert st[0] == 1 and st[1] == 0 and it[1] == 0  # v = 0: the plain guess is the root
+    g, it, st, _ = gpu_c2p(cons, guess="warm", p_prev=p)
+    assert np.all(st == 0) and np.all(it <= 1)
+    np.testing.assert_allclose(g[4], p, rtol=1e-13)
+
+
+def test_srhd_step_parity():
+    """SRHD Rusanov steps on i.i.d. random primitives, 4x4x2 patches of 16^3."""
+    announce("srhd step parity")
+    torch = need_gpu()
+    b = I.config3(grid=(4, 4, 2), seed=31)
+    o, dts, ost = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    B = pb.PatchBatch(b)
+    dt = B.fv_rusanov_step(cfl=0.4, n_steps=2, want_dt=True)
+    g = B.download()
+    st = B.stats()
+    B.close()
+    err = rel_err(b, g, o)
+    assert np.all(err <= 1e-12), err
+    assert abs(dt - dts[-1]) <= 1e-13 * dts[-1]
+    assert st["c2p_failures"] == ost.c2p_fail
+    assert st["c2p_cells"] == 2 * b.total_cells
+    assert st["c2p_max_iterations"] <= 50
+
+
+def test_srhd_free_stream_and_warm_guess():
+    announce("srhd free stream / warm guess")
+    b = I.config3(grid=(2, 2, 2), p=8)
+    cons, _ = I.srhd_prim_to_cons(np.array([0.7]), np.array([0.3]), np.array([-0.2]), np.array([0.5]),
+                                  np.array([0.9]), GAM)
+    uni = b.copy()
+    uni.state = np.tile(np.repeat(cons[:, 0], 512), 8)
+    B = pb.PatchBatch(uni)
+    B.fv_rusanov_step(cfl=0.4, n_steps=3)
+    np.testing.assert_array_equal(B.download(), uni.state)
+    B.close()
+    # warm-started con2prim gives the same evolution (to roundoff) as plain
+    bb = I.config3(grid=(2, 2, 2), p=8, seed=5)
+    P = pb.PatchBatch(bb)
+    P.fv_rusanov_step(cfl=0.4, n_steps=3)
+    W = pb.PatchBatch(bb)
+    W.set_c2p_guess("warm")
+    W.fv_rusanov_step(cfl=0.4, n_steps=3)
+    assert np.all(rel_err(bb, W.download(), P.download()) <= 1e-12)
+    assert W.stats()["c2p_iterations"] < P.stats()["c2p_iterations"]
+    P.close()
+    W.close()

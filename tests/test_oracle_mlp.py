@@ -1,0 +1,70 @@
+"""Pins of the MLP reference: bfloat16 rounding against torch's own
+conversion, a network with a closed-form output, and the hand-written
+backward pass against central finite differences."""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from paper_2608_19273_amd import inputs as I
+
+
+def test_bf16_rne_matches_torch_conversion():
+    torch = pytest.importorskip("torch")
+    x = np.concatenate([I.normal(3, 20000).astype(np.float32) * 100,
+                        np.float32([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 65504.0, 1e-30, 0.0])])
+    ours = M.bf16_rne(x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).float().numpy()
+    np.testing.assert_array_equal(ours, ref)
+    assert M.bf16_rne(np.float32(1.0 + 2 ** -8)) == 1.0          # tie to even (down)
+    assert M.bf16_rne(np.float32(1.0 + 3 * 2 ** -8)) == 1.0 + 2 ** -6  # tie to even (up)
+
+
+def test_closed_form_abs_network():
+    """Hidden unit 0 = x0, unit 1 = -x0 (after the ReLU: |x0| split), layer 2
+    copies them, w3 = (1, 1): the output is |x0| exactly (values that bf16
+    holds exactly)."""
+    W1 = np.zeros((64, 5)); W1[0, 0] = 1.0; W1[1, 0] = -1.0
+    W2 = np.zeros((64, 64)); W2[0, 0] = 1.0; W2[1, 1] = 1.0
+    w3 = np.zeros(64); w3[0] = 1.0; w3[1] = 1.0
+    p = M.pack(W1, np.zeros(64), W2, np.zeros(64), w3, 0.25)
+    norm = np.array([0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 0, 1], np.float32)
+    x = np.zeros((6, 5)); x[:, 0] = [-3.0, -0.5, 0.0, 0.75, 2.0, 1.5]
+    for bf in (True, False):
+        np.testing.assert_array_equal(M.forward(p, norm, x, bf16=bf), np.abs(x[:, 0]) + 0.25)
+
+
+def test_backward_against_finite_differences():
+    rng_p = I.normal(5, M.NPARAM) * 0.3
+    norm = np.array([0.1, -0.2, 0.3, 0.0, 0.5, 1.1, 0.9, 1.3, 0.7, 1.0, -2.0, 3.0])
+    x = I.normal(6, 40 * 5).reshape(40, 5)
+    t = I.normal(7, 40)
+    loss, g = M.loss_and_grad(rng_p, norm, x, t, bf16=False)
+    h = 1e-6
+    idx = list(range(0, 320, 37)) + [320, 333, 384 + 5, 384 + 64 * 33, 4480 + 3, 4544 + 10, 4608]
+    for i in idx:
+        e = np.zeros_like(rng_p); e[i] = h
+        fp = M.loss_and_grad(rng_p + e, norm, x, t, bf16=False)[0]
+        fm = M.loss_and_grad(rng_p - e, norm, x, t, bf16=False)[0]
+        fd = (fp - fm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+def test_adam_reference_first_step():
+    """First bias-corrected Adam step moves every parameter by lr * sign(g)
+    (up to eps)."""
+    p = np.zeros(10)
+    g = np.linspace(-1, 1, 10) + 0.05
+    p1, m, v = M.adam_step(p, np.zeros(10), np.zeros(10), g, 1, lr=1e-3)
+    np.testing.assert_allclose(p1, -1e-3 * np.sign(g), rtol=1e-6)
+
+
+def test_features_match_conservative_scaling():
+    """features depend on D/E and |S|/E only: scaling the state leaves them
+    unchanged; the target log(p/E) likewise."""
+    cons, p = I.srhd_training_pairs(9, 100)
+    f1 = M.features(cons)
+    f2 = M.features(cons * 7.5)
+    np.testing.assert_allclose(f1[:, :4], f2[:, :4], rtol=1e-13, atol=1e-13)
+    # the internal-energy feature cancels O(E^2) terms down to O(rho eps E):
+    # scaling changes its rounding, not its value
+    np.testing.assert_allclose(f1[:, 4], f2[:, 4], rtol=0, atol=1e-8)
