@@ -159,6 +159,16 @@ static pb_status enqueue_fv(pb_batch *b, double cfl, double dt_fixed, int n, hip
     return PB_OK;
 }
 
+// dt of the linear system: its largest speeds are the spectral radii rho_d
+// of B_d (part of the PDE parameters), so dt = cfl / sum_d (rho_d / dx_min)
+static double fd_dt(const pb_batch *b, double cfl, double dt_fixed)
+{
+    if (dt_fixed > 0.0) return dt_fixed;
+    double den = 0.0;
+    for (int d = 0; d < b->dim; ++d) den += b->params[d] / b->dxmin;
+    return cfl / den;
+}
+
 static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sigma, int rk, int n,
                             hipStream_t s, int *cur_io)
 {
@@ -166,19 +176,21 @@ static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sig
     pb_status st;
     const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
     void *yA = b->ws + L.yA, *yB = b->ws + L.yB;
-    if (!(dt_fixed > 0.0))
-        if ((st = launch_fd_lambda(b, cfl, s)) != PB_OK) return st;
+    const double dt = fd_dt(b, cfl, dt_fixed);
     for (int i = 0; i < n; ++i) {
         void *q0 = b->state[cur], *acc = b->state[cur ^ 1];
+        if ((st = launch_fd_reset(b, s)) != PB_OK) return st;
         if (rk == 1) {
-            if ((st = launch_fd_stage(b, 0, 1, q0, q0, nullptr, acc, 0, dt_fixed, sigma, s)) != PB_OK) return st;
+            if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
+            if ((st = launch_fd_stage(b, 0, 1, q0, q0, nullptr, acc, dt, sigma, s)) != PB_OK) return st;
+            if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
         } else {
             // stage 1 reads Q^n, stages 2-4 read the previous stage value
             void *ys[4] = {q0, yA, yB, yA};
             void *yn[4] = {yA, yB, yA, nullptr};
             for (int sg = 0; sg < 4; ++sg) {
                 if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
-                if ((st = launch_fd_stage(b, sg, 4, q0, ys[sg], yn[sg], acc, 0, dt_fixed, sigma, s)) != PB_OK)
+                if ((st = launch_fd_stage(b, sg, 4, q0, ys[sg], yn[sg], acc, dt, sigma, s)) != PB_OK)
                     return st;
                 if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
             }
@@ -284,6 +296,8 @@ pb_status patch_batch_destroy(pb_batch *b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     (void)hipFree(b->d_patches);
     (void)hipFree(b->d_order);
+    if (b->d_fd_items) (void)hipFree(b->d_fd_items);
+    if (b->d_fd_B) (void)hipFree(b->d_fd_B);
     delete b;
     return PB_OK;
 }
@@ -474,10 +488,13 @@ pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko, 
         for (int f = 0; f < 6; ++f)
             if (b->nbr[(size_t)k * 6 + f] != k) { set_error("fd_ko_step: patches must be periodic on themselves"); return PB_EUNSUPPORTED; }
     }
-    if (n_steps == 0) return finish_call(b, 0, dt_fixed, dt_last_host);
-    pb_status st = run_steps(b, 1, cfl, dt_fixed, sigma_ko, rk_stages, n_steps, use_graph);
+    const double dt = fd_dt(b, cfl, dt_fixed);
+    if (n_steps == 0) return finish_call(b, 0, dt, dt_last_host);
+    pb_status st = fd_prepare(b);
     if (st != PB_OK) return st;
-    return finish_call(b, n_steps, dt_fixed, dt_last_host);
+    st = run_steps(b, 1, cfl, dt_fixed, sigma_ko, rk_stages, n_steps, use_graph);
+    if (st != PB_OK) return st;
+    return finish_call(b, n_steps, dt, dt_last_host);
 }
 
 }  // extern "C"

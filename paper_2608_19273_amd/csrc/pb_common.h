@@ -40,7 +40,8 @@ struct Ctrl {
     unsigned int c2p_maxit;
     unsigned int pad0;
     double last_dt;
-    unsigned long long pad[19];
+    unsigned int fdq[4];                // FD work-list heads, one per RK stage
+    unsigned long long pad[17];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
@@ -108,6 +109,11 @@ struct pb_batch {
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
     bool pres_valid = false;         // SRHD: the workspace holds a previous pressure
+    // FD: tile work list (largest patches first) and the B_d matrices
+    bool fd_ready = false;
+    void *d_fd_items = nullptr;
+    int fd_n_items = 0;
+    double *d_fd_B = nullptr;
     // graph cache
     struct GraphEntry {
         int kind, n_steps, parity_cur;
@@ -144,9 +150,10 @@ pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, 
 pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt, double cfl,
                           hipStream_t s);
 pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y,
-                          void *ynext, void *acc, int slot, double dt_fixed, double sigma,
-                          hipStream_t s);
-pb_status launch_fd_lambda(pb_batch *b, double cfl, hipStream_t s);
+                          void *ynext, void *acc, double dt, double sigma, hipStream_t s);
+pb_status launch_fd_reset(pb_batch *b, hipStream_t s);
+// uploads the FD work list and B_d (library-owned; done once, before any capture)
+pb_status fd_prepare(pb_batch *b);
 pb_status launch_ctrl_init(pb_batch *b, hipStream_t s);
 pb_status launch_dt_reduce(pb_batch *b, const double *part, int n_units, int dim, int slot, double cfl, bool want_dt,
                            bool want_stats, hipStream_t s);

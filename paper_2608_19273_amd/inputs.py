@@ -347,28 +347,41 @@ def config2_sizes(seed: int = 2, n_patches: int = 4096):
     return sizes
 
 
-def linsym_patch_ic(seed: int, k: int, p: int, N: int, n_modes: int = 4) -> np.ndarray:
-    """[N, p, p, p] IC of patch k: per unknown sum of n_modes terms
-    a sin(2 pi k.x + phi), k in {-1,0,1}^3 minus 0, a ~ U(-1/4, 1/4), on the
-    unit cube sampled at cell centres."""
+def _linsym_modes(seed: int, k: int, N: int, n_modes: int):
+    """mode parameters of patch k: complex amplitudes a e^{i phi} [N, m] and
+    wave vectors (kx, ky, kz) [N, m] in {-1,0,1}^3 minus 0, a ~ U(-1/4, 1/4)"""
     s = substream(seed, 1000 + k)
     r = uniform(s, N * n_modes * 3).reshape(N, n_modes, 3)
     kk = (splitmix64(substream(s, 5), N * n_modes) % np.uint64(26)).astype(np.int64).reshape(N, n_modes)
     kk = np.where(kk >= 13, kk + 1, kk)  # skip (0,0,0), index 13 of 27
-    kx = kk % 3 - 1
-    ky = (kk // 3) % 3 - 1
-    kz = kk // 9 - 1
+    amp = (-0.25 + 0.5 * r[:, :, 0]) * np.exp(1j * 2 * np.pi * r[:, :, 1])
+    return amp, kk % 3 - 1, (kk // 3) % 3 - 1, kk // 9 - 1
+
+
+def linsym_patches_ic(seed: int, ks, p: int, N: int, n_modes: int = 4) -> np.ndarray:
+    """[len(ks), N, p, p, p] IC of patches ks (all of size p): per unknown the
+    sum of n_modes terms a sin(2 pi k.x + phi) on the unit cube at cell centres,
+    evaluated separably as Im(a e^{i phi} e^{2 pi i kz z} e^{2 pi i ky y} e^{2 pi i kx x})."""
+    import torch  # multithreaded elementwise products on the host
     x = (np.arange(p) + 0.5) / p
-    out = np.zeros((N, p, p, p))
+    e = torch.from_numpy(np.exp(2j * np.pi * np.outer(np.arange(-1, 2), x)))  # e[k+1, i] = exp(2 pi i k x_i)
+    G = len(ks)
+    out = torch.zeros((G, N, p, p, p), dtype=torch.float64)
+    params = [_linsym_modes(seed, int(k), N, n_modes) for k in ks]
+    amp = torch.from_numpy(np.stack([q[0] for q in params]))            # [G, N, m]
+    kx = torch.from_numpy(np.stack([q[1] for q in params]) + 1)
+    ky = torch.from_numpy(np.stack([q[2] for q in params]) + 1)
+    kz = torch.from_numpy(np.stack([q[3] for q in params]) + 1)
     for m in range(n_modes):
-        a = -0.25 + 0.5 * r[:, m, 0]
-        phi = 2 * np.pi * r[:, m, 1]
-        ph = (phi[:, None, None, None]
-              + 2 * np.pi * kz[:, m, None, None, None] * x[None, :, None, None]
-              + 2 * np.pi * ky[:, m, None, None, None] * x[None, None, :, None]
-              + 2 * np.pi * kx[:, m, None, None, None] * x[None, None, None, :])
-        out += a[:, None, None, None] * np.sin(ph)
-    return out
+        az = amp[:, :, m, None] * e[kz[:, :, m]]     # [G, N, p]
+        exy = e[ky[:, :, m]][:, :, :, None] * e[kx[:, :, m]][:, :, None, :]   # [G, N, p, p]
+        out += torch.imag(az[:, :, :, None, None] * exy[:, :, None, :, :])
+    return out.numpy()
+
+
+def linsym_patch_ic(seed: int, k: int, p: int, N: int, n_modes: int = 4) -> np.ndarray:
+    """[N, p, p, p] IC of patch k (see linsym_patches_ic)"""
+    return linsym_patches_ic(seed, [k], p, N, n_modes)[0]
 
 
 def config2(seed: int = 2, n_patches: int = 4096, subset=None, N: int = 58,
@@ -383,10 +396,19 @@ def config2(seed: int = 2, n_patches: int = 4096, subset=None, N: int = 58,
     ps = sizes[idx].astype(np.int32)
     K = len(ps)
     Bs, rhos = linsym_matrices(seed, N)
-    parts = [linsym_patch_ic(seed, int(k), int(p), N).reshape(-1) for k, p in zip(idx, ps)]
+    C = ps.astype(np.int64) ** 3
+    off = np.concatenate([[0], np.cumsum(C)]) * N
+    state = np.empty(int(off[-1]))
+    for p in np.unique(ps):
+        pos = np.nonzero(ps == p)[0]
+        step = max(1, 65536 // int(p) ** 3)
+        for c0 in range(0, len(pos), step):
+            chunk = pos[c0:c0 + step]
+            blocks = linsym_patches_ic(seed, idx[chunk], int(p), N)
+            for j, blk in zip(chunk, blocks):
+                state[off[j]:off[j + 1]] = blk.reshape(-1)
     return Batch(dim=3, p=ps, dx=1.0 / ps.astype(np.float64), nbr=self_periodic(K, 3), halo=h,
-                 pde="linsym", params=linsym_params(Bs, rhos), n_unknowns=N,
-                 state=np.concatenate(parts))
+                 pde="linsym", params=linsym_params(Bs, rhos), n_unknowns=N, state=state)
 
 
 def config2_subset(seed: int = 2, n_per_size=(16, 16, 16)):
