@@ -1,16 +1,22 @@
 #!/usr/bin/env python3
 """Throughput of the patch-batch hot path on one MI355X.
 
-Default workload: 3D compressible Euler (gamma 1.4), 2048 patches of 16^3
-cells (8,388,608 cells, 16x16x8 periodic patch grid), halo 1, first-order
-Rusanov finite volumes with explicit Euler at CFL 0.4, FP64 state, smooth
-seeded IC (sum of 8 random Fourier modes per primitive).  A step is one full
-pass of the fused FV kernel (halo gather, per-cell primitives, face fluxes,
-update, and the CFL reduction that yields the next dt on the device).
+Headline workload (the `value` of the JSON line): 3D compressible Euler
+(gamma 1.4), 2048 patches of 16^3 cells (8,388,608 cells, 16x16x8 periodic
+patch grid), halo 1, first-order Rusanov finite volumes with explicit Euler
+at CFL 0.4, FP64 state, smooth seeded IC (sum of 8 random Fourier modes per
+primitive).  A step is one full pass of the fused FV kernel (halo gather,
+per-cell primitives, face fluxes, update, the largest-speed partials of the
+new state) plus the one-work-group reduction that turns them into the next
+dt on the device.  State is resident in HBM for the whole timed region.
 
-Prints one JSON line: cell-updates/s over the timed steps (state resident in
-HBM), the roofline of the dominant kernel from live HIP-event timing, and the
-single-threaded CPU oracle timed on a bounded sample of the same workload.
+Further workloads are reported under "workloads": the same Euler batch with
+FP32 storage, the 2D Euler entropy wave (64x64 as 8x8 patches of 8^2) eager
+and graph-replayed, the uneven 4096-patch batch of the 58-unknown linear
+system (FD4 + KO6 + RK4, FP64 matrix cores), and special-relativistic
+hydrodynamics on 2048 x 16^3 with the plain, warm and learned con2prim guess.
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -27,23 +33,24 @@ if ROOT not in sys.path:
 
 METRIC = "cell-updates/s & % HBM roofline; SRHD step learned vs plain con2prim"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(files) -> str:
     h = hashlib.sha256()
-    for f in ("pb_fv.hip", "pb_physics.h", "pb_common.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2608_19273_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def load_traffic(name: str, sha: str, launches_bytes_scale=1.0):
-    """HBM bytes per launch of the FV kernel from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+def load_traffic(name: str, sha: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -57,9 +64,24 @@ def load_traffic(name: str, sha: str, launches_bytes_scale=1.0):
     return d.get("hbm_bytes_per_launch")
 
 
+def timed(torch, fn):
+    """seconds taken by fn() (which enqueues GPU work), max of wall clock and
+    events on the current stream, synchronised on both sides"""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    fn()
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return max(wall, e0.elapsed_time(e1) / 1e3)
+
+
 def cpu_baseline(target_s: float):
     """The oracle (single-threaded FP64 C) on a bounded sample of the
-    workload: the same IC recipe on 4x4x4 patches of 16^3."""
+    headline workload: the same IC recipe on 4x4x4 patches of 16^3."""
     import oracle
     from paper_2608_19273_amd import inputs as I
     b = I.config1(grid=(4, 4, 4))
@@ -77,104 +99,173 @@ def cpu_baseline(target_s: float):
                       f"{steps} steps, {el:.1f} s, single thread"}
 
 
+def attainable_copy(torch, pb):
+    """the library's streaming copy, 512 MiB read + 512 MiB written per launch"""
+    src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    pb.pb_stream_copy(src, dst)
+    reps = 5
+    el = timed(torch, lambda: [pb.pb_stream_copy(src, dst) for _ in range(reps)])
+    return 2 * src.numel() * 8 * reps / el / 1e9
+
+
+def bench_euler3d(torch, pb, b, storage, steps, warmup):
+    B = pb.PatchBatch(b, storage=storage)
+    B.fv_rusanov_step(cfl=0.4, n_steps=warmup)
+    B.profile(True)
+    el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.4, n_steps=steps))
+    kern_ms, launches = B.profile_read()
+    B.profile(False)
+    st = B.stats()
+    B.close()
+    cells = b.total_cells
+    es = 8 if storage == "fp64" else 4
+    bpc = 2 * b.n_unknowns * es
+    avg_s = kern_ms / 1e3 / max(launches, 1)
+    return {"cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
+            "kernel_avg_us": avg_s * 1e6, "launches": launches, "bytes_per_cell": bpc,
+            "kernel_GBs": cells * bpc / avg_s / 1e9, "nonfinite_units": st["nonfinite_units"]}
+
+
+def bench_config0(torch, pb, I, calls):
+    b = I.config0()
+    out = {}
+    for graph in (False, True):
+        B = pb.PatchBatch(b)
+        B.fv_rusanov_step(cfl=0.4, n_steps=10, use_graph=graph)
+        el = timed(torch, lambda: [B.fv_rusanov_step(cfl=0.4, n_steps=10, use_graph=graph)
+                                   for _ in range(calls)])
+        B.close()
+        out["graph" if graph else "eager"] = {"cell_updates_per_s": b.total_cells * 10 * calls / el,
+                                              "us_per_step": el * 1e6 / (10 * calls)}
+    return out
+
+
+def bench_fd(torch, pb, I, steps, warmup):
+    log("config-2 IC (4096 patches, 58 unknowns)")
+    b = I.config2()
+    cells = b.total_cells
+    B = pb.PatchBatch(b)
+    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=warmup)
+    B.profile(True)
+    el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
+    kern_ms, launches = B.profile_read()
+    B.profile(False)
+    B.close()
+    N = b.n_unknowns
+    # per RK4 step: 4 x (3 dense N x N products + 3 D4 (4 flop) + 3 KO6 (9 flop) + update) per unknown
+    flop_cell = 4 * (3 * 2 * N * N + N * (3 * 4 + 3 * 9 + 4))
+    bytes_cell = 16 * N * 8
+    step_kernel_s = kern_ms / 1e3 / max(launches, 1) * 4
+    return {"workload": "linear symmetric system N=58, 4096 patches {4^3,8^3,16^3} 1:2:1 shuffled "
+                        f"({cells} cells), FD4 + KO6 (sigma 0.1) + RK4, CFL 0.5, FP64",
+            "cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
+            "stage_kernel_avg_us": kern_ms * 1e3 / max(launches, 1),
+            "hbm_frac": cells * bytes_cell / step_kernel_s / 1e9 / HBM_PEAK_GBS,
+            "fp64_frac": cells * flop_cell / step_kernel_s / 1e12 / FP64_PEAK_TFLOPS,
+            "algorithmic_bytes_per_cell_step": bytes_cell, "algorithmic_flop_per_cell_step": flop_cell}
+
+
+def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
+    from paper_2608_19273_amd import mlp_train
+    log("config-3 IC (SRHD, 2048 x 16^3)")
+    b = I.config3()
+    cells = b.total_cells
+    res = {"workload": "3D SRHD Gamma 5/3, 2048 patches of 16^3, Rusanov FV, CFL 0.4, FP64; i.i.d. primitives "
+                       "rho, eps log-uniform [1e-3,10], W uniform [1,10]; con2prim tol 1e-12, max 50 iterations"}
+    log(f"training the guess network ({mlp_pairs} pairs, {mlp_epochs} epochs)")
+    t0 = time.perf_counter()
+    net, hist = mlp_train.train(n_pairs=mlp_pairs, epochs=mlp_epochs, batch=8192)
+    torch.cuda.synchronize()
+    res["mlp_training"] = {"seconds": time.perf_counter() - t0, "steps": hist["steps"],
+                           "final_epoch_loss": hist["epoch_loss"][-1]}
+    for guess in ("plain", "warm", "learned"):
+        B = pb.PatchBatch(b)
+        if guess != "plain":
+            B.set_c2p_guess(guess, net if guess == "learned" else None)
+        B.fv_rusanov_step(cfl=0.4, n_steps=1)   # warm-up (and the first pressure for the warm start)
+        st0 = B.stats()
+        el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.4, n_steps=steps))
+        st = B.stats()
+        B.close()
+        solves = st["c2p_cells"] - st0["c2p_cells"]
+        res[guess] = {"cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
+                      "newton_iterations_mean": (st["c2p_iterations"] - st0["c2p_iterations"]) / max(solves, 1),
+                      "newton_iterations_max": st["c2p_max_iterations"],
+                      "c2p_failures": st["c2p_failures"] - st0["c2p_failures"],
+                      "fallbacks": st["c2p_fallbacks"] - st0["c2p_fallbacks"]}
+    res["learned_over_plain_speedup"] = res["learned"]["cell_updates_per_s"] / res["plain"]["cell_updates_per_s"]
+    net.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--storage", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--slab", type=int, default=0, help="FV z-planes per work-group (0 = library default)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
+    ap.add_argument("--mlp-epochs", type=int, default=20)
+    ap.add_argument("--mlp-pairs", type=int, default=1 << 22)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; there is no multi-GPU path (--gpus must be 1)"}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import paper_2608_19273_amd as pb
     from paper_2608_19273_amd import inputs as I
 
-    log("building IC")
-    b = I.config1(seed=1)
-    cells = b.total_cells
-    log(f"IC ready: {cells} cells")
-    B = pb.PatchBatch(b, storage=args.storage)
-    if args.slab:
-        B.set_tuning(fv_slab=args.slab)
-    B.fv_rusanov_step(cfl=0.4, n_steps=args.warmup)
-    torch.cuda.synchronize()
-    log("warmup done")
-
-    B.profile(True)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    B.fv_rusanov_step(cfl=0.4, n_steps=args.steps)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = e0.elapsed_time(e1)
-    kern_ms, launches = B.profile_read()
-    B.profile(False)
-    st = B.stats()
-    log(f"timed {args.steps} steps: {gpu_ms:.3f} ms (events), {wall * 1e3:.3f} ms (wall)")
-
-    elapsed = max(wall, gpu_ms / 1e3)
-    value = cells * args.steps / elapsed
-    es = 8 if args.storage == "fp64" else 4
-    bytes_per_cell = 2 * b.n_unknowns * es
-    avg_kernel_s = kern_ms / 1e3 / max(launches, 1)
-    achieved = cells * bytes_per_cell / avg_kernel_s / 1e9
-    sha = kernel_source_sha()
-    traffic = load_traffic(f"fv_euler3d_2048x16c_{args.storage}_traffic.json", sha)
+    log("config-1 IC (3D Euler, 2048 x 16^3)")
+    b1 = I.config1(seed=1)
+    cells = b1.total_cells
+    log("headline: 3D Euler FP64")
+    h = bench_euler3d(torch, pb, b1, "fp64", args.steps, args.warmup)
+    copy_gbs = attainable_copy(torch, pb)
+    sha = kernel_source_sha(("pb_fv.hip", "pb_physics.h", "pb_common.h"))
+    traffic = load_traffic("fv_euler3d_2048x16c_fp64_traffic.json", sha)
+    achieved = h["kernel_GBs"]
     result = {
         "metric": METRIC,
-        "value": value,
+        "value": h["cell_updates_per_s"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == "fp64" else "f64 arithmetic, f32 storage",
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "3D Euler, Rusanov FV + explicit Euler, 2048 patches of 16^3 (8,388,608 cells), "
-                               f"halo 1, CFL 0.4, {args.storage.upper()} state, seeded Fourier-mode IC",
-                   "patches": b.K, "patch_cells": int(b.p[0]) ** 3, "storage": args.storage},
+                               "halo 1, CFL 0.4, FP64 state, seeded Fourier-mode IC",
+                   "patches": b1.K, "patch_cells": int(b1.p[0]) ** 3, "storage": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fv_step_kernel<Euler<3>>", "avg_launch_us": avg_kernel_s * 1e6,
-                     "launches": launches, "algorithmic_bytes_per_launch": cells * bytes_per_cell,
+                     "kernel": "fv_step_kernel<Euler<3>, 3, double, true>", "avg_launch_us": h["kernel_avg_us"],
+                     "launches": h["launches"], "algorithmic_bytes_per_launch": cells * h["bytes_per_cell"],
+                     "attainable_copy_GBs": copy_gbs, "frac_of_attainable": achieved / copy_gbs,
                      "kernel_source_sha": sha},
-        "nonfinite_units": st["nonfinite_units"],
+        "nonfinite_units": h["nonfinite_units"],
     }
-    B.close()
-    # attainable streaming bandwidth: the library's plain copy kernel, 512 MiB
-    # read + 512 MiB written per launch (also the known-traffic reference for
-    # the profiler's byte counters)
-    src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
-    dst = torch.empty_like(src)
-    pb.pb_stream_copy(src, dst)
-    torch.cuda.synchronize()
-    c0 = torch.cuda.Event(enable_timing=True)
-    c1 = torch.cuda.Event(enable_timing=True)
-    reps = 5
-    c0.record()
-    for _ in range(reps):
-        pb.pb_stream_copy(src, dst)
-    c1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 8 * reps / (c0.elapsed_time(c1) / 1e3) / 1e9
-    result["roofline"]["attainable_copy_GBs"] = copy_gbs
-    result["roofline"]["frac_of_attainable"] = achieved / copy_gbs
-    del src, dst
+    if not args.only_headline:
+        wl = {}
+        log("3D Euler FP32 storage")
+        f32 = bench_euler3d(torch, pb, b1, "fp32", args.steps, args.warmup)
+        f32["hbm_frac"] = f32["kernel_GBs"] / HBM_PEAK_GBS
+        wl["euler3d_fp32_storage"] = f32
+        del b1
+        log("2D Euler entropy wave")
+        wl["euler2d_64x64_config0"] = bench_config0(torch, pb, I, 10)
+        log("FD4 + KO6 + RK4, 58 unknowns")
+        wl["linsym58_fd4_rk4"] = bench_fd(torch, pb, I, max(2, args.steps // 4), 1)
+        log("SRHD plain / warm / learned con2prim")
+        wl["srhd"] = bench_srhd(torch, pb, I, max(2, args.steps // 2), args.mlp_epochs, args.mlp_pairs)
+        result["workloads"] = wl
     if not args.no_cpu:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
