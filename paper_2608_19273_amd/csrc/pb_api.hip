@@ -32,7 +32,8 @@ WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K)
     o += sizeof(Ctrl);
     o = align256(o);
     L.part = o;
-    o = align256(o + (size_t)8 * (size_t)max_units(K) * sizeof(double));
+    // [8][units] partials, then [8][units / 2048 + 1] for the second reduction stage
+    o = align256(o + (size_t)8 * ((size_t)max_units(K) + (size_t)max_units(K) / 2048 + 1) * sizeof(double));
     if (pde == PB_PDE_SRHD) {
         L.pres = o;
         o = align256(o + (size_t)total_cells * sizeof(double));

@@ -27,6 +27,8 @@
 
 namespace pb {
 
+constexpr int kReduceSpan = 2048;   // units per work-group of the first reduction stage
+
 namespace {
 
 template <class Ph, typename T>
@@ -406,6 +408,38 @@ __global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restric
     }
 }
 
+// first stage of the partial reduction: work-group g folds units
+// [g*kReduceSpan, (g+1)*kReduceSpan) of every row (max for rows 0-2 and 5,
+// sum otherwise) into out[r * n_out + g]
+__global__ __launch_bounds__(256) void partial_reduce_kernel(const double *__restrict__ part, int n_units, int rows,
+                                                             int dim, double *__restrict__ out, int n_out)
+{
+    __shared__ double red[256 / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+    const int u0 = blockIdx.x * kReduceSpan, u1 = min(n_units, u0 + kReduceSpan);
+    for (int r = 0; r < rows; ++r) {
+        if (r >= dim && r < 3) continue;
+        const bool mx = r < 3 || r == 5;
+        double m = 0.0;
+        for (int i = u0 + t; i < u1; i += 256) {
+            const double v = part[(long long)r * n_units + i];
+            m = mx ? fmax(m, v) : m + v;
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double u = __shfl_xor(m, o, kWave);
+            m = mx ? fmax(m, u) : m + u;
+        }
+        if (lane == 0) red[w] = m;
+        __syncthreads();
+        if (t == 0) {
+            double a = red[0];
+            for (int i = 1; i < 256 / kWave; ++i) a = mx ? fmax(a, red[i]) : a + red[i];
+            out[(long long)r * n_out + blockIdx.x] = a;
+        }
+        __syncthreads();
+    }
+}
+
 __global__ void ctrl_init_kernel(Ctrl *ctrl)
 {
     // zero the whole control block with vector stores (no memset node, so
@@ -535,6 +569,17 @@ pb_status launch_dt_reduce(pb_batch *b, const double *part, int n_units, int dim
                            bool want_stats, hipStream_t s)
 {
     if (!want_dt && !want_stats) return PB_OK;
+    const int rows = want_stats ? 8 : dim;
+    if (n_units > kReduceSpan) {
+        // first stage: one work-group per kReduceSpan units, partials of the
+        // partials into the tail of the partial buffer
+        const int g = (n_units + kReduceSpan - 1) / kReduceSpan;
+        double *part2 = const_cast<double *>(part) + (size_t)8 * max_units(b->K);
+        hipLaunchKernelGGL(partial_reduce_kernel, dim3(g), dim3(256), 0, s, part, n_units, rows, dim, part2, g);
+        PB_HIP(hipGetLastError());
+        part = part2;
+        n_units = g;
+    }
     hipLaunchKernelGGL(dt_reduce_kernel, dim3(1), dim3(1024), 0, s, part, n_units, dim, reinterpret_cast<Ctrl *>(b->ws),
                        slot, cfl, b->dxmin, want_dt ? 1 : 0, want_stats ? 1 : 0);
     PB_HIP(hipGetLastError());

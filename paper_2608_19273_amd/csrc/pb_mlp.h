@@ -41,12 +41,11 @@ struct MlpDev {
     const float *norm;    // normalisation block
 };
 
+// round to nearest even to bfloat16 (gfx950 converts in hardware,
+// v_cvt_pk_bf16_f32, under the default round-to-nearest-even mode)
 __device__ __forceinline__ unsigned short bf16_rne(float f)
 {
-    unsigned u = __float_as_uint(f);
-    if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)0x7fc0;  // NaN stays NaN
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+    return __builtin_bit_cast(unsigned short, (__bf16)f);
 }
 
 __device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
@@ -55,15 +54,17 @@ __device__ __forceinline__ float bf16_val(unsigned short h) { return __uint_as_f
 // |S|/E).  The last one measures the internal energy directly:
 // E^2 - D^2 - |S|^2 = tau (tau + 2D) - |S|^2, positive for admissible
 // states, is where the pressure of a cold, fast cell hides.
+// The ratios (and the cancelling difference) are formed in FP64, the
+// logarithms in FP32: the network reads bf16 inputs.
 __device__ __forceinline__ void mlp_features(const C2pIn &in, float *x)
 {
     const double iE = 1.0 / in.E;
     const double sE = sqrt(in.s2) * iE;
-    x[0] = (float)log(in.D * iE);
+    x[0] = __logf((float)(in.D * iE));
     x[1] = (float)sE;
-    x[2] = (float)log(1.0 - sE);
-    x[3] = (float)log(in.tau * iE);
-    x[4] = (float)log((in.tau * (in.tau + 2.0 * in.D) - in.s2) * iE * iE);
+    x[2] = __logf((float)(1.0 - sE));
+    x[3] = __logf((float)(in.tau * iE));
+    x[4] = __logf((float)((in.tau * (in.tau + 2.0 * in.D) - in.s2) * iE * iE));
 }
 
 // standardised, bf16-rounded features
@@ -73,31 +74,47 @@ __device__ __forceinline__ void mlp_inputs(const float *norm, const float *x, un
     for (int k = 0; k < kMlpIn; ++k) xb[k] = bf16_rne((x[k] - norm[k]) / norm[5 + k]);
 }
 
-// Whole-wave call (every lane of the wave must call it; lanes without a cell
-// pass admissible dummy features).  x: this lane's raw features.  Returns the
-// network output yhat (standardised log(p/E)).
-__device__ __forceinline__ float mlp_yhat(const MlpDev &m, const float *x)
-{
-    const int l = threadIdx.x & 63, g = l >> 4, j = l & 15;
-    unsigned short xb[kMlpIn];
-    mlp_inputs(m.norm, x, xb);
-    const int pk01 = (int)xb[0] | ((int)xb[1] << 16);
-    const int pk23 = (int)xb[2] | ((int)xb[3] << 16);
-    const int pk4 = (int)xb[4];
-
+// The parameters one lane needs, held in registers so that a wave can push
+// several groups of 64 cells through the network with one load: the layer-1
+// and layer-2 A operands of its lane, and the biases and w3 of the 16 hidden
+// rows its lane group owns.
+struct MlpRegs {
     bf16x4_t w1[4];
+    bf16x4_t w2[16];
+    float b1[4][4], b2[4][4], w3[4][4];
+    float b3;
+};
+
+__device__ __forceinline__ void mlp_load(const MlpDev &m, MlpRegs &r)
+{
+    const int l = threadIdx.x & 63, g = l >> 4;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) w1[mt] = m.w1[mt * 64 + l];
-    float b1r[4][4], b2r[4][4], w3r[4][4];
+    for (int mt = 0; mt < 4; ++mt) r.w1[mt] = m.w1[mt * 64 + l];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) r.w2[t] = m.w2[t * 64 + l];
 #pragma unroll
     for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int row = mt * 16 + g * 4 + i;
-            b1r[mt][i] = m.par[kOffB1 + row];
-            b2r[mt][i] = m.par[kOffB2 + row];
-            w3r[mt][i] = bf16_val(bf16_rne(m.par[kOffW3 + row]));
+            r.b1[mt][i] = m.par[kOffB1 + row];
+            r.b2[mt][i] = m.par[kOffB2 + row];
+            r.w3[mt][i] = bf16_val(bf16_rne(m.par[kOffW3 + row]));
         }
+    r.b3 = m.par[kOffB3];
+}
+
+// Whole-wave call (every lane of the wave must call it; lanes without a cell
+// pass admissible dummy features).  x: this lane's raw features.  Returns the
+// network output yhat (standardised log(p/E)).
+__device__ __forceinline__ float mlp_yhat(const MlpRegs &r, const float *norm, const float *x)
+{
+    const int l = threadIdx.x & 63, g = l >> 4, j = l & 15;
+    unsigned short xb[kMlpIn];
+    mlp_inputs(norm, x, xb);
+    const int pk01 = (int)xb[0] | ((int)xb[1] << 16);
+    const int pk23 = (int)xb[2] | ((int)xb[3] << 16);
+    const int pk4 = (int)xb[4];
 
     float part[4];
 #pragma unroll
@@ -118,9 +135,9 @@ __device__ __forceinline__ float mlp_yhat(const MlpDev &m, const float *x)
 #pragma unroll
         for (int mt = 0; mt < 4; ++mt) {
             const f32x4_t z = {0.f, 0.f, 0.f, 0.f};
-            const f32x4_t h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w1[mt], bx, z, 0, 0, 0);
+            const f32x4_t h = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w1[mt], bx, z, 0, 0, 0);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) hb[mt][i] = (short)bf16_rne(fmaxf(h[i] + b1r[mt][i], 0.f));
+            for (int i = 0; i < 4; ++i) hb[mt][i] = (short)bf16_rne(fmaxf(h[i] + r.b1[mt][i], 0.f));
         }
         float acc = 0.f;
 #pragma unroll
@@ -128,34 +145,40 @@ __device__ __forceinline__ float mlp_yhat(const MlpDev &m, const float *x)
             f32x4_t d = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt)
-                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(m.w2[(mt * 4 + kt) * 64 + l], hb[kt], d, 0, 0, 0);
+                d = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(r.w2[mt * 4 + kt], hb[kt], d, 0, 0, 0);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float h2 = bf16_val(bf16_rne(fmaxf(d[i] + b2r[mt][i], 0.f)));
-                acc = fmaf(w3r[mt][i], h2, acc);
+                const float h2 = bf16_val(bf16_rne(fmaxf(d[i] + r.b2[mt][i], 0.f)));
+                acc = fmaf(r.w3[mt][i], h2, acc);
             }
         }
         acc += __shfl_xor(acc, 16, 64);
         acc += __shfl_xor(acc, 32, 64);
         part[nt] = acc;
     }
-    return m.par[kOffB3] + (g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3]);
+    return r.b3 + (g == 0 ? part[0] : g == 1 ? part[1] : g == 2 ? part[2] : part[3]);
+}
+
+__device__ __forceinline__ float mlp_yhat(const MlpDev &m, const float *x)
+{
+    MlpRegs r;
+    mlp_load(m, r);
+    return mlp_yhat(r, m.norm, x);
 }
 
 // Whole-wave call.  The learned pressure guess E exp(y_mean + y_std yhat)
 // (the solver replaces a guess outside its bracket by the plain guess).
-__device__ __forceinline__ double mlp_guess(const MlpDev &m, const double *qv, const C2pIn &in)
+__device__ __forceinline__ double mlp_guess(const MlpRegs &r, const float *norm, const C2pIn &in)
 {
-    (void)qv;
     float x[kMlpIn];
     if (in.ok) {
         mlp_features(in, x);
     } else {
 #pragma unroll
-        for (int k = 0; k < kMlpIn; ++k) x[k] = m.norm[k];
+        for (int k = 0; k < kMlpIn; ++k) x[k] = norm[k];
     }
-    const float yhat = mlp_yhat(m, x);
-    return in.E * exp((double)m.norm[10] + (double)m.norm[11] * (double)yhat);
+    const float yhat = mlp_yhat(r, norm, x);
+    return in.E * (double)__expf(norm[10] + norm[11] * yhat);
 }
 
 }  // namespace pb

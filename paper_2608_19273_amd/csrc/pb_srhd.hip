@@ -80,8 +80,8 @@ __global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
     }
     const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
     double p0 = in.hi;
-    if (GUESS == 2 && active) p0 = pres[P.off + c];
-    if (GUESS == 1) p0 = mlp_guess(mlp, qv, in);   // all lanes: the MLP runs on whole waves
+    // warm: previous pressure; learned: the guess the network pass stored
+    if (GUESS != 0 && active) p0 = pres[P.off + c];
     if (active) {
         C2pOut o = c2p_solve(in, gam, tol, maxit, p0);
         if (GUESS != 0 && o.status == C2P_NOTCONV) {
@@ -111,11 +111,73 @@ __global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
     }
 }
 
+// Learned guesses: each wave loads the network once and pushes
+// kGuessGroups groups of 64 cells through it (a work-group covers
+// 256 * kGuessGroups cells).
+constexpr int kGuessGroups = 4;
+
+__device__ __forceinline__ double guess_of(const MlpRegs &r, const float *norm, const double *qv, bool active,
+                                           double gam)
+{
+    const double d0[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+    const double *u = active ? qv : d0;
+    const C2pIn in = c2p_setup(u[0], u[1], u[2], u[3], u[4], gam);
+    return mlp_guess(r, norm, in);
+}
+
+// p0 of every cell of the SRHD pass into `pres`
+__global__ __launch_bounds__(kC2pThreads) void srhd_guess_kernel(const double *__restrict__ q,
+                                                                 double *__restrict__ pres,
+                                                                 const PatchDev *__restrict__ patches, int gchunks,
+                                                                 double gam, MlpDev mlp)
+{
+    const int unit = blockIdx.x;
+    const int k = unit / gchunks, ch = unit - k * gchunks;
+    const PatchDev P = patches[k];
+    const long long C = (long long)P.p * P.p * P.p;
+    MlpRegs r;
+    mlp_load(mlp, r);
+#pragma unroll 1
+    for (int gi = 0; gi < kGuessGroups; ++gi) {
+        const long long c = ((long long)ch * kGuessGroups + gi) * kC2pThreads + threadIdx.x;
+        const bool active = c < C;
+        double qv[5];
+        if (active) {
+            const double *base = q + P.off * 5 + c;
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qv[v] = base[(long long)v * C];
+        }
+        const double g = guess_of(r, mlp.norm, qv, active, gam);
+        if (active) pres[P.off + c] = g;
+    }
+}
+
+// learned guesses for the standalone entry point, into p0[n]
+__global__ __launch_bounds__(kC2pThreads) void flat_guess_kernel(const double *__restrict__ cons,
+                                                                 double *__restrict__ p0, long long n, double gam,
+                                                                 MlpDev mlp)
+{
+    MlpRegs r;
+    mlp_load(mlp, r);
+#pragma unroll 1
+    for (int gi = 0; gi < kGuessGroups; ++gi) {
+        const long long i = ((long long)blockIdx.x * kGuessGroups + gi) * kC2pThreads + threadIdx.x;
+        const bool active = i < n;
+        double qv[5];
+        if (active) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qv[v] = cons[(long long)v * n + i];
+        }
+        const double g = guess_of(r, mlp.norm, qv, active, gam);
+        if (active) p0[i] = g;
+    }
+}
+
 // standalone con2prim over n cells of SoA arrays
 template <int GUESS>
 __global__ __launch_bounds__(kC2pThreads) void con2prim_kernel(
-    const double *__restrict__ cons, double *__restrict__ prim, long long n, double gam, double tol, int maxit,
-    const double *__restrict__ p_prev, int *__restrict__ iters, int *__restrict__ status,
+    const double *__restrict__ cons, double *prim, long long n, double gam, double tol, int maxit,
+    const double *p_prev, int *__restrict__ iters, int *__restrict__ status,
     unsigned long long *__restrict__ counters, MlpDev mlp)
 {
     const long long i = (long long)blockIdx.x * kC2pThreads + threadIdx.x;
@@ -127,8 +189,9 @@ __global__ __launch_bounds__(kC2pThreads) void con2prim_kernel(
     }
     const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
     double p0 = in.hi;
-    if (GUESS == 2 && active) p0 = p_prev[i];
-    if (GUESS == 1) p0 = mlp_guess(mlp, qv, in);
+    // warm: caller's previous pressures; learned: the guesses the network
+    // pass stored in prim[4]
+    if (GUESS != 0 && active) p0 = p_prev[i];
     C2pStats s = {{0.0, 0.0, 0.0}, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active) {
         C2pOut o = c2p_solve(in, gam, tol, maxit, p0);
@@ -190,6 +253,10 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
                            n_units, part, gam, tol, maxit, md);
         break;
     case PB_GUESS_LEARNED:
+        hipLaunchKernelGGL(srhd_guess_kernel, dim3(b->K * ((chunks + kGuessGroups - 1) / kGuessGroups)),
+                           dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, (chunks + kGuessGroups - 1) / kGuessGroups,
+                           gam, md);
+        PB_HIP(hipGetLastError());
         hipLaunchKernelGGL(srhd_c2p_kernel<1>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, chunks,
                            n_units, part, gam, tol, maxit, md);
         break;
@@ -239,8 +306,12 @@ extern "C" pb_status con2prim(const void *cons, void *prim, int64_t n, double ga
                            gamma, tol, max_iter, pp, it, stp, cnt, md);
         break;
     case PB_GUESS_LEARNED:
+        // guesses go to prim[4] (the pressure row), which the solve overwrites
+        hipLaunchKernelGGL(flat_guess_kernel, dim3((unsigned)((blocks + kGuessGroups - 1) / kGuessGroups)),
+                           dim3(kC2pThreads), 0, s, cd, pd + 4 * n, (long long)n, gamma, md);
+        PB_HIP(hipGetLastError());
         hipLaunchKernelGGL(con2prim_kernel<1>, dim3((unsigned)blocks), dim3(kC2pThreads), 0, s, cd, pd, (long long)n,
-                           gamma, tol, max_iter, pp, it, stp, cnt, md);
+                           gamma, tol, max_iter, pd + 4 * n, it, stp, cnt, md);
         break;
     default:
         hipLaunchKernelGGL(con2prim_kernel<2>, dim3((unsigned)blocks), dim3(kC2pThreads), 0, s, cd, pd, (long long)n,
