@@ -161,7 +161,8 @@ pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_st
  * persistent launch per stage sweeps all patches from a cost-ordered work
  * list.  dt as in fv_rusanov_step (Lambda_d = spectral radius of B_d).
  * Needs 2 extra state-sized buffers in the workspace.
- * Supported: LINSYM (N = 58, dim 3, halo >= 3, p in {4, 8, 16}), FP64.
+ * Supported: LINSYM (N <= 60; the workloads use N = 58), dim 3, halo >= 3,
+ * p in {4, 8, 16}, FP64; other N return PB_EUNSUPPORTED.
  */
 pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko,
                      int32_t rk_stages, int32_t n_steps, int32_t use_graph,
@@ -263,7 +264,8 @@ pb_status pb_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
 typedef struct {
     int32_t fv_slab;          /* FV: z-planes per work-group (0 = default) */
     int32_t fv_xcd_remap;     /* FV: 1 = group consecutive patches per XCD */
-    int32_t fd_block;         /* FD: reserved */
+    int32_t fd_xcd_remap;     /* FD: 1 = each XCD takes a contiguous run of tiles
+                                 (the tiles of one patch share its L2) */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);

@@ -55,7 +55,7 @@ class Stats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_block", C.c_int32)]
+    _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_xcd_remap", C.c_int32)]
 
 
 _lib = None
@@ -308,8 +308,8 @@ class PatchBatch:
             self.bufs[0].copy_(torch.from_numpy(np.ascontiguousarray(state)).to(self.dtype))
         _check(lib().pb_batch_reset(self.handle, 0), "pb_batch_reset")
 
-    def set_tuning(self, fv_slab=0, fv_xcd_remap=1):
-        t = Tuning(fv_slab, fv_xcd_remap, 0)
+    def set_tuning(self, fv_slab=0, fv_xcd_remap=1, fd_xcd_remap=1):
+        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap)
         _check(lib().pb_batch_set_tuning(self.handle, C.byref(t)), "pb_batch_set_tuning")
 
     def profile(self, on=True):

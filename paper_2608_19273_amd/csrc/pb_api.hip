@@ -32,8 +32,8 @@ WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K)
     o += sizeof(Ctrl);
     o = align256(o);
     L.part = o;
-    // [8][units] partials, then [8][units / 2048 + 1] for the second reduction stage
-    o = align256(o + (size_t)8 * ((size_t)max_units(K) + (size_t)max_units(K) / 2048 + 1) * sizeof(double));
+    // [8][units] partials, then [8][units / 256 + 1] for the second reduction stage
+    o = align256(o + (size_t)8 * ((size_t)max_units(K) + (size_t)max_units(K) / 256 + 1) * sizeof(double));
     if (pde == PB_PDE_SRHD) {
         L.pres = o;
         o = align256(o + (size_t)total_cells * sizeof(double));
@@ -180,7 +180,6 @@ static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sig
     const double dt = fd_dt(b, cfl, dt_fixed);
     for (int i = 0; i < n; ++i) {
         void *q0 = b->state[cur], *acc = b->state[cur ^ 1];
-        if ((st = launch_fd_reset(b, s)) != PB_OK) return st;
         if (rk == 1) {
             if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
             if ((st = launch_fd_stage(b, 0, 1, q0, q0, nullptr, acc, dt, sigma, s)) != PB_OK) return st;
@@ -264,21 +263,12 @@ pb_status patch_batch_create(const pb_batch_desc *d, pb_batch **out)
         for (int e = 1; e < b->dim; ++e) c *= P.p;
         off += c;
     }
-    // FD work list: most expensive (largest) patches first, stable in index
-    std::vector<int> order((size_t)b->K);
-    for (int k = 0; k < b->K; ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return b->p[a] > b->p[c]; });
-
     hipError_t e = hipMalloc(&b->d_patches, tab.size() * sizeof(PatchDev));
     if (e != hipSuccess) { delete b; return hip_fail(e, "hipMalloc(patch table)"); }
-    e = hipMalloc(&b->d_order, order.size() * sizeof(int));
-    if (e != hipSuccess) { (void)hipFree(b->d_patches); delete b; return hip_fail(e, "hipMalloc(work list)"); }
     e = hipMemcpy(b->d_patches, tab.data(), tab.size() * sizeof(PatchDev), hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(b->d_order, order.data(), order.size() * sizeof(int), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking);
     if (e != hipSuccess) {
         (void)hipFree(b->d_patches);
-        (void)hipFree(b->d_order);
         delete b;
         return hip_fail(e, "patch_batch_create");
     }
@@ -296,7 +286,6 @@ pb_status patch_batch_destroy(pb_batch *b)
         for (auto ev : b->prof_ev[w]) (void)hipEventDestroy(ev);
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     (void)hipFree(b->d_patches);
-    (void)hipFree(b->d_order);
     if (b->d_fd_items) (void)hipFree(b->d_fd_items);
     if (b->d_fd_B) (void)hipFree(b->d_fd_B);
     delete b;
@@ -319,6 +308,7 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     if (t->fv_slab < 0 || t->fv_slab > kFvPmax) { set_error("fv_slab must be in [0, 16]"); return PB_EINVAL; }
     b->fv_slab = t->fv_slab;
     b->fv_xcd_remap = t->fv_xcd_remap ? 1 : 0;
+    b->fd_xcd_remap = t->fd_xcd_remap ? 1 : 0;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     return PB_OK;

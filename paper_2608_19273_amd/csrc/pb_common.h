@@ -40,8 +40,7 @@ struct Ctrl {
     unsigned int c2p_maxit;
     unsigned int pad0;
     double last_dt;
-    unsigned int fdq[4];                // FD work-list heads, one per RK stage
-    unsigned long long pad[17];
+    unsigned long long pad[19];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
@@ -99,12 +98,12 @@ struct pb_batch {
     int pmax = 0;
     bool uniform_p = true;
     pb::PatchDev *d_patches = nullptr;
-    int *d_order = nullptr;          // FD: cost-ordered work list
     long long steps = 0;
     double last_dt_host = 0.0;
     // tuning
     int fv_slab = 0;
     int fv_xcd_remap = 1;
+    int fd_xcd_remap = 1;
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
@@ -151,7 +150,6 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
                           hipStream_t s);
 pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y,
                           void *ynext, void *acc, double dt, double sigma, hipStream_t s);
-pb_status launch_fd_reset(pb_batch *b, hipStream_t s);
 // uploads the FD work list and B_d (library-owned; done once, before any capture)
 pb_status fd_prepare(pb_batch *b);
 pb_status launch_ctrl_init(pb_batch *b, hipStream_t s);

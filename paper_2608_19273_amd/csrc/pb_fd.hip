@@ -6,9 +6,12 @@
 //   KO6 u = sigma/(64 dx) [(u_-3 + u_+3) - 6 (u_-2 + u_+2) + 15 (u_-1 + u_+1) - 20 u_0].
 //
 // Work decomposition (MI355X): one persistent launch per RK stage.  Work
-// items are 4x4x4 cell tiles, listed largest patches first (the patch cost
-// grows like p^3), and work-groups pop them from an atomic counter.  For a
-// tile, the N unknowns are processed in chunks of 16:
+// items are 4x4x4 cell tiles, listed largest patches first with the tiles of
+// a patch consecutive.  Every tile costs the same, so a static schedule is
+// balanced: work-group g takes a contiguous range of the list (neighbouring
+// tiles of one patch in sequence, their shared halo cells still in L2) and
+// no atomic queue is needed.  For a tile, the N unknowns are processed in
+// chunks of 16:
 //   1. the chunk's values on the tile's cross-shaped stencil footprint
 //      (64 cells + 3 layers on each of the 6 faces = 352 cells, periodic
 //      wrap inside the patch) are staged in LDS;
@@ -40,7 +43,7 @@ constexpr int kT = 4;                 // tile edge
 constexpr int kTC = kT * kT * kT;     // 64 cells per tile
 constexpr int kCh = 16;               // unknowns per chunk
 constexpr int kFoot = kTC + 6 * 3 * kT * kT;  // 352 footprint cells
-constexpr int kMaxN = 64;
+constexpr int kMaxN = 60;   // K of the dense product padded to a multiple of 4
 
 // footprint slot of tile-local coordinates (x, y, z), at most one of them
 // outside [0, 4) and then by at most 3
@@ -84,13 +87,12 @@ struct FdItem {
 __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
     const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
     double *__restrict__ acc, const PatchDev *__restrict__ patches, const FdItem *__restrict__ items, int n_items,
-    unsigned int *__restrict__ queue, const double *__restrict__ Bmat, int N, int stage, int rk, double dt,
-    double sigma)
+    const double *__restrict__ Bmat, int N, int stage, int rk, double dt,
+    double sigma, int remap)
 {
     __shared__ double sQ[kCh][kFoot];
     __shared__ double sG[3][kCh][kTC];
     __shared__ double sK[kCh][kTC];
-    __shared__ int sItem;
 
     const int t = threadIdx.x, w = t >> 6, l = t & 63, lg = l >> 4, lj = l & 15;
     // rows 16w + lj of -B_d, columns 4 ks + lg: this lane's A operands
@@ -107,12 +109,13 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
     }
     const int nch = (N + kCh - 1) / kCh;
 
-    for (;;) {
-        if (t == 0) sItem = (int)atomicAdd(queue, 1u);
-        __syncthreads();
-        const int it = sItem;
-        if (it >= n_items) break;
-        const FdItem item = items[it];
+    // rounds of gridDim.x consecutive items; inside a round the workgroups
+    // of one XCD (blockIdx mod 8) take one contiguous run of items, so the
+    // tiles of a patch share that XCD's L2 instead of fetching the patch
+    // once per XCD
+    const int G = (int)gridDim.x, slot = remap ? xcd_remap((int)blockIdx.x, G) : (int)blockIdx.x;
+    for (int base = 0; base + slot < n_items; base += G) {
+        const FdItem item = items[base + slot];
         const PatchDev P = patches[item.patch];
         const int p = P.p, ntile = p / kT;
         const long long C = (long long)p * p * p;
@@ -123,18 +126,43 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
         f64x4_t accm[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) accm[nt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+        // this thread stages footprint slots t and t + 256 (the latter for
+        // t < 96); their cell offsets inside the patch are fixed for the tile
+        const int s1 = t + kFdThreads;
+        const bool has1 = s1 < kFoot;
+        long long fo0, fo1 = 0;
+        {
+            int x, yy, z;
+            foot_coord(t, x, yy, z);
+            fo0 = ((long long)((tz + z + p) % p) * p + (ty + yy + p) % p) * p + (tx + x + p) % p;
+            if (has1) {
+                foot_coord(s1, x, yy, z);
+                fo1 = ((long long)((tz + z + p) % p) * p + (ty + yy + p) % p) * p + (tx + x + p) % p;
+            }
+        }
+        const double *ybase = y + P.off * N;
 
 #pragma unroll
-        for (int ch = 0; ch < kMaxN / kCh; ++ch) {
+        for (int ch = 0; ch < (kMaxN + kCh - 1) / kCh; ++ch) {
             if (ch >= nch) break;
             const int v0 = ch * kCh;
-            // 1. stage the footprint of unknowns v0..v0+15
-            for (int e = t; e < kCh * kFoot; e += kFdThreads) {
-                const int vl = e / kFoot, s = e - vl * kFoot, v = v0 + vl;
-                int x, yy, z;
-                foot_coord(s, x, yy, z);
-                const int gx = (tx + x + p) % p, gy = (ty + yy + p) % p, gz = (tz + z + p) % p;
-                sQ[vl][s] = v < N ? y[P.off * N + (long long)v * C + ((long long)gz * p + gy) * p + gx] : 0.0;
+            // 1. stage the footprint of unknowns v0..v0+15: all loads of a
+            //    slot are issued before its LDS stores
+            {
+                double r0[kCh];
+#pragma unroll
+                for (int vl = 0; vl < kCh; ++vl)
+                    r0[vl] = (v0 + vl < N) ? ybase[(long long)(v0 + vl) * C + fo0] : 0.0;
+#pragma unroll
+                for (int vl = 0; vl < kCh; ++vl) sQ[vl][t] = r0[vl];
+            }
+            if (has1) {
+                double r1[kCh];
+#pragma unroll
+                for (int vl = 0; vl < kCh; ++vl)
+                    r1[vl] = (v0 + vl < N) ? ybase[(long long)(v0 + vl) * C + fo1] : 0.0;
+#pragma unroll
+                for (int vl = 0; vl < kCh; ++vl) sQ[vl][s1] = r1[vl];
             }
             __syncthreads();
             // 2. gradients and dissipation of the chunk
@@ -176,6 +204,7 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
             for (int d = 0; d < 3; ++d)
 #pragma unroll
                 for (int kk = 0; kk < kCh / 4; ++kk) {
+                    if (ch * (kCh / 4) + kk >= kMaxN / 4) break;
                     const double aop = a[d][ch * (kCh / 4) + kk];
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt)
@@ -191,41 +220,46 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
             }
             __syncthreads();
         }
-        // 4. stage update in the output layout
+        // 4. stage update in the output layout, four rows at a time: reads
+        //    first, then the arithmetic and the stores
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) {
             const int c = nt * 16 + lj;
             const int x = c % kT, yy = (c / kT) % kT, z = c / (kT * kT);
             const long long cell = ((long long)(tz + z) * p + (ty + yy)) * p + (tx + x);
+            long long gidx[4];
+            double q0v[4], accv[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * w + lg + 4 * i;
+                const bool ok = r < N;
+                gidx[i] = P.off * N + (long long)(ok ? r : 0) * C + cell;
+                q0v[i] = (ok && (rk == 1 || stage < 3)) ? q0[gidx[i]] : 0.0;
+                accv[i] = (ok && rk == 4 && stage > 0) ? acc[gidx[i]] : 0.0;
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = 16 * w + lg + 4 * i;
                 if (r >= N) continue;
-                const long long g = P.off * N + (long long)r * C + cell;
+                const long long g = gidx[i];
                 const double R = accm[nt][i];
                 if (rk == 1) {
-                    acc[g] = q0[g] + dt * R;
+                    acc[g] = q0v[i] + dt * R;
                 } else if (stage == 0) {
-                    const double qv = q0[g];
-                    ynext[g] = qv + 0.5 * dt * R;
-                    acc[g] = qv + (dt / 6.0) * R;
+                    ynext[g] = q0v[i] + 0.5 * dt * R;
+                    acc[g] = q0v[i] + (dt / 6.0) * R;
                 } else if (stage == 1) {
-                    ynext[g] = q0[g] + 0.5 * dt * R;
-                    acc[g] += (dt / 3.0) * R;
+                    ynext[g] = q0v[i] + 0.5 * dt * R;
+                    acc[g] = accv[i] + (dt / 3.0) * R;
                 } else if (stage == 2) {
-                    ynext[g] = q0[g] + dt * R;
-                    acc[g] += (dt / 3.0) * R;
+                    ynext[g] = q0v[i] + dt * R;
+                    acc[g] = accv[i] + (dt / 3.0) * R;
                 } else {
-                    acc[g] += (dt / 6.0) * R;
+                    acc[g] = accv[i] + (dt / 6.0) * R;
                 }
             }
         }
     }
-}
-
-__global__ void fd_reset_kernel(unsigned int *queue)
-{
-    if (threadIdx.x < 4) queue[threadIdx.x] = 0u;
 }
 
 // ------------------------------------------------------------------ host --
@@ -252,22 +286,12 @@ pb_status fd_prepare(pb_batch *b)
     return PB_OK;
 }
 
-pb_status launch_fd_reset(pb_batch *b, hipStream_t s)
-{
-    pb_status st = fd_prepare(b);
-    if (st != PB_OK) return st;
-    Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
-    hipLaunchKernelGGL(fd_reset_kernel, dim3(1), dim3(64), 0, s, ctrl->fdq);
-    PB_HIP(hipGetLastError());
-    return PB_OK;
-}
-
 pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y, void *ynext,
                           void *acc, double dt, double sigma, hipStream_t s)
 {
     pb_status st = fd_prepare(b);
     if (st != PB_OK) return st;
-    if (b->N > kMaxN) { set_error("fd_ko_step: at most 64 unknowns"); return PB_EUNSUPPORTED; }
+    if (b->N > kMaxN) { set_error("fd_ko_step: at most 60 unknowns"); return PB_EUNSUPPORTED; }
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
     int dev = 0, cus = 0;
     PB_HIP(hipGetDevice(&dev));
@@ -276,7 +300,7 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
     hipLaunchKernelGGL(fd_stage_kernel, dim3(grid), dim3(kFdThreads), 0, s, static_cast<const double *>(y),
                        static_cast<const double *>(q0), static_cast<double *>(ynext), static_cast<double *>(acc),
                        b->d_patches, reinterpret_cast<const FdItem *>(b->d_fd_items), b->fd_n_items,
-                       ctrl->fdq + stage, b->d_fd_B, b->N, stage, rk_stages, dt, sigma);
+                       b->d_fd_B, b->N, stage, rk_stages, dt, sigma, b->fd_xcd_remap);
     PB_HIP(hipGetLastError());
     return PB_OK;
 }

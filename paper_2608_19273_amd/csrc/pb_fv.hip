@@ -27,7 +27,7 @@
 
 namespace pb {
 
-constexpr int kReduceSpan = 2048;   // units per work-group of the first reduction stage
+constexpr int kReduceSpan = 256;    // units per work-group of the first reduction stage
 
 namespace {
 

@@ -48,8 +48,8 @@ def test_workspace_size_layout():
     def a256(v):
         return (v + 255) // 256 * 256
 
-    def part(K):  # per-unit partials [8][16 K] doubles + second-stage [8][16 K / 2048 + 1]
-        return a256(8 * (16 * K + 16 * K // 2048 + 1) * 8)
+    def part(K):  # per-unit partials [8][16 K] doubles + second-stage [8][16 K / 256 + 1]
+        return a256(8 * (16 * K + 16 * K // 256 + 1) * 8)
 
     b = I.config0()
     d, keep = desc_for(b)
