@@ -109,8 +109,22 @@ def attainable_copy(torch, pb):
     return 2 * src.numel() * 8 * reps / el / 1e9
 
 
+def tune(B, kind, **kw):
+    """run the library's autotuner on batch B (outside any timed region) and
+    summarise its measurements"""
+    r = B.autotune(kind, trials=3, **kw)
+
+    def name(t):
+        if kind == "fv":
+            return f"slab{t['fv_slab']}/remap{t['fv_xcd_remap']}"
+        return f"remap{t['fd_xcd_remap']}/wg{t['fd_wg_per_cu']}"
+    return {"chosen": name(r["best"]), "from_cache": r["from_cache"],
+            "candidates_us": {name(t): round(us, 2) for t, us in r["candidates"]}}
+
+
 def bench_euler3d(torch, pb, b, storage, steps, warmup):
     B = pb.PatchBatch(b, storage=storage)
+    tuned = tune(B, "fv", cfl=0.4)
     B.fv_rusanov_step(cfl=0.4, n_steps=warmup)
     B.profile(True)
     el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.4, n_steps=steps))
@@ -124,7 +138,8 @@ def bench_euler3d(torch, pb, b, storage, steps, warmup):
     avg_s = kern_ms / 1e3 / max(launches, 1)
     return {"cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
             "kernel_avg_us": avg_s * 1e6, "launches": launches, "bytes_per_cell": bpc,
-            "kernel_GBs": cells * bpc / avg_s / 1e9, "nonfinite_units": st["nonfinite_units"]}
+            "kernel_GBs": cells * bpc / avg_s / 1e9, "nonfinite_units": st["nonfinite_units"],
+            "autotune": tuned}
 
 
 def bench_config0(torch, pb, I, calls):
@@ -146,6 +161,7 @@ def bench_fd(torch, pb, I, steps, warmup):
     b = I.config2()
     cells = b.total_cells
     B = pb.PatchBatch(b)
+    tuned = tune(B, "fd", cfl=0.5, sigma_ko=0.1)
     B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=warmup)
     B.profile(True)
     el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
@@ -163,7 +179,8 @@ def bench_fd(torch, pb, I, steps, warmup):
             "stage_kernel_avg_us": kern_ms * 1e3 / max(launches, 1),
             "hbm_frac": cells * bytes_cell / step_kernel_s / 1e9 / HBM_PEAK_GBS,
             "fp64_frac": cells * flop_cell / step_kernel_s / 1e12 / FP64_PEAK_TFLOPS,
-            "algorithmic_bytes_per_cell_step": bytes_cell, "algorithmic_flop_per_cell_step": flop_cell}
+            "algorithmic_bytes_per_cell_step": bytes_cell, "algorithmic_flop_per_cell_step": flop_cell,
+            "autotune": tuned}
 
 
 def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
@@ -181,6 +198,7 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
                            "final_epoch_loss": hist["epoch_loss"][-1]}
     for guess in ("plain", "warm", "learned"):
         B = pb.PatchBatch(b)
+        tuned = tune(B, "fv", cfl=0.4)   # measured for the first mode, then from the cache
         if guess != "plain":
             B.set_c2p_guess(guess, net if guess == "learned" else None)
         B.fv_rusanov_step(cfl=0.4, n_steps=1)   # warm-up (and the first pressure for the warm start)
@@ -193,7 +211,7 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
                       "newton_iterations_mean": (st["c2p_iterations"] - st0["c2p_iterations"]) / max(solves, 1),
                       "newton_iterations_max": st["c2p_max_iterations"],
                       "c2p_failures": st["c2p_failures"] - st0["c2p_failures"],
-                      "fallbacks": st["c2p_fallbacks"] - st0["c2p_fallbacks"]}
+                      "fallbacks": st["c2p_fallbacks"] - st0["c2p_fallbacks"], "autotune": tuned}
     res["learned_over_plain_speedup"] = res["learned"]["cell_updates_per_s"] / res["plain"]["cell_updates_per_s"]
     net.close()
     return res
@@ -251,6 +269,7 @@ def main():
                      "attainable_copy_GBs": copy_gbs, "frac_of_attainable": achieved / copy_gbs,
                      "kernel_source_sha": sha},
         "nonfinite_units": h["nonfinite_units"],
+        "autotune": h["autotune"],
     }
     if not args.only_headline:
         wl = {}

@@ -261,14 +261,67 @@ pb_status pb_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
 
 /* --------------------------------------------------------------- tuning -- */
 
+/* Launch-shape choices of the step kernels.  None of them changes what is
+ * computed; the FV slab changes the order of a few additions at slab seams
+ * (last-bit differences), the others change nothing in the results. */
 typedef struct {
-    int32_t fv_slab;          /* FV: z-planes per work-group (0 = default) */
+    int32_t fv_slab;          /* FV: z-planes per work-group (0 = whole patch) */
     int32_t fv_xcd_remap;     /* FV: 1 = group consecutive patches per XCD */
     int32_t fd_xcd_remap;     /* FD: 1 = each XCD takes a contiguous run of tiles
                                  (the tiles of one patch share its L2) */
+    int32_t fd_wg_per_cu;     /* FD: resident work-groups per CU, 1 or 2 (0 = 2) */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
+pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
+
+/* ------------------------------------------------------------ autotuner -- */
+
+/* Measured search over the launch shapes of one step kernel for this batch
+ * (the tuning frameworks and exhaustive search that Sec. V names as the way
+ * to choose kernel variants per architecture).
+ *
+ * kind 0 = the finite-volume step (fv_rusanov_step with the given cfl /
+ * dt_fixed), kind 1 = one FD4+KO6 stage (fd_ko_step with sigma_ko; cfl /
+ * dt_fixed as there).  Candidates:
+ *   FV 3D: fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0};
+ *   FV 2D: fv_xcd_remap {1, 0};
+ *   FD:    fd_xcd_remap {1, 0} x fd_wg_per_cu {2, 1}.
+ * Each candidate runs one untimed launch and then `trials` timed launches
+ * (HIP events on the batch's stream), over two interleaved passes; its time
+ * is the smaller of the two pass averages.  The trial launches read the
+ * current state and write only the other state buffer and the workspace, so
+ * the current state is unchanged; the control block (dt slots, counters) is
+ * saved before and restored after.  SRHD: the con2prim pass runs once first
+ * (so afterwards the warm-start guess is the pressure of the current state).
+ * The fastest candidate is applied to the batch (captured graphs are
+ * dropped) and cached in this process under a key of (kind, PDE, dim, N,
+ * storage, halo, patch-size histogram); with use_cache = 1 a cached entry is
+ * applied without timing anything (out->from_cache = 1).
+ * Synchronises the stream.  Errors: PB_EINVAL for bad arguments or a kind
+ * that does not match the PDE, PB_EHIP for HIP failures. */
+#define PB_TUNE_MAX 16
+typedef struct {
+    int32_t n_candidates;
+    int32_t from_cache;
+    int32_t best;                    /* index into cand / cand_us */
+    int32_t pad_;
+    pb_tuning cand[PB_TUNE_MAX];
+    double cand_us[PB_TUNE_MAX];     /* average launch duration (microseconds) */
+} pb_autotune_result;
+
+pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, double sigma_ko, int32_t trials,
+                      int32_t use_cache, pb_autotune_result *out);
+
+/* The process-wide tuning cache as a text file, one entry per line:
+ * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu>".
+ * save writes every entry (replacing the file); load adds the file's entries
+ * (a later entry of the same key wins) and stores their number in *n_loaded
+ * (nullable).  Host-only; PB_EINVAL on a file that cannot be opened or a
+ * malformed line (entries before it stay loaded). */
+pb_status pb_autotune_cache_save(const char *path);
+pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded);
+pb_status pb_autotune_cache_clear(void);
 
 const char *pb_last_error(void);
 

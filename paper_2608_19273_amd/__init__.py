@@ -55,7 +55,19 @@ class Stats(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_xcd_remap", C.c_int32)]
+    _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_xcd_remap", C.c_int32),
+                ("fd_wg_per_cu", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PB_TUNE_MAX = 16
+
+
+class AutotuneResult(C.Structure):
+    _fields_ = [("n_candidates", C.c_int32), ("from_cache", C.c_int32), ("best", C.c_int32),
+                ("pad_", C.c_int32), ("cand", Tuning * PB_TUNE_MAX), ("cand_us", C.c_double * PB_TUNE_MAX)]
 
 
 _lib = None
@@ -77,6 +89,12 @@ def lib():
         L.pb_batch_reset.argtypes = [vp, C.c_int32]
         L.pb_batch_stats.argtypes = [vp, C.POINTER(Stats)]
         L.pb_batch_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.pb_batch_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.pb_autotune.argtypes = [vp, C.c_int32, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int32,
+                                  C.POINTER(AutotuneResult)]
+        L.pb_autotune_cache_save.argtypes = [C.c_char_p]
+        L.pb_autotune_cache_load.argtypes = [C.c_char_p, C.POINTER(C.c_int32)]
+        L.pb_autotune_cache_clear.argtypes = []
         L.pb_batch_set_c2p_guess.argtypes = [vp, C.c_int32, vp]
         L.pb_batch_profile.argtypes = [vp, C.c_int32]
         L.pb_batch_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
@@ -96,7 +114,8 @@ def lib():
         L.pb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                                         C.c_int32, vp, vp]
         for name in ("pb_workspace_size", "patch_batch_create", "patch_batch_destroy", "pb_batch_reset",
-                     "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_set_c2p_guess", "pb_batch_profile",
+                     "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_get_tuning", "pb_autotune",
+                     "pb_autotune_cache_save", "pb_autotune_cache_load", "pb_autotune_cache_clear", "pb_batch_set_c2p_guess", "pb_batch_profile",
                      "pb_batch_profile_read", "pb_stream_copy", "fv_rusanov_step",
                      "fd_ko_step", "con2prim", "pb_mlp_create", "pb_mlp_destroy", "pb_mlp_set_params",
                      "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_features", "pb_mlp_grad", "pb_mlp_train_step"):
@@ -173,6 +192,31 @@ def pb_stream_copy(src, dst):
 
 
 # -------------------------------------------------------------- wrappers --
+
+
+
+def pb_autotune(h, kind="fv", cfl=0.4, dt_fixed=0.0, sigma_ko=0.1, trials=5, use_cache=True):
+    r = AutotuneResult()
+    k = {"fv": 0, "fd": 1}[kind] if isinstance(kind, str) else int(kind)
+    _check(lib().pb_autotune(h, k, cfl, dt_fixed, sigma_ko, int(trials), int(bool(use_cache)), C.byref(r)),
+           "pb_autotune")
+    cands = [(r.cand[i].as_dict(), r.cand_us[i]) for i in range(r.n_candidates)]
+    return {"best": cands[r.best][0], "best_us": cands[r.best][1], "from_cache": bool(r.from_cache),
+            "candidates": cands}
+
+
+def pb_autotune_cache_save(path):
+    _check(lib().pb_autotune_cache_save(os.fsencode(path)), "pb_autotune_cache_save")
+
+
+def pb_autotune_cache_load(path) -> int:
+    n = C.c_int32(0)
+    _check(lib().pb_autotune_cache_load(os.fsencode(path), C.byref(n)), "pb_autotune_cache_load")
+    return n.value
+
+
+def pb_autotune_cache_clear():
+    _check(lib().pb_autotune_cache_clear(), "pb_autotune_cache_clear")
 
 
 class Mlp:
@@ -308,9 +352,19 @@ class PatchBatch:
             self.bufs[0].copy_(torch.from_numpy(np.ascontiguousarray(state)).to(self.dtype))
         _check(lib().pb_batch_reset(self.handle, 0), "pb_batch_reset")
 
-    def set_tuning(self, fv_slab=0, fv_xcd_remap=1, fd_xcd_remap=1):
-        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap)
+    def set_tuning(self, fv_slab=0, fv_xcd_remap=1, fd_xcd_remap=1, fd_wg_per_cu=2):
+        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap, fd_wg_per_cu)
         _check(lib().pb_batch_set_tuning(self.handle, C.byref(t)), "pb_batch_set_tuning")
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().pb_batch_get_tuning(self.handle, C.byref(t)), "pb_batch_get_tuning")
+        return t.as_dict()
+
+    def autotune(self, kind="fv", cfl=0.4, dt_fixed=0.0, sigma_ko=0.1, trials=5, use_cache=True):
+        """measured launch-shape search (pb_autotune); returns the chosen tuning
+        and the measured candidates"""
+        return pb_autotune(self.handle, kind, cfl, dt_fixed, sigma_ko, trials, use_cache)
 
     def profile(self, on=True):
         _check(lib().pb_batch_profile(self.handle, int(on)), "pb_batch_profile")

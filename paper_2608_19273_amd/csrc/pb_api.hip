@@ -162,7 +162,7 @@ static pb_status enqueue_fv(pb_batch *b, double cfl, double dt_fixed, int n, hip
 
 // dt of the linear system: its largest speeds are the spectral radii rho_d
 // of B_d (part of the PDE parameters), so dt = cfl / sum_d (rho_d / dx_min)
-static double fd_dt(const pb_batch *b, double cfl, double dt_fixed)
+double fd_dt(const pb_batch *b, double cfl, double dt_fixed)
 {
     if (dt_fixed > 0.0) return dt_fixed;
     double den = 0.0;
@@ -306,11 +306,23 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
 {
     if (!b || !t) { set_error("NULL argument"); return PB_EINVAL; }
     if (t->fv_slab < 0 || t->fv_slab > kFvPmax) { set_error("fv_slab must be in [0, 16]"); return PB_EINVAL; }
+    if (t->fd_wg_per_cu < 0 || t->fd_wg_per_cu > 2) { set_error("fd_wg_per_cu must be 0, 1 or 2"); return PB_EINVAL; }
     b->fv_slab = t->fv_slab;
     b->fv_xcd_remap = t->fv_xcd_remap ? 1 : 0;
     b->fd_xcd_remap = t->fd_xcd_remap ? 1 : 0;
+    b->fd_wg_per_cu = t->fd_wg_per_cu == 0 ? 2 : t->fd_wg_per_cu;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
+    return PB_OK;
+}
+
+pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
+{
+    if (!b || !out) { set_error("NULL argument"); return PB_EINVAL; }
+    out->fv_slab = b->fv_slab;
+    out->fv_xcd_remap = b->fv_xcd_remap;
+    out->fd_xcd_remap = b->fd_xcd_remap;
+    out->fd_wg_per_cu = b->fd_wg_per_cu;
     return PB_OK;
 }
 

@@ -104,6 +104,7 @@ struct pb_batch {
     int fv_slab = 0;
     int fv_xcd_remap = 1;
     int fd_xcd_remap = 1;
+    int fd_wg_per_cu = 2;
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
@@ -150,6 +151,8 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
                           hipStream_t s);
 pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y,
                           void *ynext, void *acc, double dt, double sigma, hipStream_t s);
+// dt of an FD step: dt_fixed if > 0, else cfl / sum_d (rho(B_d) / dx_min)
+double fd_dt(const pb_batch *b, double cfl, double dt_fixed);
 // uploads the FD work list and B_d (library-owned; done once, before any capture)
 pb_status fd_prepare(pb_batch *b);
 pb_status launch_ctrl_init(pb_batch *b, hipStream_t s);

@@ -296,7 +296,7 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
     int dev = 0, cus = 0;
     PB_HIP(hipGetDevice(&dev));
     PB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int grid = std::max(1, std::min(b->fd_n_items, cus * 2));
+    const int grid = std::max(1, std::min(b->fd_n_items, cus * b->fd_wg_per_cu));
     hipLaunchKernelGGL(fd_stage_kernel, dim3(grid), dim3(kFdThreads), 0, s, static_cast<const double *>(y),
                        static_cast<const double *>(q0), static_cast<double *>(ynext), static_cast<double *>(acc),
                        b->d_patches, reinterpret_cast<const FdItem *>(b->d_fd_items), b->fd_n_items,

@@ -116,3 +116,37 @@ def test_python_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(pb, "_lib", None)
     with pytest.raises(pb.PbError):
         pb.lib()
+
+
+def test_autotune_rejects_bad_arguments_without_gpu():
+    L = pb.lib()
+    r = pb.AutotuneResult()
+    assert L.pb_autotune(None, 0, 0.4, 0.0, 0.1, 5, 1, C.byref(r)) == pb.PB_EINVAL
+    assert L.pb_batch_get_tuning(None, None) == pb.PB_EINVAL
+    assert L.pb_batch_set_tuning(None, None) == pb.PB_EINVAL
+
+
+def test_autotune_cache_file_round_trip(tmp_path):
+    """the tuning cache is host-side: entries load, save and reload unchanged;
+    a malformed line is rejected with the entries before it kept"""
+    pb.pb_autotune_cache_clear()
+    src = tmp_path / "in.txt"
+    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1\n")
+    assert pb.pb_autotune_cache_load(str(src)) == 2
+    out = tmp_path / "out.txt"
+    pb.pb_autotune_cache_save(str(out))
+    lines = sorted(out.read_text().splitlines())
+    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2",
+                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1"])
+    bad = tmp_path / "bad.txt"
+    bad.write_text("fv/x 4 1 1 2\nfv/y 99 1 1 2\nfv/z 4 1 1 2\n")
+    with pytest.raises(pb.PbError, match="bad.txt:2"):
+        pb.pb_autotune_cache_load(str(bad))
+    pb.pb_autotune_cache_save(str(out))
+    keys = {ln.split()[0] for ln in out.read_text().splitlines()}
+    assert "fv/x" in keys and "fv/y" not in keys and "fv/z" not in keys
+    with pytest.raises(pb.PbError):
+        pb.pb_autotune_cache_load(str(tmp_path / "missing.txt"))
+    pb.pb_autotune_cache_clear()
+    pb.pb_autotune_cache_save(str(out))
+    assert out.read_text() == ""

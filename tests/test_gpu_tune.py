@@ -1,0 +1,91 @@
+"""The measured launch-shape search (pb_autotune): it picks one of its
+candidates, leaves the state and the control block untouched, caches its
+choice, and the steps that follow still match the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2608_19273_amd as pb
+from paper_2608_19273_amd import inputs as I
+
+from gpu_helpers import announce, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def check_result(r, n_cand):
+    assert not r["from_cache"]
+    assert len(r["candidates"]) == n_cand
+    us = [t for _, t in r["candidates"]]
+    assert all(np.isfinite(t) and t > 0 for t in us)
+    assert r["best_us"] == min(us)
+
+
+def test_fv_autotune_euler3d():
+    announce("autotune fv euler3d")
+    need_gpu()
+    pb.pb_autotune_cache_clear()
+    b = I.config1(grid=(4, 4, 2))
+    B = pb.PatchBatch(b)
+    before, st0 = B.download(), B.stats()
+    r = B.autotune("fv", cfl=0.4, trials=2)
+    check_result(r, 8)
+    assert sorted({c["fv_slab"] for c, _ in r["candidates"]}) == [2, 4, 8, 16]
+    assert B.get_tuning() == r["best"]
+    np.testing.assert_array_equal(B.download(), before)
+    assert B.stats() == st0
+    r2 = B.autotune("fv", cfl=0.4, trials=2)
+    assert r2["from_cache"] and r2["best"] == r["best"]
+    B.fv_rusanov_step(cfl=0.4, n_steps=5)
+    g = B.download()
+    B.close()
+    o, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=5)
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+    pb.pb_autotune_cache_clear()
+
+
+def test_fd_autotune_is_bitwise_neutral():
+    """FD tunings only move tiles between work-groups: a step after tuning is
+    bitwise equal to a step at the default tuning."""
+    announce("autotune fd")
+    need_gpu()
+    pb.pb_autotune_cache_clear()
+    b = I.config2(n_patches=24, N=20, sizes=np.array([4, 8, 16] * 8, np.int32))
+    B = pb.PatchBatch(b)
+    before, st0 = B.download(), B.stats()
+    r = B.autotune("fd", cfl=0.5, sigma_ko=0.1, trials=2)
+    check_result(r, 4)
+    np.testing.assert_array_equal(B.download(), before)
+    assert B.stats() == st0
+    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
+    g = B.download()
+    B.close()
+    B0 = pb.PatchBatch(b)
+    B0.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
+    g0 = B0.download()
+    B0.close()
+    np.testing.assert_array_equal(g, g0)
+    o, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+    with pytest.raises(pb.PbError):
+        pb.PatchBatch(b).autotune("fv")
+    pb.pb_autotune_cache_clear()
+
+
+def test_srhd_autotune_then_step():
+    announce("autotune fv srhd")
+    need_gpu()
+    pb.pb_autotune_cache_clear()
+    b = I.config3(grid=(2, 2, 2), seed=31)
+    B = pb.PatchBatch(b)
+    before, st0 = B.download(), B.stats()
+    r = B.autotune("fv", cfl=0.4, trials=2)
+    check_result(r, 8)
+    np.testing.assert_array_equal(B.download(), before)
+    assert B.stats() == st0
+    B.fv_rusanov_step(cfl=0.4, n_steps=2)
+    g = B.download()
+    B.close()
+    o, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+    pb.pb_autotune_cache_clear()
