@@ -9,7 +9,8 @@ parameters (used to pin the hand-written backward pass by finite
 differences).
 
 Parameter vector order: W1[64][5], b1[64], W2[64][64], b2[64], w3[64], b3.
-Normalisation vector: x_mean[5], x_std[5], y_mean, y_std.
+Normalisation vector: x_mean[5], x_std[5], y_mean, y_std (inputs are
+standardised as (x - x_mean) * binary32(1 / x_std)).
 Features of a conserved state (D, S, tau), E = tau + D, s = |S|:
     [log(D/E), s/E, log(1 - s/E), log(tau/E), log((tau (tau + 2D) - s^2) / E^2)]
 (the last is log((E^2 - D^2 - s^2)/E^2), a direct measure of the internal energy);
@@ -61,10 +62,14 @@ def features(cons) -> np.ndarray:
 
 
 def standardise(x, norm, bf16=True):
-    """(x - mean) / std in binary32 (x first rounded to binary32), then bf16"""
+    """(x - mean) * (1/std) in binary32 (x first rounded to binary32; the
+    reciprocal is the correctly rounded binary32 quotient 1/std), then bf16.
+    The product by the reciprocal is within 1.5 ulp of the quotient and is
+    what the network defines as its input."""
     n32 = np.asarray(norm, dtype=np.float32)
     x32 = np.asarray(x, dtype=np.float64).astype(np.float32)
-    z = (x32 - n32[:5]) / n32[5:10]
+    inv = np.float32(1.0) / n32[5:10]
+    z = (x32 - n32[:5]) * inv
     return bf16_rne(z).astype(np.float64) if bf16 else z.astype(np.float64)
 
 

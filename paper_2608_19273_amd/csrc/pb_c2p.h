@@ -27,7 +27,7 @@ struct C2pOut {
 };
 
 struct C2pIn {
-    double D, s2, tau, E;
+    double D, s2, s, tau, E;   // s = |S|
     double lo, hi;   // bracket
     bool ok;         // admissible input
 };
@@ -40,6 +40,7 @@ __device__ __forceinline__ C2pIn c2p_setup(double D, double Sx, double Sy, doubl
     in.s2 = Sx * Sx + Sy * Sy + Sz * Sz;
     in.E = tau + D;
     const double s = sqrt(in.s2);
+    in.s = s;
     in.ok = isfinite(D) && isfinite(in.s2) && isfinite(tau) && D > 0.0 && tau > 0.0;
     double lo = s - in.E;
     in.lo = lo > 0.0 ? lo : 0.0;

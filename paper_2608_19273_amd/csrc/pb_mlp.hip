@@ -24,7 +24,7 @@ struct pb_mlp {
     float *madam = nullptr;     // Adam first moments
     float *vadam = nullptr;     // Adam second moments
     float *norm = nullptr;      // [kMlpNNorm]
-    pb::bf16x4_t *w1s = nullptr, *w2s = nullptr;   // swizzled bf16 A operands
+    pb::MlpPack *pack = nullptr;  // inference operands (bf16, lane-swizzled), see pb_mlp.h
     float *grad = nullptr;      // [kMlpNParam] gradient of the last train step
     float *loss = nullptr;      // [1]
     float *scratch = nullptr;   // training activations, library-owned
@@ -41,43 +41,65 @@ namespace {
 constexpr int kChunks = 32;
 constexpr int kT = 256;
 
-// bf16 A operands from the FP32 masters (layout of pb_mlp.h)
-__global__ __launch_bounds__(1024) void mlp_refresh_kernel(const float *__restrict__ par, bf16x4_t *__restrict__ w1s,
-                                                           bf16x4_t *__restrict__ w2s)
+// the inference blob from the FP32 masters and the normalisation block
+// (layout of pb_mlp.h)
+__global__ __launch_bounds__(256) void mlp_refresh_kernel(const float *__restrict__ par, const float *__restrict__ norm,
+                                                          MlpPack *__restrict__ P)
 {
-    for (int idx = threadIdx.x; idx < 4 * 64 + 16 * 64; idx += blockDim.x) {
+    const int t = threadIdx.x;
+    for (int idx = t; idx < 4 * 64; idx += blockDim.x) {
+        const int mt = idx / 64, l = idx % 64, g = l / 16, j = l % 16, row = 16 * mt + j;
         bf16x4_t v;
-        if (idx < 4 * 64) {
-            const int mt = idx / 64, l = idx % 64, g = l / 16, j = l % 16;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int k = g * 4 + i, row = mt * 16 + j;
-                v[i] = (short)(k < kMlpIn ? bf16_rne(par[kOffW1 + row * kMlpIn + k]) : 0);
-            }
-            w1s[idx] = v;
-        } else {
-            const int id2 = idx - 4 * 64;
-            const int tile = id2 / 64, l = id2 % 64, g = l / 16, j = l % 16;
-            const int mt = tile / 4, kt = tile % 4;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int row = mt * 16 + j, k = kt * 16 + g * 4 + i;
-                v[i] = (short)bf16_rne(par[kOffW2 + row * kMlpHid + k]);
-            }
-            w2s[id2] = v;
+        for (int i = 0; i < 4; ++i) {
+            const int k = 4 * g + i;
+            v[i] = (short)(k < kMlpIn ? bf16_rne(par[kOffW1 + row * kMlpIn + k]) : 0);
         }
+        P->w1[mt][l] = v;
+    }
+    for (int idx = t; idx < 4 * 2 * 64; idx += blockDim.x) {
+        const int mt = idx / 128, kt = (idx / 64) % 2, l = idx % 64, g = l / 16, j = l % 16, row = 16 * mt + j;
+        bf16x8_t v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (__bf16)par[kOffW2 + row * kMlpHid + mlp_kperm(kt, g, i)];
+        P->w2[mt][kt][l] = v;
+    }
+    for (int idx = t; idx < 2 * 64; idx += blockDim.x) {
+        const int kt = idx / 64, l = idx % 64, g = l / 16;
+        bf16x8_t v;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = (__bf16)par[kOffW3 + mlp_kperm(kt, g, i)];
+        P->w3[kt][l] = v;
+    }
+    for (int i = t; i < kMlpHid; i += blockDim.x) {
+        P->b1[i] = par[kOffB1 + i];
+        P->b2[i] = par[kOffB2 + i];
+    }
+    if (t < kMlpIn) {
+        P->xm[t] = norm[t];
+        P->xi[t] = 1.0f / norm[5 + t];
+    }
+    if (t == 0) {
+        P->ym = norm[10];
+        P->ys = norm[11];
+        P->b3 = par[kOffB3];
+        P->pad = 0.f;
     }
 }
 
 // standalone forward: x [n][5] raw features -> y [n] (network output)
-__global__ __launch_bounds__(kT) void mlp_forward_kernel(MlpDev m, const float *__restrict__ x, float *__restrict__ y,
+__global__ __launch_bounds__(kT, 4) void mlp_forward_kernel(MlpDev m, const float *__restrict__ x, float *__restrict__ y,
                                                          long long n)
 {
     const long long i = (long long)blockIdx.x * kT + threadIdx.x;
-    float xi[kMlpIn];
+    float xm[kMlpIn], xi[kMlpIn], xr[kMlpIn];
 #pragma unroll
-    for (int k = 0; k < kMlpIn; ++k) xi[k] = i < n ? x[i * kMlpIn + k] : m.norm[k];
-    const float yh = mlp_yhat(m, xi);   // whole wave
+    for (int k = 0; k < kMlpIn; ++k) {
+        xm[k] = m.pack->xm[k];
+        xi[k] = m.pack->xi[k];
+        xr[k] = i < n ? x[i * kMlpIn + k] : xm[k];
+    }
+    const float yh = mlp_yhat(*m.pack, xm, xi, xr);   // whole wave
     if (i < n) y[i] = yh;
 }
 
@@ -110,7 +132,8 @@ __global__ __launch_bounds__(kT) void mlp_fwd_bwd_kernel(const float *__restrict
         unsigned short xb16[kMlpIn];
 #pragma unroll
         for (int k = 0; k < kMlpIn; ++k) xr[k] = x[s * kMlpIn + k];
-        mlp_inputs(norm, xr, xb16);
+#pragma unroll
+        for (int k = 0; k < kMlpIn; ++k) xb16[k] = bf16_rne((xr[k] - norm[k]) * (1.0f / norm[5 + k]));
         float xb[kMlpIn];
 #pragma unroll
         for (int k = 0; k < kMlpIn; ++k) {
@@ -241,7 +264,7 @@ __global__ __launch_bounds__(kT) void mlp_features_kernel(const double *__restri
 
 pb_status refresh(pb_mlp *m, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_refresh_kernel, dim3(1), dim3(1024), 0, s, m->par, m->w1s, m->w2s);
+    hipLaunchKernelGGL(mlp_refresh_kernel, dim3(1), dim3(256), 0, s, m->par, m->norm, m->pack);
     PB_HIP(hipGetLastError());
     return PB_OK;
 }
@@ -292,8 +315,7 @@ pb_status run_grad(pb_mlp *m, const float *x, const float *t, long long n, hipSt
 pb_status mlp_device_view(const pb_mlp *m, MlpDev *out)
 {
     if (!m || !out) { set_error("MLP is NULL"); return PB_EINVAL; }
-    out->w1 = m->w1s;
-    out->w2 = m->w2s;
+    out->pack = m->pack;
     out->par = m->par;
     out->norm = m->norm;
     return PB_OK;
@@ -312,15 +334,14 @@ pb_status pb_mlp_create(pb_mlp **out)
     pb_mlp *m = new (std::nothrow) pb_mlp();
     if (!m) { set_error("out of host memory"); return PB_ENOMEM; }
     const size_t nf = (size_t)kMlpNParam * 5 + 16 + (size_t)kChunks * kMlpNParam;
-    const size_t bytes = nf * sizeof(float) + (4 * 64 + 16 * 64) * sizeof(bf16x4_t) + 1024;
+    const size_t bytes = nf * sizeof(float) + sizeof(MlpPack) + 4096;
     hipError_t e = hipMalloc(&m->dev, bytes);
     if (e != hipSuccess) { delete m; return hip_fail(e, "hipMalloc(mlp)"); }
     e = hipMemset(m->dev, 0, bytes);
     if (e != hipSuccess) { (void)hipFree(m->dev); delete m; return hip_fail(e, "hipMemset(mlp)"); }
     char *p = m->dev;
     auto take = [&](size_t b) { char *r = p; p += (b + 255) & ~(size_t)255; return r; };
-    m->w1s = reinterpret_cast<bf16x4_t *>(take(4 * 64 * sizeof(bf16x4_t)));
-    m->w2s = reinterpret_cast<bf16x4_t *>(take(16 * 64 * sizeof(bf16x4_t)));
+    m->pack = reinterpret_cast<MlpPack *>(take(sizeof(MlpPack)));
     m->par = reinterpret_cast<float *>(take(kMlpNParam * sizeof(float)));
     m->madam = reinterpret_cast<float *>(take(kMlpNParam * sizeof(float)));
     m->vadam = reinterpret_cast<float *>(take(kMlpNParam * sizeof(float)));

@@ -1,10 +1,11 @@
 // pb_srhd.hip -- the per-cell conservative-to-primitive pass of the SRHD
 // finite-volume step, and the standalone con2prim entry point.
 //
-// The SRHD step is two launches (plus the one-work-group dt reduction):
+// The SRHD step is two launches (plus the small dt reduction):
 //   1. this pass: one lane per cell recovers the pressure by the bracketed
 //      FP64 Newton iteration (pb_c2p.h), seeded by the plain guess, the
-//      previous step's pressure (warm) or the MLP (learned); writes p to the
+//      previous step's pressure (warm) or the MLP (learned, evaluated in the
+//      same pass on the matrix cores: see pb_mlp.h); writes p to the
 //      workspace and per-work-group partials: largest speeds of Q^n (for dt),
 //      Newton iterations, failures, fallbacks;
 //   2. the fused Rusanov kernel (pb_fv.hip) with the SRHD functor, which
@@ -59,11 +60,67 @@ __device__ __forceinline__ void reduce_stats(C2pStats &s)
     }
 }
 
-// guess: 0 plain, 1 learned (mlp), 2 warm (pres holds the previous pressure)
+// Newton from p0; a learned guess that does not converge is retried from the
+// plain guess (counted as a fallback)
+__device__ __forceinline__ C2pOut solve_cell(const C2pIn &in, double gam, double tol, int maxit, double p0,
+                                             bool retry, double &fallbacks)
+{
+    C2pOut o = c2p_solve(in, gam, tol, maxit, p0);
+    if (retry && o.status == C2P_NOTCONV) {
+        const C2pOut o2 = c2p_solve(in, gam, tol, maxit, in.hi);
+        fallbacks += 1.0;
+        o.p = o2.p;
+        o.status = o2.status;
+        o.it += o2.it;
+    }
+    return o;
+}
+
+__device__ __forceinline__ void add_cell(C2pStats &s, const C2pOut &o)
+{
+    s.iters += o.it;
+    s.fails += o.status != C2P_OK ? 1.0 : 0.0;
+    s.maxit = fmax(s.maxit, (double)o.it);
+    s.cells += 1.0;
+}
+
+// per-lane totals over the cells a lane visits (integers where they count)
+struct CellAcc {
+    double lam[3] = {0.0, 0.0, 0.0};
+    int iters = 0, fails = 0, maxit = 0, fallbacks = 0, cells = 0;
+    __device__ __forceinline__ void add(const C2pOut &o)
+    {
+        iters += o.it;
+        fails += o.status != C2P_OK;
+        maxit = max(maxit, o.it);
+        ++cells;
+    }
+    __device__ __forceinline__ C2pStats stats() const
+    {
+        return {{lam[0], lam[1], lam[2]}, (double)iters, (double)fails, (double)maxit, (double)fallbacks,
+                (double)cells};
+    }
+};
+
+__device__ __forceinline__ C2pOut solve_cell_i(const C2pIn &in, double gam, double tol, int maxit, double p0,
+                                               int &fallbacks)
+{
+    C2pOut o = c2p_solve(in, gam, tol, maxit, p0);
+    if (o.status == C2P_NOTCONV) {
+        const C2pOut o2 = c2p_solve(in, gam, tol, maxit, in.hi);
+        ++fallbacks;
+        o.p = o2.p;
+        o.status = o2.status;
+        o.it += o2.it;
+    }
+    return o;
+}
+
+// plain (0) or warm (2: pres holds the previous pressure) guess, one cell per lane
 template <int GUESS>
 __global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
     const double *__restrict__ q, double *__restrict__ pres, const PatchDev *__restrict__ patches,
-    int chunks, int n_units, double *__restrict__ part, double gam, double tol, int maxit, MlpDev mlp)
+    int chunks, int n_units, double *__restrict__ part, double gam, double tol, int maxit)
 {
     const int unit = blockIdx.x;
     const int k = unit / chunks, ch = unit - k * chunks;
@@ -79,29 +136,16 @@ __global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
         for (int v = 0; v < 5; ++v) qv[v] = base[(long long)v * C];
     }
     const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
-    double p0 = in.hi;
-    // warm: previous pressure; learned: the guess the network pass stored
-    if (GUESS != 0 && active) p0 = pres[P.off + c];
     if (active) {
-        C2pOut o = c2p_solve(in, gam, tol, maxit, p0);
-        if (GUESS != 0 && o.status == C2P_NOTCONV) {
-            const C2pOut o2 = c2p_solve(in, gam, tol, maxit, in.hi);
-            s.fallbacks = 1.0;
-            o.p = o2.p;
-            o.status = o2.status;
-            o.it += o2.it;
-        }
+        const double p0 = GUESS == 2 ? pres[P.off + c] : in.hi;
+        const C2pOut o = solve_cell(in, gam, tol, maxit, p0, GUESS != 0, s.fallbacks);
         pres[P.off + c] = o.p;
         const Srhd ph{gam};
         double a[Srhd::A], e[1] = {o.p};
         ph.aux(qv, e, a);
-        s.lam[0] = a[4];
-        s.lam[1] = a[5];
-        s.lam[2] = a[6];
-        s.iters = o.it;
-        s.fails = o.status != C2P_OK ? 1.0 : 0.0;
-        s.maxit = o.it;
-        s.cells = 1.0;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) s.lam[d] = a[4 + d];
+        add_cell(s, o);
     }
     reduce_stats(s);
     if (threadIdx.x == 0) {
@@ -111,74 +155,130 @@ __global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
     }
 }
 
-// Learned guesses: each wave loads the network once and pushes
-// kGuessGroups groups of 64 cells through it (a work-group covers
-// 256 * kGuessGroups cells).
-constexpr int kGuessGroups = 4;
+// The learned pass: each work-group copies the network to LDS once and walks
+// kLearnChunks chunks of 256 cells of its patch (the next chunk's state is
+// loaded while the current one is solved).
+constexpr int kLearnChunks = 8;
 
-__device__ __forceinline__ double guess_of(const MlpRegs &r, const float *norm, const double *qv, bool active,
-                                           double gam)
+// the same LDS object behind an offset the compiler cannot see through: keeps
+// it from hoisting the (loop-invariant) weight reads out of the cell loop,
+// which would hold every weight tile in registers for the whole launch
+__device__ __forceinline__ const MlpPack &lds_fresh(const MlpPack &sp)
 {
-    const double d0[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-    const double *u = active ? qv : d0;
-    const C2pIn in = c2p_setup(u[0], u[1], u[2], u[3], u[4], gam);
-    return mlp_guess(r, norm, in);
+    unsigned off = 0;
+    __asm__ volatile("" : "+v"(off));
+    return *reinterpret_cast<const MlpPack *>(reinterpret_cast<const char *>(&sp) + off);
 }
 
-// p0 of every cell of the SRHD pass into `pres`
-__global__ __launch_bounds__(kC2pThreads) void srhd_guess_kernel(const double *__restrict__ q,
-                                                                 double *__restrict__ pres,
-                                                                 const PatchDev *__restrict__ patches, int gchunks,
-                                                                 double gam, MlpDev mlp)
+struct MlpLane {
+    float xm[kMlpIn], xi[kMlpIn], ym, ys;
+};
+
+// copies the blob to the work-group's LDS (returned) and the standardisation
+// constants to L
+__device__ __forceinline__ const MlpPack &mlp_lane_setup(const MlpPack *__restrict__ pack, MlpLane &L)
 {
+    __shared__ MlpPack sp;
+    const u32x4_t *src = reinterpret_cast<const u32x4_t *>(pack);
+    u32x4_t *dst = reinterpret_cast<u32x4_t *>(&sp);
+    for (int i = threadIdx.x; i < (int)(sizeof(MlpPack) / 16); i += kC2pThreads) dst[i] = src[i];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kMlpIn; ++k) {
+        L.xm[k] = pack->xm[k];
+        L.xi[k] = pack->xi[k];
+    }
+    L.ym = pack->ym;
+    L.ys = pack->ys;
+    return sp;
+}
+
+__global__ __launch_bounds__(kC2pThreads, 4) void srhd_c2p_learned_kernel(
+    const double *__restrict__ q, double *__restrict__ pres, const PatchDev *__restrict__ patches, int gchunks,
+    int n_units, double *__restrict__ part, double gam, double tol, int maxit, const MlpPack *__restrict__ pack)
+{
+    MlpLane L;
+    const MlpPack &sp = mlp_lane_setup(pack, L);
     const int unit = blockIdx.x;
-    const int k = unit / gchunks, ch = unit - k * gchunks;
+    const int k = unit / gchunks, gc = unit - k * gchunks;
     const PatchDev P = patches[k];
     const long long C = (long long)P.p * P.p * P.p;
-    MlpRegs r;
-    mlp_load(mlp, r);
+    const double *base = q + P.off * 5;
+    CellAcc acc;
+    const long long c0 = (long long)gc * kLearnChunks * kC2pThreads + threadIdx.x;
+    double nx[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+    if (c0 < C) {
+#pragma unroll
+        for (int v = 0; v < 5; ++v) nx[v] = base[(long long)v * C + c0];
+    }
 #pragma unroll 1
-    for (int gi = 0; gi < kGuessGroups; ++gi) {
-        const long long c = ((long long)ch * kGuessGroups + gi) * kC2pThreads + threadIdx.x;
+    for (int gi = 0; gi < kLearnChunks; ++gi) {
+        const long long c = c0 + (long long)gi * kC2pThreads;
+        if (c - threadIdx.x >= C) break;   // the same for the whole work-group
         const bool active = c < C;
         double qv[5];
-        if (active) {
-            const double *base = q + P.off * 5 + c;
 #pragma unroll
-            for (int v = 0; v < 5; ++v) qv[v] = base[(long long)v * C];
+        for (int v = 0; v < 5; ++v) qv[v] = nx[v];
+        const long long cn = c + kC2pThreads;
+        if (gi + 1 < kLearnChunks && cn < C) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) nx[v] = base[(long long)v * C + cn];
         }
-        const double g = guess_of(r, mlp.norm, qv, active, gam);
-        if (active) pres[P.off + c] = g;
+        const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
+        const double p0 = mlp_guess(lds_fresh(sp), L.xm, L.xi, L.ym, L.ys, in);   // whole wave
+        if (active) {
+            const C2pOut o = solve_cell_i(in, gam, tol, maxit, p0, acc.fallbacks);
+            pres[P.off + c] = o.p;
+            const Srhd ph{gam};
+            double a[Srhd::A], e[1] = {o.p};
+            ph.aux(qv, e, a);
+#pragma unroll
+            for (int d = 0; d < 3; ++d) acc.lam[d] = fmax(acc.lam[d], a[4 + d]);
+            acc.add(o);
+        }
+    }
+    C2pStats s = acc.stats();
+    reduce_stats(s);
+    if (threadIdx.x == 0) {
+        const double v[8] = {s.lam[0], s.lam[1], s.lam[2], s.iters, s.fails, s.maxit, s.fallbacks, s.cells};
+#pragma unroll
+        for (int r = 0; r < 8; ++r) part[(long long)r * n_units + unit] = v[r];
     }
 }
 
-// learned guesses for the standalone entry point, into p0[n]
-__global__ __launch_bounds__(kC2pThreads) void flat_guess_kernel(const double *__restrict__ cons,
-                                                                 double *__restrict__ p0, long long n, double gam,
-                                                                 MlpDev mlp)
+// standalone con2prim, one cell of SoA arrays: primitives out
+__device__ __forceinline__ void prim_out(const double *qv, const C2pIn &in, const C2pOut &o, double *prim,
+                                         long long n, long long i, int *iters, int *status)
 {
-    MlpRegs r;
-    mlp_load(mlp, r);
-#pragma unroll 1
-    for (int gi = 0; gi < kGuessGroups; ++gi) {
-        const long long i = ((long long)blockIdx.x * kGuessGroups + gi) * kC2pThreads + threadIdx.x;
-        const bool active = i < n;
-        double qv[5];
-        if (active) {
-#pragma unroll
-            for (int v = 0; v < 5; ++v) qv[v] = cons[(long long)v * n + i];
-        }
-        const double g = guess_of(r, mlp.norm, qv, active, gam);
-        if (active) p0[i] = g;
+    const double iEp = 1.0 / (in.E + o.p);
+    const double vx = qv[1] * iEp, vy = qv[2] * iEp, vz = qv[3] * iEp;
+    const double v2 = vx * vx + vy * vy + vz * vz;
+    prim[i] = qv[0] * sqrt(1.0 - v2);
+    prim[n + i] = vx;
+    prim[2 * n + i] = vy;
+    prim[3 * n + i] = vz;
+    prim[4 * n + i] = o.p;
+    if (iters) iters[i] = o.it;
+    if (status) status[i] = o.status;
+}
+
+__device__ __forceinline__ void counters_out(C2pStats &s, unsigned long long *counters)
+{
+    reduce_stats(s);
+    if (threadIdx.x == 0) {
+        if (s.fails > 0.0) atomicAdd(&counters[0], (unsigned long long)s.fails);
+        atomicAdd(&counters[1], (unsigned long long)s.iters);
+        if (s.fallbacks > 0.0) atomicAdd(&counters[2], (unsigned long long)s.fallbacks);
+        atomicMax(&counters[3], (unsigned long long)s.maxit);
     }
 }
 
-// standalone con2prim over n cells of SoA arrays
+// standalone con2prim over n cells, plain (0) or warm (2) guess
 template <int GUESS>
 __global__ __launch_bounds__(kC2pThreads) void con2prim_kernel(
-    const double *__restrict__ cons, double *prim, long long n, double gam, double tol, int maxit,
-    const double *p_prev, int *__restrict__ iters, int *__restrict__ status,
-    unsigned long long *__restrict__ counters, MlpDev mlp)
+    const double *__restrict__ cons, double *__restrict__ prim, long long n, double gam, double tol, int maxit,
+    const double *__restrict__ p_prev, int *__restrict__ iters, int *__restrict__ status,
+    unsigned long long *__restrict__ counters)
 {
     const long long i = (long long)blockIdx.x * kC2pThreads + threadIdx.x;
     const bool active = i < n;
@@ -188,42 +288,48 @@ __global__ __launch_bounds__(kC2pThreads) void con2prim_kernel(
         for (int v = 0; v < 5; ++v) qv[v] = cons[(long long)v * n + i];
     }
     const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
-    double p0 = in.hi;
-    // warm: caller's previous pressures; learned: the guesses the network
-    // pass stored in prim[4]
-    if (GUESS != 0 && active) p0 = p_prev[i];
     C2pStats s = {{0.0, 0.0, 0.0}, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (active) {
-        C2pOut o = c2p_solve(in, gam, tol, maxit, p0);
-        if (GUESS != 0 && o.status == C2P_NOTCONV) {
-            const C2pOut o2 = c2p_solve(in, gam, tol, maxit, in.hi);
-            s.fallbacks = 1.0;
-            o.p = o2.p;
-            o.status = o2.status;
-            o.it += o2.it;
+        const double p0 = GUESS == 2 ? p_prev[i] : in.hi;
+        const C2pOut o = solve_cell(in, gam, tol, maxit, p0, GUESS != 0, s.fallbacks);
+        prim_out(qv, in, o, prim, n, i, iters, status);
+        add_cell(s, o);
+    }
+    if (counters) counters_out(s, counters);
+}
+
+// standalone con2prim with the learned guess: kLearnChunks x 256 cells per
+// work-group, the network evaluated in the same pass
+__global__ __launch_bounds__(kC2pThreads, 4) void con2prim_learned_kernel(
+    const double *__restrict__ cons, double *__restrict__ prim, long long n, double gam, double tol, int maxit,
+    int *__restrict__ iters, int *__restrict__ status, unsigned long long *__restrict__ counters,
+    const MlpPack *__restrict__ pack)
+{
+    MlpLane L;
+    const MlpPack &sp = mlp_lane_setup(pack, L);
+    CellAcc acc;
+    const long long i0 = (long long)blockIdx.x * kLearnChunks * kC2pThreads + threadIdx.x;
+#pragma unroll 1
+    for (int gi = 0; gi < kLearnChunks; ++gi) {
+        const long long i = i0 + (long long)gi * kC2pThreads;
+        if (i - threadIdx.x >= n) break;   // the same for the whole work-group
+        const bool active = i < n;
+        double qv[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+        if (active) {
+#pragma unroll
+            for (int v = 0; v < 5; ++v) qv[v] = cons[(long long)v * n + i];
         }
-        const double iEp = 1.0 / (in.E + o.p);
-        const double vx = qv[1] * iEp, vy = qv[2] * iEp, vz = qv[3] * iEp;
-        const double v2 = vx * vx + vy * vy + vz * vz;
-        prim[i] = qv[0] * sqrt(1.0 - v2);
-        prim[n + i] = vx;
-        prim[2 * n + i] = vy;
-        prim[3 * n + i] = vz;
-        prim[4 * n + i] = o.p;
-        if (iters) iters[i] = o.it;
-        if (status) status[i] = o.status;
-        s.iters = o.it;
-        s.fails = o.status != C2P_OK ? 1.0 : 0.0;
-        s.maxit = o.it;
+        const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
+        const double p0 = mlp_guess(lds_fresh(sp), L.xm, L.xi, L.ym, L.ys, in);   // whole wave
+        if (active) {
+            const C2pOut o = solve_cell_i(in, gam, tol, maxit, p0, acc.fallbacks);
+            prim_out(qv, in, o, prim, n, i, iters, status);
+            acc.add(o);
+        }
     }
     if (counters) {
-        reduce_stats(s);
-        if (threadIdx.x == 0) {
-            if (s.fails > 0.0) atomicAdd(&counters[0], (unsigned long long)s.fails);
-            atomicAdd(&counters[1], (unsigned long long)s.iters);
-            if (s.fallbacks > 0.0) atomicAdd(&counters[2], (unsigned long long)s.fallbacks);
-            atomicMax(&counters[3], (unsigned long long)s.maxit);
-        }
+        C2pStats s = acc.stats();
+        counters_out(s, counters);
     }
 }
 
@@ -236,33 +342,30 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
     double *part = reinterpret_cast<double *>(b->ws + L.part);
     const long long cmax = (long long)b->pmax * b->pmax * b->pmax;
     const int chunks = (int)((cmax + kC2pThreads - 1) / kC2pThreads);
-    const int n_units = b->K * chunks;
     const double gam = b->params[0], tol = b->params[1];
     const int maxit = (int)b->params[2];
     int guess = b->guess;
     if (guess == PB_GUESS_WARM && !b->pres_valid) guess = PB_GUESS_PLAIN;
-    MlpDev md{};
-    if (guess == PB_GUESS_LEARNED) {
-        pb_status st = mlp_device_view(b->mlp, &md);
-        if (st != PB_OK) return st;
-    }
     const double *qd = static_cast<const double *>(q);
+    int n_units = b->K * chunks;
     switch (guess) {
     case PB_GUESS_PLAIN:
         hipLaunchKernelGGL(srhd_c2p_kernel<0>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, chunks,
-                           n_units, part, gam, tol, maxit, md);
+                           n_units, part, gam, tol, maxit);
         break;
-    case PB_GUESS_LEARNED:
-        hipLaunchKernelGGL(srhd_guess_kernel, dim3(b->K * ((chunks + kGuessGroups - 1) / kGuessGroups)),
-                           dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, (chunks + kGuessGroups - 1) / kGuessGroups,
-                           gam, md);
-        PB_HIP(hipGetLastError());
-        hipLaunchKernelGGL(srhd_c2p_kernel<1>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, chunks,
-                           n_units, part, gam, tol, maxit, md);
+    case PB_GUESS_LEARNED: {
+        MlpDev md{};
+        pb_status st = mlp_device_view(b->mlp, &md);
+        if (st != PB_OK) return st;
+        const int gchunks = (chunks + kLearnChunks - 1) / kLearnChunks;
+        n_units = b->K * gchunks;
+        hipLaunchKernelGGL(srhd_c2p_learned_kernel, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches,
+                           gchunks, n_units, part, gam, tol, maxit, md.pack);
         break;
+    }
     default:
         hipLaunchKernelGGL(srhd_c2p_kernel<2>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, chunks,
-                           n_units, part, gam, tol, maxit, md);
+                           n_units, part, gam, tol, maxit);
     }
     PB_HIP(hipGetLastError());
     b->pres_valid = true;
@@ -303,19 +406,15 @@ extern "C" pb_status con2prim(const void *cons, void *prim, int64_t n, double ga
     switch (guess) {
     case PB_GUESS_PLAIN:
         hipLaunchKernelGGL(con2prim_kernel<0>, dim3((unsigned)blocks), dim3(kC2pThreads), 0, s, cd, pd, (long long)n,
-                           gamma, tol, max_iter, pp, it, stp, cnt, md);
+                           gamma, tol, max_iter, pp, it, stp, cnt);
         break;
     case PB_GUESS_LEARNED:
-        // guesses go to prim[4] (the pressure row), which the solve overwrites
-        hipLaunchKernelGGL(flat_guess_kernel, dim3((unsigned)((blocks + kGuessGroups - 1) / kGuessGroups)),
-                           dim3(kC2pThreads), 0, s, cd, pd + 4 * n, (long long)n, gamma, md);
-        PB_HIP(hipGetLastError());
-        hipLaunchKernelGGL(con2prim_kernel<1>, dim3((unsigned)blocks), dim3(kC2pThreads), 0, s, cd, pd, (long long)n,
-                           gamma, tol, max_iter, pd + 4 * n, it, stp, cnt, md);
+        hipLaunchKernelGGL(con2prim_learned_kernel, dim3((unsigned)((blocks + kLearnChunks - 1) / kLearnChunks)),
+                           dim3(kC2pThreads), 0, s, cd, pd, (long long)n, gamma, tol, max_iter, it, stp, cnt, md.pack);
         break;
     default:
         hipLaunchKernelGGL(con2prim_kernel<2>, dim3((unsigned)blocks), dim3(kC2pThreads), 0, s, cd, pd, (long long)n,
-                           gamma, tol, max_iter, pp, it, stp, cnt, md);
+                           gamma, tol, max_iter, pp, it, stp, cnt);
     }
     PB_HIP(hipGetLastError());
     return PB_OK;

@@ -68,3 +68,21 @@ def test_features_match_conservative_scaling():
     # the internal-energy feature cancels O(E^2) terms down to O(rho eps E):
     # scaling changes its rounding, not its value
     np.testing.assert_allclose(f1[:, 4], f2[:, 4], rtol=0, atol=1e-8)
+
+
+def test_standardise_is_the_quotient_up_to_rounding():
+    """(x - m) * rn(1/s) against (x - m) / s: equal when s is a power of two
+    (exact reciprocal) and within 1.5 binary32 ulp otherwise (the product of
+    a half-ulp reciprocal error and a half-ulp product rounding)."""
+    x = I.normal(21, 4000).reshape(800, 5) * 3.0
+    norm = np.array([0.5, -1.0, 0.25, 2.0, -0.75, 2.0, 0.5, 4.0, 1.0, 0.125, 0.0, 1.0], np.float32)
+    z = M.standardise(x, norm, bf16=False)
+    x32 = x.astype(np.float32)
+    q = ((x32 - norm[:5]) / norm[5:10]).astype(np.float64)
+    np.testing.assert_array_equal(z, q)
+    norm2 = norm.copy()
+    norm2[5:10] = [0.3, 1.7, 2.9, 0.77, 5.3]
+    z2 = M.standardise(x, norm2, bf16=False)
+    q2 = ((x32 - norm2[:5]) / norm2[5:10]).astype(np.float32)
+    ulp = np.spacing(np.abs(q2)).astype(np.float64)
+    assert np.all(np.abs(z2 - q2.astype(np.float64)) <= 1.5 * ulp)
