@@ -5,27 +5,42 @@
 //   D4 u  = [(u_-2 - u_+2) + 8 (u_+1 - u_-1)] / (12 dx),
 //   KO6 u = sigma/(64 dx) [(u_-3 + u_+3) - 6 (u_-2 + u_+2) + 15 (u_-1 + u_+1) - 20 u_0].
 //
-// Work decomposition (MI355X): one persistent launch per RK stage.  Work
-// items are 4x4x4 cell tiles, listed largest patches first with the tiles of
-// a patch consecutive.  Every tile costs the same, so a static schedule is
-// balanced: work-group g takes a contiguous range of the list (neighbouring
-// tiles of one patch in sequence, their shared halo cells still in L2) and
-// no atomic queue is needed.  For a tile, the N unknowns are processed in
-// chunks of 16:
-//   1. the chunk's values on the tile's cross-shaped stencil footprint
-//      (64 cells + 3 layers on each of the 6 faces = 352 cells, periodic
-//      wrap inside the patch) are staged in LDS;
+// Work decomposition (MI355X): one persistent launch per RK stage, two
+// work-groups of four waves per CU.  Work items are 4x4x4 cell tiles, listed
+// largest patches first with the tiles of a patch consecutive; the launch
+// walks the list in rounds of gridDim.x items, and inside a round the
+// work-groups of one XCD take one contiguous run (one whole 16^3 patch), so a
+// patch is fetched into that XCD's L2 once.  For a tile, the N unknowns are
+// processed in chunks of 8:
+//   1. the chunk's values on the tile's stencil footprint are copied from HBM
+//      straight into LDS by the gfx950 global->LDS DMA loads (16 bytes = two
+//      x-adjacent cells per lane, no registers involved).  The footprint of
+//      one unknown is 384 doubles: 16 rows of 12 cells along x (the tile's
+//      rows with 4 halo cells on each side, one of them unused), and the 3
+//      halo layers on the -y, +y, -z, +z faces as rows of 4 cells;
+//      periodic wrap inside the patch.  The DMA for the next chunk (or the
+//      next tile's first chunk) is issued into the other of two buffers
+//      before the current chunk is computed, so HBM/L2 latency overlaps the
+//      arithmetic;
 //   2. every (unknown, cell) pair of the chunk gets D4_x, D4_y, D4_z (the
 //      gradient G_d, stored in LDS as matrix-core operands) and the summed
-//      KO6 term;
+//      KO6 term.  A thread always owns the same cell, so its 13 stencil
+//      addresses are computed once per launch;
 //   3. the dense product -sum_d B_d G_d runs on the FP64 matrix cores
 //      (v_mfma_f64_16x16x4f64): wave w owns output rows 16w..16w+15 and keeps
-//      its rows of -B_d (K padded to 64) in registers for the whole launch,
+//      its rows of -B_d (K padded to 60) in registers for the whole launch,
 //      accumulating over chunks and directions;
 // then the stage update (RK4 Butcher weights) is applied in the matrix-core
 // output layout.  For v_mfma_f64_16x16x4f64 lane l holds A[l%16][l/16] and
 // B[l/16][l%16] and its four result registers i hold D[4i + l/16][l%16]
 // (rows step by 4 across registers; checked on the device).
+//
+// Barriers: the plain work-group barrier also waits for every outstanding
+// memory operation of the wave (including the DMA just issued for the next
+// chunk), which would serialise the pipeline.  The kernel therefore waits
+// explicitly (vmcnt: all but the DMA issued for the next chunk; lgkmcnt: LDS
+// writes) and then issues the bare barrier instruction, with a compiler
+// memory clobber so no LDS access moves across it.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -37,42 +52,41 @@ namespace pb {
 namespace {
 
 typedef double f64x4_t __attribute__((ext_vector_type(4)));
+#define PB_LDS(ptr) ((__attribute__((address_space(3))) void *)(ptr))
 
 constexpr int kFdThreads = 256;
-constexpr int kT = 4;                 // tile edge
-constexpr int kTC = kT * kT * kT;     // 64 cells per tile
-constexpr int kCh = 16;               // unknowns per chunk
-constexpr int kFoot = kTC + 6 * 3 * kT * kT;  // 352 footprint cells
-constexpr int kMaxN = 60;   // K of the dense product padded to a multiple of 4
+constexpr int kT = 4;                  // tile edge
+constexpr int kTC = kT * kT * kT;      // 64 cells per tile
+constexpr int kCh = 8;                 // unknowns per chunk
+constexpr int kMaxCh = 8;              // chunks per tile (N <= 60, rounded up to even)
+constexpr int kRowX = 12;              // x-extended row: x in [-4, 8)
+constexpr int kRegY = 16 * kRowX;      // 192: first y-halo row
+constexpr int kRegZ = kRegY + 24 * kT; // 288: first z-halo row
+constexpr int kFoot = kRegZ + 24 * kT; // 384 doubles per unknown
+constexpr int kMaxN = 60;              // K of the dense product padded to a multiple of 4
 
-// footprint slot of tile-local coordinates (x, y, z), at most one of them
-// outside [0, 4) and then by at most 3
+// LDS slot of tile-local (x, y, z), at most one coordinate outside [0, 4)
+// (x in [-4, 8), y and z in [-3, 7))
 __device__ __forceinline__ int foot_slot(int x, int y, int z)
 {
-    if (x < 0) return kTC + 0 * 48 + (x + 3) * 16 + z * 4 + y;
-    if (x >= kT) return kTC + 1 * 48 + (x - kT) * 16 + z * 4 + y;
-    if (y < 0) return kTC + 2 * 48 + (y + 3) * 16 + z * 4 + x;
-    if (y >= kT) return kTC + 3 * 48 + (y - kT) * 16 + z * 4 + x;
-    if (z < 0) return kTC + 4 * 48 + (z + 3) * 16 + y * 4 + x;
-    if (z >= kT) return kTC + 5 * 48 + (z - kT) * 16 + y * 4 + x;
-    return (z * kT + y) * kT + x;
+    if (y < 0 || y >= kT) return kRegY + (z * 6 + (y < 0 ? y + 3 : y - 1)) * kT + x;
+    if (z < 0 || z >= kT) return kRegZ + (y * 6 + (z < 0 ? z + 3 : z - 1)) * kT + x;
+    return (z * kT + y) * kRowX + x + 4;
 }
 
-// inverse: slot -> tile-local coordinates
-__device__ __forceinline__ void foot_coord(int s, int &x, int &y, int &z)
+// first cell (x, x + 1 share the piece) of 16-byte piece q of the footprint,
+// in LDS order: piece q fills slots 2q and 2q + 1
+__device__ __forceinline__ void piece_coord(int q, int &x, int &y, int &z)
 {
-    if (s < kTC) {
-        x = s % kT; y = (s / kT) % kT; z = s / (kT * kT);
-        return;
-    }
-    const int f = (s - kTC) / 48, r = (s - kTC) % 48, layer = r / 16, a = (r / 4) % 4, b = r % 4;
-    switch (f) {
-    case 0: x = layer - 3; z = a; y = b; break;
-    case 1: x = kT + layer; z = a; y = b; break;
-    case 2: y = layer - 3; z = a; x = b; break;
-    case 3: y = kT + layer; z = a; x = b; break;
-    case 4: z = layer - 3; y = a; x = b; break;
-    default: z = kT + layer; y = a; x = b; break;
+    if (q < kRegY / 2) {
+        const int r = q / 6;
+        z = r / kT; y = r % kT; x = -4 + 2 * (q % 6);
+    } else if (q < kRegZ / 2) {
+        const int qq = q - kRegY / 2, r = qq / 2, yy = r % 6;
+        z = r / 6; y = yy < 3 ? yy - 3 : yy + 1; x = 2 * (qq % 2);
+    } else {
+        const int qq = q - kRegZ / 2, r = qq / 2, zz = r % 6;
+        y = r / 6; z = zz < 3 ? zz - 3 : zz + 1; x = 2 * (qq % 2);
     }
 }
 
@@ -81,16 +95,77 @@ struct FdItem {
     int tile;
 };
 
+// geometry of one tile as this lane needs it for the DMA
+struct TileSrc {
+    const double *base;   // y + offset of the patch's block
+    long long C;          // cells of the patch (unknown stride)
+    int fo[3];            // cell offset (< p^3) of this lane's piece in each of the 3 DMA rounds
+};
+
+__device__ __forceinline__ TileSrc tile_src(const double *y, long long off, int p, int tile, int N)
+{
+    TileSrc t;
+    const int nt = p / kT;
+    t.C = (long long)p * p * p;
+    t.base = y + off * N;
+    const int tx = kT * (tile % nt), ty = kT * ((tile / nt) % nt), tz = kT * (tile / (nt * nt));
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        int x, yy, z;
+        piece_coord(64 * i + l, x, yy, z);
+        t.fo[i] = (((tz + z + p) % p) * p + (ty + yy + p) % p) * p + (tx + x + p) % p;
+    }
+    return t;
+}
+
+// DMA of unknowns v0 + 2w, v0 + 2w + 1 (wave w) of one tile into buf;
+// returns the number of DMA instructions this wave issued
+__device__ __forceinline__ int issue_chunk(double (&buf)[kCh][kFoot], const TileSrc &t, int v0, int N)
+{
+    const int w = threadIdx.x >> 6;
+    int n = 0;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int vl = 2 * w + u, v = v0 + vl;
+        if (v < N) {
+            const double *src = t.base + (long long)v * t.C;
+#pragma unroll
+            for (int i = 0; i < 3; ++i)
+                __builtin_amdgcn_global_load_lds(src + t.fo[i], PB_LDS(&buf[vl][128 * i]), 16, 0, 0);
+            n += 3;
+        }
+    }
+    return n;
+}
+
+// wait until this wave has at most `pending` vector-memory operations in
+// flight (the DMA just issued for the next chunk) and its LDS writes are
+// done, then the work-group barrier
+__device__ __forceinline__ void barrier_keep(int pending)
+{
+    if (pending >= 6) __builtin_amdgcn_s_waitcnt(0x0076);
+    else if (pending >= 3) __builtin_amdgcn_s_waitcnt(0x0073);
+    else __builtin_amdgcn_s_waitcnt(0x0070);
+    __asm__ volatile("s_barrier" ::: "memory");
+}
+
+// LDS writes done, then the work-group barrier
+__device__ __forceinline__ void barrier_lds()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    __asm__ volatile("s_barrier" ::: "memory");
+}
+
 }  // namespace
 
 // stage: 0..3 (RK4) with rk = 4, or 0 with rk = 1
 __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
     const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
     double *__restrict__ acc, const PatchDev *__restrict__ patches, const FdItem *__restrict__ items, int n_items,
-    const double *__restrict__ Bmat, int N, int stage, int rk, double dt,
-    double sigma, int remap)
+    const double *__restrict__ Bmat, int N, int stage, int rk, double dt, double sigma, int remap)
 {
-    __shared__ double sQ[kCh][kFoot];
+    __shared__ double sQ0[kCh][kFoot], sQ1[kCh][kFoot];
     __shared__ double sG[3][kCh][kTC];
     __shared__ double sK[kCh][kTC];
 
@@ -107,158 +182,184 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
                 a[d][ks] = (m < N && k < N) ? -Bmat[(long long)d * N * N + (long long)m * N + k] : 0.0;
             }
     }
-    const int nch = (N + kCh - 1) / kCh;
+    // chunks per tile, even so that every tile starts in buffer 0
+    const int nch = (((N + kCh - 1) / kCh) + 1) & ~1;
+    // this thread's cell of the gradient phase (the same in every chunk) and
+    // its stencil slots
+    const int cx = l % kT, cy = (l / kT) % kT, cz = l / (kT * kT);
+    const int sc = foot_slot(cx, cy, cz);
+    int sy[6], sz[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sy[k] = foot_slot(cx, cy - 3 + k, cz);
+        sy[3 + k] = foot_slot(cx, cy + 1 + k, cz);
+        sz[k] = foot_slot(cx, cy, cz - 3 + k);
+        sz[3 + k] = foot_slot(cx, cy, cz + 1 + k);
+    }
 
-    // rounds of gridDim.x consecutive items; inside a round the workgroups
-    // of one XCD (blockIdx mod 8) take one contiguous run of items, so the
-    // tiles of a patch share that XCD's L2 instead of fetching the patch
-    // once per XCD
     const int G = (int)gridDim.x, slot = remap ? xcd_remap((int)blockIdx.x, G) : (int)blockIdx.x;
-    for (int base = 0; base + slot < n_items; base += G) {
-        const FdItem item = items[base + slot];
+    int it = slot;
+    if (it >= n_items) return;
+    // current tile: patch block offset, edge, 1/dx, tile index, DMA sources
+    long long off;
+    int p, tile;
+    double inv_dx;
+    TileSrc src;
+    {
+        const FdItem item = items[it];
         const PatchDev P = patches[item.patch];
-        const int p = P.p, ntile = p / kT;
-        const long long C = (long long)p * p * p;
-        const int tx = kT * (item.tile % ntile), ty = kT * ((item.tile / ntile) % ntile),
-                  tz = kT * (item.tile / (ntile * ntile));
-        const double idx = P.inv_dx;
-        const double c4 = idx / 12.0, cko = sigma * idx / 64.0;
+        off = P.off; p = P.p; inv_dx = P.inv_dx; tile = item.tile;
+        src = tile_src(y, off, p, tile, N);
+    }
+    issue_chunk(sQ0, src, 0, N);
+
+    while (true) {
+        const int ntile = p / kT;
+        const long long C = src.C;
+        const int tx = kT * (tile % ntile), ty = kT * ((tile / ntile) % ntile), tz = kT * (tile / (ntile * ntile));
+        const double c4 = inv_dx / 12.0, cko = sigma * inv_dx / 64.0;
+        // the next tile of this work-group (its first chunk is prefetched
+        // during the last chunk of this one)
+        const int itn = it + G;
+        const bool has_next = itn < n_items;
+        long long offn = off;
+        int pn = p, tilen = tile;
+        double inv_dxn = inv_dx;
+        TileSrc srcn = src;
+        if (has_next) {
+            const FdItem item = items[itn];
+            const PatchDev P = patches[item.patch];
+            offn = P.off; pn = P.p; inv_dxn = P.inv_dx; tilen = item.tile;
+            srcn = tile_src(y, offn, pn, tilen, N);
+        }
         f64x4_t accm[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) accm[nt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
-        // this thread stages footprint slots t and t + 256 (the latter for
-        // t < 96); their cell offsets inside the patch are fixed for the tile
-        const int s1 = t + kFdThreads;
-        const bool has1 = s1 < kFoot;
-        long long fo0, fo1 = 0;
-        {
-            int x, yy, z;
-            foot_coord(t, x, yy, z);
-            fo0 = ((long long)((tz + z + p) % p) * p + (ty + yy + p) % p) * p + (tx + x + p) % p;
-            if (has1) {
-                foot_coord(s1, x, yy, z);
-                fo1 = ((long long)((tz + z + p) % p) * p + (ty + yy + p) % p) * p + (tx + x + p) % p;
-            }
-        }
-        const double *ybase = y + P.off * N;
 
 #pragma unroll
-        for (int ch = 0; ch < (kMaxN + kCh - 1) / kCh; ++ch) {
+        for (int ch = 0; ch < kMaxCh; ++ch) {
             if (ch >= nch) break;
+            double (&buf)[kCh][kFoot] = (ch & 1) ? sQ1 : sQ0;
+            double (&nbuf)[kCh][kFoot] = (ch & 1) ? sQ0 : sQ1;
             const int v0 = ch * kCh;
-            // 1. stage the footprint of unknowns v0..v0+15: all loads of a
-            //    slot are issued before its LDS stores
-            {
-                double r0[kCh];
-#pragma unroll
-                for (int vl = 0; vl < kCh; ++vl)
-                    r0[vl] = (v0 + vl < N) ? ybase[(long long)(v0 + vl) * C + fo0] : 0.0;
-#pragma unroll
-                for (int vl = 0; vl < kCh; ++vl) sQ[vl][t] = r0[vl];
+            // 1. prefetch the next chunk, then wait for this one
+            int pend = 0;
+            if (ch + 1 < nch) {
+                pend = issue_chunk(nbuf, src, v0 + kCh, N);
+            } else if (has_next) {
+                pend = issue_chunk(nbuf, srcn, 0, N);
             }
-            if (has1) {
-                double r1[kCh];
+            barrier_keep(pend);
+            // 2. gradients and dissipation of the chunk (cell l, unknowns w, w + 4)
 #pragma unroll
-                for (int vl = 0; vl < kCh; ++vl)
-                    r1[vl] = (v0 + vl < N) ? ybase[(long long)(v0 + vl) * C + fo1] : 0.0;
-#pragma unroll
-                for (int vl = 0; vl < kCh; ++vl) sQ[vl][s1] = r1[vl];
+            for (int j = 0; j < 2; ++j) {
+                const int vl = w + 4 * j;
+                double g0 = 0.0, g1 = 0.0, g2 = 0.0, ko = 0.0;
+                if (v0 + vl < N) {
+                    const double *u = buf[vl];
+                    const double u0 = u[sc];
+                    {
+                        const double m3 = u[sc - 3], m2 = u[sc - 2], m1 = u[sc - 1], p1 = u[sc + 1], p2 = u[sc + 2],
+                                     p3 = u[sc + 3];
+                        g0 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                        ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                    }
+                    {
+                        const double m3 = u[sy[0]], m2 = u[sy[1]], m1 = u[sy[2]], p1 = u[sy[3]], p2 = u[sy[4]],
+                                     p3 = u[sy[5]];
+                        g1 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                        ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                    }
+                    {
+                        const double m3 = u[sz[0]], m2 = u[sz[1]], m1 = u[sz[2]], p1 = u[sz[3]], p2 = u[sz[4]],
+                                     p3 = u[sz[5]];
+                        g2 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                        ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                    }
+                }
+                sG[0][vl][l] = g0;
+                sG[1][vl][l] = g1;
+                sG[2][vl][l] = g2;
+                sK[vl][l] = cko * ko;
             }
-            __syncthreads();
-            // 2. gradients and dissipation of the chunk
-            for (int e = t; e < kCh * kTC; e += kFdThreads) {
-                const int vl = e / kTC, c = e - vl * kTC;
-                const int x = c % kT, yy = (c / kT) % kT, z = c / (kT * kT);
-                const double *u = sQ[vl];
-                const double u0 = u[c];
-                double ko = 0.0;
-                // x
-                {
-                    const double m3 = u[foot_slot(x - 3, yy, z)], m2 = u[foot_slot(x - 2, yy, z)],
-                                 m1 = u[foot_slot(x - 1, yy, z)], p1 = u[foot_slot(x + 1, yy, z)],
-                                 p2 = u[foot_slot(x + 2, yy, z)], p3 = u[foot_slot(x + 3, yy, z)];
-                    sG[0][vl][c] = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
-                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
-                }
-                // y
-                {
-                    const double m3 = u[foot_slot(x, yy - 3, z)], m2 = u[foot_slot(x, yy - 2, z)],
-                                 m1 = u[foot_slot(x, yy - 1, z)], p1 = u[foot_slot(x, yy + 1, z)],
-                                 p2 = u[foot_slot(x, yy + 2, z)], p3 = u[foot_slot(x, yy + 3, z)];
-                    sG[1][vl][c] = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
-                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
-                }
-                // z
-                {
-                    const double m3 = u[foot_slot(x, yy, z - 3)], m2 = u[foot_slot(x, yy, z - 2)],
-                                 m1 = u[foot_slot(x, yy, z - 1)], p1 = u[foot_slot(x, yy, z + 1)],
-                                 p2 = u[foot_slot(x, yy, z + 2)], p3 = u[foot_slot(x, yy, z + 3)];
-                    sG[2][vl][c] = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
-                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
-                }
-                sK[vl][c] = cko * ko;
-            }
-            __syncthreads();
+            barrier_lds();
             // 3. accumulate -B_d G_d over the chunk's K rows on the matrix cores
+            if (v0 < N) {
 #pragma unroll
-            for (int d = 0; d < 3; ++d)
+                for (int d = 0; d < 3; ++d)
 #pragma unroll
-                for (int kk = 0; kk < kCh / 4; ++kk) {
-                    if (ch * (kCh / 4) + kk >= kMaxN / 4) break;
-                    const double aop = a[d][ch * (kCh / 4) + kk];
+                    for (int kk = 0; kk < kCh / 4; ++kk) {
+                        const int ks = ch * (kCh / 4) + kk;
+                        if (ks >= kMaxN / 4) break;
+                        const double aop = a[d][ks];
+#pragma unroll
+                        for (int nt = 0; nt < 4; ++nt)
+                            accm[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, sG[d][4 * kk + lg][nt * 16 + lj],
+                                                                            accm[nt], 0, 0, 0);
+                    }
+                // the wave whose output rows are this chunk's unknowns adds KO6
+                if (w == ch / 2) {
+                    const int h = ch % 2;
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt)
-                        accm[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, sG[d][4 * kk + lg][nt * 16 + lj],
-                                                                        accm[nt], 0, 0, 0);
-                }
-            // the chunk whose unknowns are this wave's output rows adds KO6
-            if (ch == w) {
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) accm[nt][i] += sK[lg + 4 * i][nt * 16 + lj];
-            }
-            __syncthreads();
-        }
-        // 4. stage update in the output layout, four rows at a time: reads
-        //    first, then the arithmetic and the stores
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const int c = nt * 16 + lj;
-            const int x = c % kT, yy = (c / kT) % kT, z = c / (kT * kT);
-            const long long cell = ((long long)(tz + z) * p + (ty + yy)) * p + (tx + x);
-            long long gidx[4];
-            double q0v[4], accv[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = 16 * w + lg + 4 * i;
-                const bool ok = r < N;
-                gidx[i] = P.off * N + (long long)(ok ? r : 0) * C + cell;
-                q0v[i] = (ok && (rk == 1 || stage < 3)) ? q0[gidx[i]] : 0.0;
-                accv[i] = (ok && rk == 4 && stage > 0) ? acc[gidx[i]] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = 16 * w + lg + 4 * i;
-                if (r >= N) continue;
-                const long long g = gidx[i];
-                const double R = accm[nt][i];
-                if (rk == 1) {
-                    acc[g] = q0v[i] + dt * R;
-                } else if (stage == 0) {
-                    ynext[g] = q0v[i] + 0.5 * dt * R;
-                    acc[g] = q0v[i] + (dt / 6.0) * R;
-                } else if (stage == 1) {
-                    ynext[g] = q0v[i] + 0.5 * dt * R;
-                    acc[g] = accv[i] + (dt / 3.0) * R;
-                } else if (stage == 2) {
-                    ynext[g] = q0v[i] + dt * R;
-                    acc[g] = accv[i] + (dt / 3.0) * R;
-                } else {
-                    acc[g] = accv[i] + (dt / 6.0) * R;
+                        for (int ii = 0; ii < 2; ++ii) accm[nt][2 * h + ii] += sK[lg + 4 * ii][nt * 16 + lj];
                 }
             }
         }
+        // 4. stage update in the output layout, in two rounds of two column
+        //    tiles: all reads of a round first (one memory round trip), then
+        //    the arithmetic and the stores
+        {
+            const bool need_q0 = rk == 1 || stage < 3, need_acc = rk == 4 && stage > 0;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                long long gbase[2];
+                double q0v[2][4], accv[2][4];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int c = (2 * half + h) * 16 + lj;
+                    const int x = c % kT, yy = (c / kT) % kT, z = c / (kT * kT);
+                    gbase[h] = off * N + ((long long)(tz + z) * p + (ty + yy)) * p + (tx + x);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * w + lg + 4 * i;
+                        const long long g = gbase[h] + (long long)(r < N ? r : 0) * C;
+                        q0v[h][i] = (r < N && need_q0) ? q0[g] : 0.0;
+                        accv[h][i] = (r < N && need_acc) ? acc[g] : 0.0;
+                    }
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * w + lg + 4 * i;
+                        if (r >= N) continue;
+                        const long long g = gbase[h] + (long long)r * C;
+                        const double R = accm[2 * half + h][i];
+                        if (rk == 1) {
+                            acc[g] = q0v[h][i] + dt * R;
+                        } else if (stage == 0) {
+                            ynext[g] = q0v[h][i] + 0.5 * dt * R;
+                            acc[g] = q0v[h][i] + (dt / 6.0) * R;
+                        } else if (stage == 1) {
+                            ynext[g] = q0v[h][i] + 0.5 * dt * R;
+                            acc[g] = accv[h][i] + (dt / 3.0) * R;
+                        } else if (stage == 2) {
+                            ynext[g] = q0v[h][i] + dt * R;
+                            acc[g] = accv[h][i] + (dt / 3.0) * R;
+                        } else {
+                            acc[g] = accv[h][i] + (dt / 6.0) * R;
+                        }
+                    }
+            }
+        }
+        if (!has_next) break;
+        it = itn;
+        off = offn; p = pn; inv_dx = inv_dxn; tile = tilen;
+        src = srcn;
     }
 }
 
