@@ -270,6 +270,11 @@ typedef struct {
     int32_t fd_xcd_remap;     /* FD: 1 = each XCD takes a contiguous run of tiles
                                  (the tiles of one patch share its L2) */
     int32_t fd_wg_per_cu;     /* FD: resident work-groups per CU, 1 or 2 (0 = 2) */
+    int32_t fv_dma;           /* FV 3D: 1 = the DMA-fed kernel (state planes copied
+                                 HBM -> LDS three planes ahead) where the batch
+                                 allows it (no SRHD, every p a multiple of 4,
+                                 16-byte aligned state), 0 = the register-prefetch
+                                 kernel (the default) */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
@@ -284,7 +289,8 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  * kind 0 = the finite-volume step (fv_rusanov_step with the given cfl /
  * dt_fixed), kind 1 = one FD4+KO6 stage (fd_ko_step with sigma_ko; cfl /
  * dt_fixed as there).  Candidates:
- *   FV 3D: fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0};
+ *   FV 3D: fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0}
+ *          x fv_dma {1, 0} (only 0 where the DMA-fed kernel does not apply);
  *   FV 2D: fv_xcd_remap {1, 0};
  *   FD:    fd_xcd_remap {1, 0} x fd_wg_per_cu {2, 1}.
  * Each candidate runs one untimed launch and then `trials` timed launches
@@ -314,7 +320,7 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
                       int32_t use_cache, pb_autotune_result *out);
 
 /* The process-wide tuning cache as a text file, one entry per line:
- * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu>".
+ * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma>".
  * save writes every entry (replacing the file); load adds the file's entries
  * (a later entry of the same key wins) and stores their number in *n_loaded
  * (nullable).  Host-only; PB_EINVAL on a file that cannot be opened or a

@@ -70,6 +70,31 @@ __device__ __forceinline__ unsigned long long dbits(double v)
 // Work-group order -> unit order such that the units one XCD runs (the
 // hardware deals work-groups round-robin over the 8 XCDs) are consecutive:
 // neighbouring patches then share that XCD's L2 for their halo reads.
+// Global -> LDS DMA (gfx950 global_load_lds_dword / _dwordx4): every active
+// lane copies 4 / 16 bytes from its global address to lds + 4 / 16 * lane.
+// The destination is wave-uniform (M0).  They are issued from inline
+// assembly on purpose: the compiler then does not add conservative waits for
+// them before unrelated LDS reads (its alias tracking of such copies gives up
+// when a kernel has many of them), and the callers wait explicitly
+// (s_waitcnt vmcnt) before they read the copied data.  The instructions have
+// no register results; the memory clobber keeps LDS accesses in order.
+__device__ __forceinline__ unsigned lds_address(const void *p)
+{
+    return (unsigned)(size_t)((__attribute__((address_space(3))) const void *)p);
+}
+
+__device__ __forceinline__ void dma_to_lds16(const void *g, const void *lds)
+{
+    const unsigned a = __builtin_amdgcn_readfirstlane(lds_address(lds));
+    __asm__ volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dwordx4 %1, off" : : "s"(a), "v"(g) : "memory", "m0");
+}
+
+__device__ __forceinline__ void dma_to_lds4(const void *g, const void *lds)
+{
+    const unsigned a = __builtin_amdgcn_readfirstlane(lds_address(lds));
+    __asm__ volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off" : : "s"(a), "v"(g) : "memory", "m0");
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int n)
 {
     const int q = n >> 3, r = n & 7;
@@ -105,6 +130,7 @@ struct pb_batch {
     int fv_xcd_remap = 1;
     int fd_xcd_remap = 1;
     int fd_wg_per_cu = 2;
+    int fv_dma = 0;
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
@@ -151,6 +177,9 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
                           hipStream_t s);
 pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y,
                           void *ynext, void *acc, double dt, double sigma, hipStream_t s);
+// the DMA-fed FV kernel applies to this batch (3D, no extra per-cell input,
+// every p a multiple of 4, 16-byte aligned state buffers)
+bool fv_dma_eligible(const pb_batch *b);
 // dt of an FD step: dt_fixed if > 0, else cfl / sum_d (rho(B_d) / dx_min)
 double fd_dt(const pb_batch *b, double cfl, double dt_fixed);
 // uploads the FD work list and B_d (library-owned; done once, before any capture)

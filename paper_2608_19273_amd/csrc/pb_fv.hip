@@ -332,6 +332,283 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     if (kLam) store_partial<DIM>(part, lm, unit, n_units);
 }
 
+// ---------------------------------------------------------------------------
+// DMA-fed variant of the same step (3D, no extra per-cell input, p a
+// multiple of 4): the state planes do not pass through registers.  Each
+// plane of the slab (interior p x p cells and the four face-halo strips read
+// from the neighbours) is copied HBM/L2 -> LDS by the gfx950 global->LDS DMA
+// loads three planes ahead into a ring of four plane buffers, so about three
+// planes of loads per work-group are always in flight and the waves only
+// compute.  Interior and +-y strips move in 16-byte pieces, the strided
+// +-x strips as 4-byte words.  Per plane z the work-group
+//   1. writes the aux of its cells (computed one plane earlier) and of the
+//      halo cells (computed now from the halo strips in LDS) to LDS;
+//   2. waits for the DMA of plane z+1 (exact vmcnt: only the DMA and stores
+//      issued after it may still be in flight) and meets at a bare barrier;
+//   3. issues the DMA of plane z+3 into the buffer plane z-1 used;
+//   4. evaluates the faces and updates the cell exactly as fv_step_kernel.
+// The plane loop is dispatched on z % 4 to four copies of the body, each
+// naming its buffers statically, so the compiler can tell the ring's buffers
+// apart and does not wait for DMA into a buffer it is not reading.
+namespace {
+
+constexpr int kDmaNP = kFvPmax * kFvPmax + 4 * kFvPmax;   // slots per unknown and plane
+
+// the wave index, as a value the compiler knows is the same in every lane
+__device__ __forceinline__ int wave_index() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6); }
+
+// wait until at most n of this wave's vector-memory operations are in flight
+__device__ __forceinline__ void wait_vm(int n)
+{
+    switch (n) {
+    case 0: __builtin_amdgcn_s_waitcnt(0x0070); break;
+    case 1: __builtin_amdgcn_s_waitcnt(0x0071); break;
+    case 2: __builtin_amdgcn_s_waitcnt(0x0072); break;
+    case 3: __builtin_amdgcn_s_waitcnt(0x0073); break;
+    case 4: __builtin_amdgcn_s_waitcnt(0x0074); break;
+    case 5: __builtin_amdgcn_s_waitcnt(0x0075); break;
+    case 6: __builtin_amdgcn_s_waitcnt(0x0076); break;
+    case 7: __builtin_amdgcn_s_waitcnt(0x0077); break;
+    case 8: __builtin_amdgcn_s_waitcnt(0x0078); break;
+    case 9: __builtin_amdgcn_s_waitcnt(0x0079); break;
+    case 10: __builtin_amdgcn_s_waitcnt(0x007a); break;
+    case 11: __builtin_amdgcn_s_waitcnt(0x007b); break;
+    case 12: __builtin_amdgcn_s_waitcnt(0x007c); break;
+    case 13: __builtin_amdgcn_s_waitcnt(0x007d); break;
+    case 14: __builtin_amdgcn_s_waitcnt(0x007e); break;
+    default: __builtin_amdgcn_s_waitcnt(0x007f); break;   // 15 (larger counts are clamped down: still safe)
+    }
+}
+
+// the bare work-group barrier (no memory fence: callers wait for what they need)
+__device__ __forceinline__ void bare_barrier() { __asm__ volatile("s_barrier" ::: "memory"); }
+
+// DMA of one plane (plane index zl inside the source patch `own` for the
+// interior; the halo strips from the face neighbours) into buf[N][kDmaNP].
+// Jobs: per unknown `ji` interior pieces of 1 KB, one +-x job, one +-y job;
+// job k runs on wave k % 4.  Every wave issues the same number of DMA
+// instructions in every plane (lanes without data are masked).
+__device__ __forceinline__ void dma_plane(void *buf_v, const void *q_v, int esz, int N, long long C, int p,
+                                          long long own, const long long *onb, int zl, int ji, int w)
+{
+    char *buf = static_cast<char *>(buf_v);
+    const char *q = static_cast<const char *>(q_v);
+    const int epp = 16 / esz;   // elements per 16-byte piece
+    const int dpe = esz / 4;    // 4-byte words per element
+    const int L = threadIdx.x & 63;
+    const long long pp = (long long)p * p;
+    const int J = N * (ji + 2);
+    for (int k = w; k < J; k += 4) {
+        const int v = k / (ji + 2), r = k - v * (ji + 2);
+        char *dst = buf + (long long)v * kDmaNP * esz;
+        const long long row = (long long)v * C + zl * pp;   // element offset of the plane row in a patch block
+        if (r < ji) {
+            const int piece = 64 * r + L;
+            if (piece * epp < pp)
+                dma_to_lds16(q + (own * N + row + (long long)piece * epp) * esz, dst + 1024 * r);
+        } else if (r == ji) {
+            const int j = L / dpe, word = L - j * dpe;
+            if (j < 2 * p) {
+                const int side = j / p, yy = j - side * p;
+                const long long e = onb[side] * N + row + (long long)yy * p + (side == 0 ? p - 1 : 0);
+                dma_to_lds4(q + e * esz + 4 * word, dst + pp * esz);
+            }
+        } else {
+            const int pps = p / epp;   // pieces per strip
+            if (L < 2 * pps) {
+                const int side = L / pps, kk = L - side * pps;
+                const long long e = onb[2 + side] * N + row + (long long)(side == 0 ? p - 1 : 0) * p + kk * epp;
+                dma_to_lds16(q + e * esz, dst + (pp + 2 * p) * esz);
+            }
+        }
+    }
+}
+
+}  // namespace
+
+template <class Ph, typename T, bool kLam>
+__global__ __launch_bounds__(kFvThreads, 2) void fv_step_dma_kernel(
+    const T *__restrict__ qin, T *__restrict__ qout, const PatchDev *__restrict__ patches, int n_units,
+    int n_slabs, int slab, int remap, Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in,
+    double dt_fixed, Ph ph)
+{
+    constexpr int N = Ph::N, A = Ph::A, AA = A > 0 ? A : 1;
+    static_assert(Ph::E == 0, "the DMA variant has no extra per-cell input");
+    __shared__ T sq0[N * kDmaNP], sq1[N * kDmaNP], sq2[N * kDmaNP], sq3[N * kDmaNP];
+    __shared__ double sa[2][AA][kDmaNP];
+
+    const int t = threadIdx.x, w = wave_index();
+    const int unit = remap ? xcd_remap(blockIdx.x, n_units) : (int)blockIdx.x;
+    const int k = unit / n_slabs, sl = unit - k * n_slabs;
+    const PatchDev P = patches[k];
+    const int p = P.p;
+    const long long C = (long long)p * p * p, pp = (long long)p * p;
+    long long onb[6];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) onb[f] = patches[P.nbr[f]].off;
+    const int z0 = sl * slab, z1 = min(p, z0 + slab);
+    const bool work = z0 < p;
+    const bool active = work && t < pp;
+    const int x = active ? t % p : 0, y = active ? t / p : 0;
+    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot_in];
+    const double hr_ = 0.5 * dt * P.inv_dx;
+    // LDS slots of the cell and its four in-plane neighbours (halo strips
+    // follow the p x p interior: -x, +x, -y, +y, p cells each)
+    const int li = y * p + x;
+    const int lxm = x == 0 ? (int)pp + y : li - 1, lxp = x == p - 1 ? (int)pp + p + y : li + 1;
+    const int lym = y == 0 ? (int)pp + 2 * p + x : li - p, lyp = y == p - 1 ? (int)pp + 3 * p + x : li + p;
+    // halo cells whose aux this thread evaluates: wave w serves strip w
+    const int j = t & 63;
+    const bool halo = work && j < p;
+    const int hslot = (int)pp + w * p + j;
+    // DMA instructions per wave and plane, and stores per wave and plane
+    const int ji = (int)((pp * (long long)sizeof(T) + 1023) / 1024);
+    const int J = N * (ji + 2);
+    const int dw = (J - w + 3) / 4;
+    const int sw = (64 * w < pp) ? N : 0;
+
+    double lm[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    if (work) {
+        double qc[N], ac[AA], fzc[N], fs2l[N], dn2l[N], e[1] = {0.0};
+        double lzc = 0.0;
+        auto src_of = [&](int zz) __device__ -> long long { return zz >= p ? onb[5] : P.off; };
+        auto dma = [&](int zz) __device__ {   // plane zz into ring buffer zz % 4
+            T *b = (zz & 3) == 0 ? sq0 : (zz & 3) == 1 ? sq1 : (zz & 3) == 2 ? sq2 : sq3;
+            dma_plane(b, qin, (int)sizeof(T), N, C, p, src_of(zz), onb, zz >= p ? zz - p : zz, ji, w);
+        };
+        auto d_of = [&](int zz) __device__ { return zz <= z1 ? dw : 0; };
+        // the plane below the slab (for the first z face): a register load,
+        // issued before the DMA so that waiting for it leaves the DMA in flight
+        double qm[N];
+        if (active) {
+            const long long om = (z0 == 0) ? onb[4] : P.off;
+            const int zm = (z0 == 0) ? p - 1 : z0 - 1;
+            const T *b = qin + om * N + (long long)zm * pp + li;
+#pragma unroll
+            for (int v = 0; v < N; ++v) qm[v] = (double)b[(long long)v * C];
+        }
+        dma(z0);
+        if (z0 + 1 <= z1) dma(z0 + 1);
+        if (z0 + 2 <= z1) dma(z0 + 2);
+        wait_vm(d_of(z0 + 1) + d_of(z0 + 2));
+        bare_barrier();
+        if (active) {
+            const T *cb = (z0 & 3) == 0 ? sq0 : (z0 & 3) == 1 ? sq1 : (z0 & 3) == 2 ? sq2 : sq3;
+#pragma unroll
+            for (int v = 0; v < N; ++v) qc[v] = (double)cb[v * kDmaNP + li];
+            double am[AA], fzm[N];
+            ph.aux(qm, e, am);
+            phys_flux_or_zero<Ph, 2>(ph, qm, am, fzm);
+            ph.aux(qc, e, ac);
+            phys_flux_or_zero<Ph, 2>(ph, qc, ac, fzc);
+            lzc = ph.template eig<2>(qc, ac);
+            rusanov_face2<Ph, 2>(ph, qm, fzm, ph.template eig<2>(qm, am), qc, fzc, lzc, fs2l, dn2l);
+        }
+
+        auto plane = [&](auto bufc, int z) __device__ {
+            constexpr int B = decltype(bufc)::value;
+            T *cur = B == 0 ? sq0 : B == 1 ? sq1 : B == 2 ? sq2 : sq3;
+            T *nxt = B == 3 ? sq0 : B == 0 ? sq1 : B == 1 ? sq2 : sq3;
+            T *prv = B == 1 ? sq0 : B == 2 ? sq1 : B == 3 ? sq2 : sq3;   // buffer of plane z-1 (= z+3)
+            double(*sab)[kDmaNP] = sa[z & 1];
+            // 1. aux of this plane's cells and halo cells to LDS
+            if (active) {
+#pragma unroll
+                for (int a = 0; a < A; ++a) sab[a][li] = ac[a];
+            }
+            if (halo) {
+                double hq[N], ha[AA];
+#pragma unroll
+                for (int v = 0; v < N; ++v) hq[v] = (double)cur[v * kDmaNP + hslot];
+                ph.aux(hq, e, ha);
+#pragma unroll
+                for (int a = 0; a < A; ++a) sab[a][hslot] = ha[a];
+            }
+            // 2. plane z+1 landed (all but the DMA and stores issued after it)
+            wait_vm(d_of(z + 2) + sw * min(2, z - z0));
+            __builtin_amdgcn_s_waitcnt(0xc07f);   // this wave's LDS writes done
+            bare_barrier();
+            // 3. prefetch plane z+3 into the buffer plane z-1 used
+            if (z + 3 <= z1)
+                dma_plane(prv, qin, (int)sizeof(T), N, C, p, src_of(z + 3), onb, z + 3 >= p ? z + 3 - p : z + 3, ji, w);
+            // 4. faces and update
+            if (active) {
+                double qn[N], an[AA], fzn[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) qn[v] = (double)nxt[v * kDmaNP + li];
+                ph.aux(qn, e, an);
+                phys_flux_or_zero<Ph, 2>(ph, qn, an, fzn);
+                const double lzn = ph.template eig<2>(qn, an);
+                double acc2[N];
+#pragma unroll
+                for (int v = 0; v < N; ++v) acc2[v] = 0.0;
+                {
+                    double qL[N], aL[AA], qR[N], aR[AA];
+#pragma unroll
+                    for (int v = 0; v < N; ++v) { qL[v] = (double)cur[v * kDmaNP + lxm]; qR[v] = (double)cur[v * kDmaNP + lxp]; }
+#pragma unroll
+                    for (int a = 0; a < A; ++a) { aL[a] = sab[a][lxm]; aR[a] = sab[a][lxp]; }
+                    rusanov_pair2<Ph, 0>(ph, qL, aL, qc, ac, qR, aR, acc2);
+                }
+                {
+                    double qL[N], aL[AA], qR[N], aR[AA];
+#pragma unroll
+                    for (int v = 0; v < N; ++v) { qL[v] = (double)cur[v * kDmaNP + lym]; qR[v] = (double)cur[v * kDmaNP + lyp]; }
+#pragma unroll
+                    for (int a = 0; a < A; ++a) { aL[a] = sab[a][lym]; aR[a] = sab[a][lyp]; }
+                    rusanov_pair2<Ph, 1>(ph, qL, aL, qc, ac, qR, aR, acc2);
+                }
+                {
+                    double fs2u[N], dn2u[N];
+                    rusanov_face2<Ph, 2>(ph, qc, fzc, lzc, qn, fzn, lzn, fs2u, dn2u);
+#pragma unroll
+                    for (int v = 0; v < N; ++v) {
+                        acc2[v] += (fs2u[v] - fs2l[v]) + (dn2u[v] + dn2l[v]);
+                        fs2l[v] = fs2u[v];
+                        dn2l[v] = dn2u[v];
+                    }
+                }
+                double S[N];
+                if (Ph::kSrc) {
+                    ph.source(qc, ac, S);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < N; ++v) S[v] = 0.0;
+                }
+                double qw[N];
+                T *dst = qout + P.off * N + (long long)z * pp + li;
+#pragma unroll
+                for (int v = 0; v < N; ++v) {
+                    const double nv = qc[v] - hr_ * acc2[v] + dt * S[v];
+                    const T st = (T)nv;
+                    __builtin_nontemporal_store(st, dst + (long long)v * C);
+                    qw[v] = (double)st;
+                    bad |= !isfinite(qw[v]);
+                }
+                if (kLam) cell_speeds_fast<Ph, 3>(ph, qw, lm);
+#pragma unroll
+                for (int v = 0; v < N; ++v) { qc[v] = qn[v]; fzc[v] = fzn[v]; }
+#pragma unroll
+                for (int a = 0; a < A; ++a) ac[a] = an[a];
+                lzc = lzn;
+            }
+        };
+        for (int z = z0; z < z1; ++z) {
+            switch (z & 3) {
+            case 0: plane(std::integral_constant<int, 0>(), z); break;
+            case 1: plane(std::integral_constant<int, 1>(), z); break;
+            case 2: plane(std::integral_constant<int, 2>(), z); break;
+            default: plane(std::integral_constant<int, 3>(), z); break;
+            }
+        }
+        // no DMA may still write LDS when the work-group ends
+        wait_vm(0);
+    }
+    if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
+    if (kLam) store_partial<3>(part, lm, unit, n_units);
+}
+
 // Largest speeds of the current state (first step of a call in CFL mode):
 // one work-group per patch, partial maxima per patch.
 template <class Ph, int DIM, typename T>
@@ -470,6 +747,15 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
         hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                            ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
                            slot_in, dt_fixed, ph);
+    } else if (DIM == 3 && b->fv_dma && fv_dma_eligible(b)) {
+        if (dt_fixed > 0.0)
+            hipLaunchKernelGGL((fv_step_dma_kernel<Ph, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
+                               b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part, slot_in, dt_fixed,
+                               ph);
+        else
+            hipLaunchKernelGGL((fv_step_dma_kernel<Ph, T, true>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
+                               b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part, slot_in, dt_fixed,
+                               ph);
     } else {
         if (dt_fixed > 0.0)
             hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi,
@@ -538,6 +824,16 @@ pb_status dispatch(pb_batch *b, F &&f)
 }
 
 }  // namespace
+
+bool fv_dma_eligible(const pb_batch *b)
+{
+    if (b->dim != 3 || b->pde == PB_PDE_SRHD || b->pde == PB_PDE_LINSYM) return false;
+    for (int pk : b->p)
+        if (pk % 4 != 0 || pk > kFvPmax) return false;
+    for (int i = 0; i < 2; ++i)
+        if (reinterpret_cast<uintptr_t>(b->state[i]) % 16 != 0) return false;
+    return true;
+}
 
 pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, double dt_fixed,
                          double cfl, hipStream_t s)

@@ -45,6 +45,7 @@ pb_tuning current(const pb_batch *b)
     t.fv_xcd_remap = b->fv_xcd_remap;
     t.fd_xcd_remap = b->fd_xcd_remap;
     t.fd_wg_per_cu = b->fd_wg_per_cu;
+    t.fv_dma = b->fv_dma;
     return t;
 }
 
@@ -54,6 +55,7 @@ void apply(pb_batch *b, const pb_tuning &t)
     b->fv_xcd_remap = t.fv_xcd_remap;
     b->fd_xcd_remap = t.fd_xcd_remap;
     b->fd_wg_per_cu = t.fd_wg_per_cu == 0 ? 2 : t.fd_wg_per_cu;
+    b->fv_dma = t.fv_dma;
 }
 
 std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
@@ -68,13 +70,16 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
         } else {
             slabs.push_back(0);
         }
-        for (int remap = 1; remap >= 0; --remap)
-            for (int s : slabs) {
-                pb_tuning t = base;
-                t.fv_slab = s;
-                t.fv_xcd_remap = remap;
-                c.push_back(t);
-            }
+        const int dma_hi = fv_dma_eligible(b) ? 1 : 0;
+        for (int dma = dma_hi; dma >= 0; --dma)
+            for (int remap = 1; remap >= 0; --remap)
+                for (int s : slabs) {
+                    pb_tuning t = base;
+                    t.fv_slab = s;
+                    t.fv_xcd_remap = remap;
+                    t.fv_dma = dma;
+                    c.push_back(t);
+                }
     } else {
         for (int wg = 2; wg >= 1; --wg)
             for (int remap = 1; remap >= 0; --remap) {
@@ -207,7 +212,7 @@ pb_status pb_autotune_cache_save(const char *path)
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &e : g_cache)
         f << e.first << ' ' << e.second.fv_slab << ' ' << e.second.fv_xcd_remap << ' ' << e.second.fd_xcd_remap << ' '
-          << e.second.fd_wg_per_cu << '\n';
+          << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << '\n';
     if (!f) { set_error(std::string("write failed: ") + path); return PB_EINVAL; }
     return PB_OK;
 }
@@ -226,9 +231,10 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
         std::istringstream in(line);
         std::string key, extra;
         pb_tuning t{};
-        if (!(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu) || (in >> extra) ||
+        if (!(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu >> t.fv_dma) || (in >> extra) ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
-            t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2) {
+            t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
+            t.fv_dma > 1) {
             set_error(std::string(path) + ":" + std::to_string(lineno) + ": malformed tuning entry");
             if (n_loaded) *n_loaded = n;
             return PB_EINVAL;

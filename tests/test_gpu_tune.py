@@ -29,8 +29,9 @@ def test_fv_autotune_euler3d():
     B = pb.PatchBatch(b)
     before, st0 = B.download(), B.stats()
     r = B.autotune("fv", cfl=0.4, trials=2)
-    check_result(r, 8)
+    check_result(r, 16)
     assert sorted({c["fv_slab"] for c, _ in r["candidates"]}) == [2, 4, 8, 16]
+    assert {c["fv_dma"] for c, _ in r["candidates"]} == {0, 1}
     assert B.get_tuning() == r["best"]
     np.testing.assert_array_equal(B.download(), before)
     assert B.stats() == st0
@@ -80,7 +81,8 @@ def test_srhd_autotune_then_step():
     B = pb.PatchBatch(b)
     before, st0 = B.download(), B.stats()
     r = B.autotune("fv", cfl=0.4, trials=2)
-    check_result(r, 8)
+    check_result(r, 8)   # SRHD has no DMA-fed kernel: slabs x remap only
+    assert {c["fv_dma"] for c, _ in r["candidates"]} == {0}
     np.testing.assert_array_equal(B.download(), before)
     assert B.stats() == st0
     B.fv_rusanov_step(cfl=0.4, n_steps=2)
