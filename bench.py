@@ -48,9 +48,10 @@ def kernel_source_sha(files) -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(name: str, sha: str):
+def load_traffic(name: str, sha: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source (else None)."""
+    it was taken on the current kernel source and the same kernel (else
+    None)."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -59,7 +60,7 @@ def load_traffic(name: str, sha: str):
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("source_sha") != sha:
+    if d.get("source_sha") != sha or d.get("kernel") != kernel:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -109,10 +110,14 @@ def attainable_copy(torch, pb):
     return 2 * src.numel() * 8 * reps / el / 1e9
 
 
+RETUNE = False
+
+
 def tune(B, kind, **kw):
-    """run the library's autotuner on batch B (outside any timed region) and
-    summarise its measurements"""
-    r = B.autotune(kind, trials=3, **kw)
+    """the library's autotuner on batch B (outside any timed region): the
+    cached choice for this workload if the tuning file holds one, else a
+    measured search; returns a summary of what was used"""
+    r = B.autotune(kind, trials=3, use_cache=not RETUNE, **kw)
 
     def name(t):
         if kind == "fv":
@@ -131,6 +136,7 @@ def bench_euler3d(torch, pb, b, storage, steps, warmup):
     kern_ms, launches = B.profile_read()
     B.profile(False)
     st = B.stats()
+    tuning = B.get_tuning()
     B.close()
     cells = b.total_cells
     es = 8 if storage == "fp64" else 4
@@ -139,7 +145,7 @@ def bench_euler3d(torch, pb, b, storage, steps, warmup):
     return {"cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
             "kernel_avg_us": avg_s * 1e6, "launches": launches, "bytes_per_cell": bpc,
             "kernel_GBs": cells * bpc / avg_s / 1e9, "nonfinite_units": st["nonfinite_units"],
-            "autotune": tuned}
+            "autotune": tuned, "tuning": tuning}
 
 
 def bench_config0(torch, pb, I, calls):
@@ -227,6 +233,10 @@ def main():
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--mlp-pairs", type=int, default=1 << 22)
+    ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_2608_19273_amd", "tuning_gfx950.txt"),
+                    help="autotuner cache to start from (measured launch shapes per workload)")
+    ap.add_argument("--retune", action="store_true", help="measure every workload's candidates again")
+    ap.add_argument("--save-tuning", default=None, help="write the autotuner cache here at the end")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; there is no multi-GPU path (--gpus must be 1)"}))
@@ -237,6 +247,11 @@ def main():
     import paper_2608_19273_amd as pb
     from paper_2608_19273_amd import inputs as I
 
+    global RETUNE
+    RETUNE = args.retune
+    if not args.retune and os.path.exists(args.tuning_file):
+        log(f"tuning cache: {pb.pb_autotune_cache_load(args.tuning_file)} entries from {args.tuning_file}")
+
     log("config-1 IC (3D Euler, 2048 x 16^3)")
     b1 = I.config1(seed=1)
     cells = b1.total_cells
@@ -244,7 +259,9 @@ def main():
     h = bench_euler3d(torch, pb, b1, "fp64", args.steps, args.warmup)
     copy_gbs = attainable_copy(torch, pb)
     sha = kernel_source_sha(("pb_fv.hip", "pb_physics.h", "pb_common.h"))
-    traffic = load_traffic("fv_euler3d_2048x16c_fp64_traffic.json", sha)
+    kernel = ("fv_step_dma_kernel<Euler<3>, double, true>" if h["tuning"]["fv_dma"]
+              else "fv_step_kernel<Euler<3>, 3, double, true>")
+    traffic = load_traffic("fv_euler3d_2048x16c_fp64_traffic.json", sha, kernel)
     achieved = h["kernel_GBs"]
     result = {
         "metric": METRIC,
@@ -264,7 +281,7 @@ def main():
                    "patches": b1.K, "patch_cells": int(b1.p[0]) ** 3, "storage": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "fv_step_kernel<Euler<3>, 3, double, true>", "avg_launch_us": h["kernel_avg_us"],
+                     "kernel": kernel, "avg_launch_us": h["kernel_avg_us"],
                      "launches": h["launches"], "algorithmic_bytes_per_launch": cells * h["bytes_per_cell"],
                      "attainable_copy_GBs": copy_gbs, "frac_of_attainable": achieved / copy_gbs,
                      "kernel_source_sha": sha},
@@ -285,6 +302,9 @@ def main():
         log("SRHD plain / warm / learned con2prim")
         wl["srhd"] = bench_srhd(torch, pb, I, max(2, args.steps // 2), args.mlp_epochs, args.mlp_pairs)
         result["workloads"] = wl
+    if args.save_tuning:
+        pb.pb_autotune_cache_save(args.save_tuning)
+        log(f"tuning cache written to {args.save_tuning}")
     if not args.no_cpu:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
