@@ -192,6 +192,12 @@ typedef enum { PB_GUESS_PLAIN = 0, PB_GUESS_LEARNED = 1, PB_GUESS_WARM = 2 } pb_
  * status: device [n] int32: 0 ok, 1 not converged, 2 bad input (nullable).
  * counters: device, 8 int64 accumulated (nullable):
  *         [0] failures, [1] total iterations, [2] fallbacks, [3] max iterations.
+ * stream: hipStream_t (NULL = default stream); asynchronous.
+ * Errors (checked on the host before any launch): PB_EINVAL for n < 0, a NULL
+ * cons/prim with n > 0, Gamma outside (1, 2], tol <= 0, max_iter outside
+ * [0, 1000], an unknown guess, LEARNED without mlp, WARM without p_prev.
+ * n = 0 does nothing and returns PB_OK (the pointers are not looked at).
+ * Non-convergence and bad inputs are not errors: see status / counters.
  */
 pb_status con2prim(const void *cons, void *prim, int64_t n, double gamma, double tol,
                    int32_t max_iter, int32_t guess, const pb_mlp *mlp, const void *p_prev,

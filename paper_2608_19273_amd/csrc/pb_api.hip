@@ -488,6 +488,7 @@ pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko, 
     if (b->pde != PB_PDE_LINSYM) { set_error("fd_ko_step: only the linear symmetric system is implemented"); return PB_EUNSUPPORTED; }
     if (b->h < 3) { set_error("fd_ko_step needs halo >= 3"); return PB_EINVAL; }
     if (b->dim != 3 || b->storage != PB_STORE_FP64) { set_error("fd_ko_step: dim 3, FP64 storage"); return PB_EUNSUPPORTED; }
+    if (b->N > 60) { set_error("fd_ko_step: at most 60 unknowns"); return PB_EUNSUPPORTED; }
     for (int k = 0; k < b->K; ++k) {
         if (b->p[k] != 4 && b->p[k] != 8 && b->p[k] != 16) { set_error("fd_ko_step: p must be 4, 8 or 16"); return PB_EUNSUPPORTED; }
         for (int f = 0; f < 6; ++f)

@@ -380,8 +380,8 @@ extern "C" pb_status con2prim(const void *cons, void *prim, int64_t n, double ga
                               int32_t guess, const pb_mlp *mlp, const void *p_prev, void *iters, void *status,
                               void *counters, void *stream)
 {
-    if (!cons || !prim) { set_error("con2prim: cons and prim are required"); return PB_EINVAL; }
     if (n < 0) { set_error("con2prim: n must be >= 0"); return PB_EINVAL; }
+    if (n > 0 && (!cons || !prim)) { set_error("con2prim: cons and prim are required"); return PB_EINVAL; }
     if (!(gamma > 1.0 && gamma <= 2.0)) { set_error("con2prim: Gamma must be in (1, 2]"); return PB_EINVAL; }
     if (!(tol > 0.0)) { set_error("con2prim: tol must be > 0"); return PB_EINVAL; }
     if (max_iter < 0 || max_iter > 1000) { set_error("con2prim: max_iter must be in [0, 1000]"); return PB_EINVAL; }

@@ -1,0 +1,163 @@
+"""Edge cases of the GPU path against the oracle: single patches, zero steps,
+fixed time steps, ragged and tiny con2prim sizes (every guess), the limits
+of the FD unknown count, and SRHD batches whose patches are smaller than one
+work-group's chunk."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2608_19273_amd as pb
+from paper_2608_19273_amd import inputs as I
+from paper_2608_19273_amd import mlp_train
+
+from gpu_helpers import announce, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+GAM = 5.0 / 3.0
+
+
+def euler_single_patch(dim, p, seed):
+    n = p ** dim
+    rho = I.uniform(seed, n, 0.8, 1.2)
+    vel = [I.uniform(seed + 1 + i, n, -0.3, 0.3) for i in range(dim)]
+    pr = I.uniform(seed + 5, n, 0.8, 1.2)
+    state = np.stack(I.euler_prim_to_state(rho, vel, pr, 1.4)).reshape(-1)
+    return I.Batch(dim=dim, p=np.array([p], np.int32), dx=np.array([1.0 / p]), nbr=I.self_periodic(1, dim),
+                   halo=1, pde="euler", params=np.array([1.4]), n_unknowns=dim + 2, state=state)
+
+
+@pytest.mark.parametrize("dim,p", [(2, 8), (3, 16), (3, 4)])
+def test_single_patch_fv(dim, p):
+    """K = 1, the patch periodic on itself (every halo cell comes from the
+    patch's own opposite face)."""
+    announce(f"single patch fv {dim}d p={p}")
+    need_gpu()
+    b = euler_single_patch(dim, p, 70 + p)
+    o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=3)
+    B = pb.PatchBatch(b)
+    dt = B.fv_rusanov_step(cfl=0.4, n_steps=3, want_dt=True)
+    g = B.download()
+    B.close()
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+
+
+def test_zero_steps_and_fixed_dt():
+    """n_steps = 0 leaves state and statistics alone; fixed-dt steps (FV and
+    FD) match the oracle with the same fixed dt."""
+    announce("zero steps / fixed dt")
+    need_gpu()
+    b = I.config1(grid=(2, 2, 1))
+    B = pb.PatchBatch(b)
+    s0, st0 = B.download(), B.stats()
+    B.fv_rusanov_step(cfl=0.4, n_steps=0)
+    np.testing.assert_array_equal(B.download(), s0)
+    assert B.stats()["steps"] == st0["steps"]
+    B.fv_rusanov_step(dt_fixed=2e-4, n_steps=3)
+    g = B.download()
+    B.close()
+    o, _, _ = oracle.fv_step(b, dt_fixed=2e-4, n_steps=3)
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+    b2 = I.config2(n_patches=3, N=12, sizes=np.array([8, 4, 8], np.int32))
+    B2 = pb.PatchBatch(b2)
+    B2.fd_ko_step(dt_fixed=1e-3, sigma_ko=0.1, n_steps=2)
+    g2 = B2.download()
+    B2.close()
+    o2, _ = oracle.fd_step(b2, dt_fixed=1e-3, sigma=0.1, n_steps=2)
+    assert np.all(rel_err(b2, g2, o2) <= 1e-12)
+
+
+@pytest.mark.parametrize("N", [1, 60])
+def test_fd_unknown_count_limits(N):
+    """The smallest and the largest unknown count of the FD kernel (its dense
+    product is padded to 64 rows and 60 columns), on one single-tile patch and
+    two larger ones."""
+    announce(f"fd N={N}")
+    need_gpu()
+    b = I.config2(n_patches=3, N=N, sizes=np.array([4, 8, 16], np.int32))
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
+    B = pb.PatchBatch(b)
+    dt = B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2, want_dt=True)
+    g = B.download()
+    B.close()
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-15 * dts[-1]
+
+
+def test_fd_rejects_too_many_unknowns():
+    announce("fd N=61 rejected")
+    need_gpu()
+    b = I.config2(n_patches=1, N=61, sizes=np.array([4], np.int32))
+    B = pb.PatchBatch(b)
+    with pytest.raises(pb.PbError, match="60"):
+        B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=1)
+    np.testing.assert_array_equal(B.download(), b.state)
+    B.close()
+
+
+@pytest.fixture(scope="module")
+def small_net():
+    need_gpu()
+    net, _ = mlp_train.train(n_pairs=1 << 16, epochs=2, batch=1024, lr=3e-3, seed=9)
+    return net
+
+
+def c2p(cons, guess, mlp=None, p_prev=None):
+    torch = need_gpu()
+    n = cons.shape[1]
+    c = torch.from_numpy(np.ascontiguousarray(cons)).cuda()
+    prim = torch.full((5, n), -7.0, dtype=torch.float64, device="cuda")
+    st = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    cnt = torch.zeros(8, dtype=torch.int64, device="cuda")
+    pp = None if p_prev is None else torch.from_numpy(np.ascontiguousarray(p_prev)).cuda()
+    pb.con2prim(c, prim, GAM, 1e-12, 50, guess=guess, mlp=mlp, p_prev=pp, status=st, counters=cnt)
+    torch.cuda.synchronize()
+    return prim.cpu().numpy(), st.cpu().numpy(), cnt.cpu().numpy()
+
+
+@pytest.mark.parametrize("n", [1, 63, 255, 257, 2047, 2049, 5000])
+def test_con2prim_ragged_sizes_every_guess(n, small_net):
+    """Sizes that end inside a wave, a work-group and (for the learned pass,
+    which walks 8 chunks of 256 cells per work-group) inside a chunk group:
+    every guess converges to the oracle's pressure within the conditioning
+    of the problem, and no cell is left unwritten."""
+    announce(f"con2prim n={n}")
+    rho, vx, vy, vz, eps = I.srhd_primitives(500 + n, n)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, GAM)
+    o = oracle.con2prim(cons)[0]
+    W2 = 1.0 / (1.0 - (o[1] ** 2 + o[2] ** 2 + o[3] ** 2))
+    bound = np.maximum(1e-12, 8 * 2.2e-16 * W2 / (o[4] / ((GAM - 1) * o[0])))
+    for guess, kw in (("plain", {}), ("warm", {"p_prev": p * 1.01}), ("learned", {"mlp": small_net})):
+        g, st, cnt = c2p(cons, guess, **kw)
+        assert np.all(st == 0), (guess, st)
+        assert np.all(np.abs(g[4] - o[4]) / o[4] <= bound), guess
+        assert cnt[0] == 0
+
+
+def test_con2prim_empty():
+    announce("con2prim n=0")
+    torch = need_gpu()
+    c = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+    prim = torch.zeros((5, 0), dtype=torch.float64, device="cuda")
+    pb.con2prim(c, prim, GAM, 1e-12, 50)
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p", [4, 8])
+def test_srhd_small_patches_every_guess(p, small_net):
+    """SRHD patches of 4^3 and 8^3 cells: fewer cells than one work-group
+    chunk of the con2prim pass (partially active waves, idle waves in the
+    network's whole-wave evaluation)."""
+    announce(f"srhd p={p}")
+    b = I.config3(grid=(2, 2, 1), p=p, seed=60 + p)
+    o, dts, ost = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    for guess in ("plain", "warm", "learned"):
+        B = pb.PatchBatch(b)
+        if guess != "plain":
+            B.set_c2p_guess(guess, small_net if guess == "learned" else None)
+        B.fv_rusanov_step(cfl=0.4, n_steps=2)
+        g = B.download()
+        st = B.stats()
+        B.close()
+        assert np.all(rel_err(b, g, o) <= 1e-12), (guess, rel_err(b, g, o))
+        assert st["c2p_cells"] == 2 * b.total_cells and st["c2p_failures"] == 0
