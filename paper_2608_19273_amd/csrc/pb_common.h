@@ -29,9 +29,7 @@ static_assert(sizeof(PatchDev) == 48, "PatchDev layout");
 // Control block at the start of the workspace (256 bytes).
 struct Ctrl {
     double dt[2];                       // step sizes, ping-ponged by step parity
-    unsigned long long lam[3];          // running max of lambda_d (IEEE bits, >= 0)
-    unsigned int done;                  // work units finished in the current launch
-    unsigned int queue;                 // FD work-list head
+    unsigned long long reserved[4];
     unsigned long long nonfinite;       // units that produced NaN/Inf
     unsigned long long c2p_cells;
     unsigned long long c2p_fail;
