@@ -246,11 +246,12 @@ def fourier_field(seed: int, coords, lengths, n_modes: int = 8, kmax: int = 4) -
     return out / asum
 
 
-def config1(seed: int = 1, grid=C1_GRID, p: int = 16, gamma: float = 1.4) -> Batch:
-    """3D Euler, smooth random IC (sum of 8 Fourier modes per primitive)."""
+def config1(seed: int = 1, grid=C1_GRID, p: int = 16, gamma: float = 1.4, halo: int = 1) -> Batch:
+    """3D Euler, smooth random IC (sum of 8 Fourier modes per primitive).
+    halo = 1 for the finite-volume step, 3 for the FD4 + KO6 step."""
     cells = tuple(g * p for g in grid)
     dx = 1.0 / cells[0]
-    b = make_uniform_batch(grid, p, 1, "euler", [gamma], 5, dx)
+    b = make_uniform_batch(grid, p, halo, "euler", [gamma], 5, dx)
     lengths = tuple(c * dx for c in cells)
     coords = _centres(cells, dx)
     s = [fourier_field(substream(seed, 10 + f), coords, lengths) for f in range(5)]
