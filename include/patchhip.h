@@ -157,12 +157,21 @@ pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_st
  *   R(Q) = sum_d ( -D4_d F_d - B_d D4_d Q + KO6_d Q ) + S(Q),
  *   D4 u = [(u_-2 - u_+2) + 8 (u_+1 - u_-1)] / (12 dx),
  *   KO6 u = sigma/(64 dx) [(u_-3 + u_+3) - 6 (u_-2 + u_+2) + 15 (u_-1 + u_+1) - 20 u_0].
- * Patches must be periodic on themselves (neighbor = self), so one
- * persistent launch per stage sweeps all patches from a cost-ordered work
- * list.  dt as in fv_rusanov_step (Lambda_d = spectral radius of B_d).
- * Needs 2 extra state-sized buffers in the workspace.
- * Supported: LINSYM (N <= 60; the workloads use N = 58), dim 3, halo >= 3,
- * p in {4, 8, 16}, FP64; other N return PB_EUNSUPPORTED.
+ * Two PDEs (other PDEs return PB_EUNSUPPORTED):
+ *  - LINSYM (the B_d term): patches must be periodic on themselves
+ *    (neighbor = self), so one persistent launch per stage sweeps all
+ *    patches from a cost-ordered work list; dt as in fv_rusanov_step with
+ *    Lambda_d = spectral radius of B_d (computed on the host).  N <= 60
+ *    (the workloads use N = 58), p in {4, 8, 16}.
+ *  - EULER (the F_d term, flux differencing; the paper's fourth scheme,
+ *    Sec. IV): patches are joined through their face neighbours (the halo
+ *    of width 3 is read from the neighbours' interiors inside each stage);
+ *    3 <= p <= 16; dt as in fv_rusanov_step, reduced on the device from the
+ *    state at the start of each step.
+ * Both: dim 3, halo >= 3, FP64 storage; the workspace carries two extra
+ * state-sized stage buffers (pb_workspace_size adds them for LINSYM and for
+ * 3D EULER with halo >= 3).  The result lands in the state buffer opposite
+ * to the current one after every step (the stage sum accumulates there).
  */
 pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko,
                      int32_t rk_stages, int32_t n_steps, int32_t use_graph,

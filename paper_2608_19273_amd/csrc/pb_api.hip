@@ -24,7 +24,7 @@ pb_status hip_fail(hipError_t e, const char *what)
 
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K)
+WsLayout ws_layout(int pde, int dim, int h, long long total_cells, int N, int storage, int K)
 {
     WsLayout L;
     size_t o = 0;
@@ -38,7 +38,7 @@ WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K)
         L.pres = o;
         o = align256(o + (size_t)total_cells * sizeof(double));
     }
-    if (pde == PB_PDE_LINSYM) {
+    if (fd_buffers(pde, dim, h)) {
         const size_t es = storage == PB_STORE_FP32 ? 4 : 8;
         L.yA = o;
         o = align256(o + (size_t)total_cells * N * es);
@@ -124,7 +124,7 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
     if (need_buffers) {
         if (!d->state || !d->state_alt) { set_error("state and state_alt are required"); return PB_EINVAL; }
         if (d->state == d->state_alt) { set_error("state and state_alt must differ"); return PB_EINVAL; }
-        const WsLayout L = ws_layout(d->pde, cells, N, d->storage, d->n_patches);
+        const WsLayout L = ws_layout(d->pde, d->dim, d->halo, cells, N, d->storage, d->n_patches);
         if (!d->workspace) { set_error("workspace is required"); return PB_EINVAL; }
         if (((uintptr_t)d->workspace & 255) != 0) { set_error("workspace must be 256-byte aligned"); return PB_EINVAL; }
         if (d->workspace_bytes < L.total) {
@@ -175,8 +175,30 @@ static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sig
 {
     int cur = *cur_io;
     pb_status st;
-    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     void *yA = b->ws + L.yA, *yB = b->ws + L.yB;
+    if (b->pde == PB_PDE_EULER) {
+        // dt on the device: from Q^n for the first step, then from the last
+        // stage of each step (ping-pong slots as in the FV path)
+        if (!(dt_fixed > 0.0))
+            if ((st = launch_fv_lambda(b, b->state[cur], cfl, s)) != PB_OK) return st;
+        for (int i = 0; i < n; ++i) {
+            void *q0 = b->state[cur], *acc = b->state[cur ^ 1];
+            const int slot = i & 1;
+            void *ys[4] = {q0, yA, yB, yA};
+            void *yn[4] = {yA, yB, yA, nullptr};
+            for (int sg = 0; sg < (rk == 1 ? 1 : 4); ++sg) {
+                if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
+                if ((st = launch_fd_euler_stage(b, sg, rk, q0, ys[sg], rk == 1 ? nullptr : yn[sg], acc, slot,
+                                                dt_fixed, cfl, sigma, s)) != PB_OK)
+                    return st;
+                if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
+            }
+            cur ^= 1;
+        }
+        *cur_io = cur;
+        return PB_OK;
+    }
     const double dt = fd_dt(b, cfl, dt_fixed);
     for (int i = 0; i < n; ++i) {
         void *q0 = b->state[cur], *acc = b->state[cur ^ 1];
@@ -215,7 +237,7 @@ pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes)
     long long cells = 0;
     pb_status st = validate(desc, false, &cells, nullptr, nullptr);
     if (st != PB_OK) return st;
-    *bytes = ws_layout(desc->pde, cells, desc->n_unknowns, desc->storage, desc->n_patches).total;
+    *bytes = ws_layout(desc->pde, desc->dim, desc->halo, cells, desc->n_unknowns, desc->storage, desc->n_patches).total;
     return PB_OK;
 }
 
@@ -485,9 +507,19 @@ pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko, 
         set_error("need dt_fixed > 0 or a finite cfl > 0");
         return PB_EINVAL;
     }
-    if (b->pde != PB_PDE_LINSYM) { set_error("fd_ko_step: only the linear symmetric system is implemented"); return PB_EUNSUPPORTED; }
+    if (b->pde != PB_PDE_LINSYM && b->pde != PB_PDE_EULER) {
+        set_error("fd_ko_step: implemented for LINSYM and EULER");
+        return PB_EUNSUPPORTED;
+    }
     if (b->h < 3) { set_error("fd_ko_step needs halo >= 3"); return PB_EINVAL; }
     if (b->dim != 3 || b->storage != PB_STORE_FP64) { set_error("fd_ko_step: dim 3, FP64 storage"); return PB_EUNSUPPORTED; }
+    if (b->pde == PB_PDE_EULER) {
+        if (b->pmax > kFvPmax) { set_error("fd_ko_step: p > 16 is not supported for EULER"); return PB_EUNSUPPORTED; }
+        if (n_steps == 0) return finish_call(b, 0, dt_fixed, dt_last_host);
+        pb_status st = run_steps(b, 1, cfl, dt_fixed, sigma_ko, rk_stages, n_steps, use_graph);
+        if (st != PB_OK) return st;
+        return finish_call(b, n_steps, dt_fixed, dt_last_host);
+    }
     if (b->N > 60) { set_error("fd_ko_step: at most 60 unknowns"); return PB_EUNSUPPORTED; }
     for (int k = 0; k < b->K; ++k) {
         if (b->p[k] != 4 && b->p[k] != 8 && b->p[k] != 16) { set_error("fd_ko_step: p must be 4, 8 or 16"); return PB_EUNSUPPORTED; }

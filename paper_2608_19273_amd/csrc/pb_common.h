@@ -93,6 +93,28 @@ __device__ __forceinline__ void dma_to_lds4(const void *g, const void *lds)
     __asm__ volatile("s_mov_b32 m0, %0\n\tglobal_load_lds_dword %1, off" : : "s"(a), "v"(g) : "memory", "m0");
 }
 
+// Work-group max of lm[0..DIM) stored as this unit's partial (plain stores,
+// no atomics and no fence: the kernel boundary makes them visible to the
+// reduction kernel that follows).  Layout: part[d * n_units + unit].
+template <int DIM>
+__device__ __forceinline__ void store_partial(double *__restrict__ part, const double *lm, int unit,
+                                              int n_units)
+{
+    __shared__ double red[3][kFvThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double m = wave_max(lm[d]);
+        if (lane == 0) red[d][w] = m;
+    }
+    __syncthreads();
+    if (t < DIM) {
+        double m = red[t][0];
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[t][i]);
+        part[(long long)t * n_units + unit] = m;
+    }
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int n)
 {
     const int q = n >> 3, r = n & 7;
@@ -163,7 +185,13 @@ struct WsLayout {
     size_t yA = 0, yB = 0; // FD: stage buffers
     size_t total = 0;
 };
-WsLayout ws_layout(int pde, long long total_cells, int N, int storage, int K);
+// the FD step's two stage buffers exist for the linear system and for 3D
+// Euler batches whose halo reaches the FD stencil (h >= 3)
+inline bool fd_buffers(int pde, int dim, int h)
+{
+    return pde == PB_PDE_LINSYM || (pde == PB_PDE_EULER && dim == 3 && h >= 3);
+}
+WsLayout ws_layout(int pde, int dim, int h, long long total_cells, int N, int storage, int K);
 // largest number of work units any launch uses (partials are sized for it)
 inline long long max_units(int K) { return (long long)K * kFvPmax; }
 
@@ -175,6 +203,10 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
                           hipStream_t s);
 pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y,
                           void *ynext, void *acc, double dt, double sigma, hipStream_t s);
+// one stage of the Euler FD4 + KO6 step (dt from ctrl->dt[slot] unless
+// dt_fixed > 0; the last stage writes the next step's dt to slot ^ 1)
+pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y, void *ynext,
+                                void *acc, int slot, double dt_fixed, double cfl, double sigma, hipStream_t s);
 // the DMA-fed FV kernel applies to this batch (3D, no extra per-cell input,
 // every p a multiple of 4, 16-byte aligned state buffers)
 bool fv_dma_eligible(const pb_batch *b);

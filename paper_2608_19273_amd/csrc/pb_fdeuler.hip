@@ -1,0 +1,341 @@
+// pb_fdeuler.hip -- one Runge-Kutta stage of the fourth-order finite-difference
+// scheme with sixth-order Kreiss-Oliger dissipation for the 3D Euler equations
+// in flux form (the paper's fourth scheme, Sec. IV, with the flux-divergence
+// term of Eq. (1)), on a batch of patches joined through their face
+// neighbours:
+//   R(Q) = sum_d ( -D4_d F_d(Q) + KO6_d Q ),
+//   D4 f  = [(f_-2 - f_+2) + 8 (f_+1 - f_-1)] / (12 dx),
+//   KO6 u = sigma/(64 dx) [(u_-3 + u_+3) - 6 (u_-2 + u_+2) + 15 (u_-1 + u_+1) - 20 u_0].
+// The stencil reaches 3 cells along each axis and never diagonally, so the
+// halo is the three face layers of each side (no edges or corners).
+//
+// Work decomposition (MI355X): as the FV step, one work-group of 256 threads
+// per z-slab of one patch; thread t owns column (x, y) = (t % p, t / p) and
+// the work-group marches up the slab plane by plane.  Per output plane z:
+//   1. each thread holds its column's Q on planes z-3..z+3 and 1/rho, p on
+//      planes z-2..z+2 in registers (plane z+3 arrives from a load issued one
+//      plane earlier; its division happens once, as it enters the flux
+//      window), so the z derivatives need no LDS; F_z is re-formed from the
+//      window per unknown (a multiplication or two each, cheaper in
+//      registers than a window of fluxes);
+//   2. the work-group writes Q, F_x and F_y of plane z to LDS, together with
+//      the 12p face-halo cells of the plane (three layers per side, read
+//      straight from the face neighbours' interiors: the halo gather of
+//      Sec. II, Eq. (2), fused into the stage) and, for the two inner
+//      layers, their F_x or F_y, so every x and y flux is evaluated once;
+//   3. after a barrier each thread forms R of its cell, meets the others at
+//      a second barrier (the LDS is single-buffered: 45 KB, two work-groups
+//      per CU), applies the RK stage update and stores.
+// The last stage of a step also folds the largest characteristic speeds of
+// the new state into per-unit partials for the next step's dt, and counts
+// non-finite results.
+#include <algorithm>
+
+#include "pb_common.h"
+#include "pb_physics.h"
+
+namespace pb {
+
+namespace {
+
+constexpr int kEN = 5;                      // unknowns of 3D Euler
+constexpr int kQS = kFvPmax + 6;            // row stride of the Q plane: x in [-3, p + 3)
+constexpr int kFxS = kFvPmax + 4;           // row stride of F_x: x in [-2, p + 2)
+constexpr int kPlaneQ = kQS * kQS;          // Q plane slots (corners unused)
+constexpr int kPlaneF = kFvPmax * kFxS;     // F_x and F_y plane slots
+
+__device__ __forceinline__ int q_slot(int x, int y) { return (y + 3) * kQS + x + 3; }
+__device__ __forceinline__ int fx_slot(int x, int y) { return y * kFxS + x + 2; }
+__device__ __forceinline__ int fy_slot(int x, int y) { return (y + 2) * kFvPmax + x; }
+
+// 1/rho and the pressure (all the fluxes need; no sound speed), in the
+// aux layout the Euler functor's flux reads
+__device__ __forceinline__ void euler_ip(const double *q, double gm1, double *a)
+{
+    const double ir = recip(q[0]);
+    const double m2 = q[1] * q[1] + q[2] * q[2] + q[3] * q[3];
+    a[0] = ir;
+    a[1] = gm1 * (q[4] - 0.5 * m2 * ir);
+}
+
+__device__ __forceinline__ double d4(double m2, double m1, double p1, double p2)
+{
+    return (m2 - p2) + 8.0 * (p1 - m1);
+}
+
+__device__ __forceinline__ double ko6(double m3, double m2, double m1, double c, double p1, double p2, double p3)
+{
+    return (((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1)) - 20.0 * c;
+}
+
+// the 5 unknowns of one cell: base points at unknown 0 of the patch block,
+// o is the cell's offset in it, C the unknown stride (all offsets fit 32
+// bits: p <= 16)
+__device__ __forceinline__ void load5(const double *__restrict__ base, unsigned o, unsigned C, double *out)
+{
+#pragma unroll
+    for (int v = 0; v < kEN; ++v) out[v] = base[o + v * C];
+}
+
+}  // namespace
+
+// S: RK4 stage 0..3, or 4 for the single forward-Euler stage.
+//   S = 0: ynext = y + dt/2 R, acc = y + dt/6 R      (y = Q^n)
+//   S = 1: ynext = q0 + dt/2 R, acc += dt/3 R
+//   S = 2: ynext = q0 + dt R,   acc += dt/3 R
+//   S = 3: acc += dt/6 R                              (acc = Q^{n+1})
+//   S = 4: acc = y + dt R                             (y = Q^n)
+// kLam: fold the speeds of the new state (last stage, CFL mode).
+template <int S, bool kLam>
+__global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
+    const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
+    double *__restrict__ acc, const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
+    Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot, double dt_fixed, double gamma, double sigma)
+{
+    constexpr int N = kEN;
+    constexpr bool kReadQ0 = S == 1 || S == 2;
+    constexpr bool kReadAcc = S == 1 || S == 2 || S == 3;
+    constexpr bool kFinal = S == 3 || S == 4;
+    __shared__ double sQ[N][kPlaneQ];
+    __shared__ double sFx[N][kPlaneF];
+    __shared__ double sFy[N][kPlaneF];
+
+    const int t = threadIdx.x;
+    const int unit = remap ? xcd_remap(blockIdx.x, n_units) : (int)blockIdx.x;
+    const int k = unit / n_slabs, sl = unit - k * n_slabs;
+    const PatchDev P = patches[k];
+    const int p = P.p;
+    const unsigned C = (unsigned)(p * p * p), pp = (unsigned)(p * p);
+    // patch blocks: this patch in every buffer, the z neighbours in y
+    const double *yo = y + P.off * N, *ylo = y + patches[P.nbr[4]].off * N, *yhi = y + patches[P.nbr[5]].off * N;
+    const double *q0o = q0 + P.off * N, *acco = acc + P.off * N;
+    double *yno = ynext + P.off * N, *accw = acc + P.off * N;
+    const int z0 = sl * slab, z1 = min(p, z0 + slab);
+    // a slab can start beyond the last plane of a patch smaller than the
+    // batch maximum: such a unit only takes part in the reductions
+    const bool work = z0 < p;
+    const bool active = work && t < p * p;
+    const int x = active ? t % p : 0, yy = active ? t / p : 0;
+    const unsigned cxy = (unsigned)(yy * p + x);
+    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot];
+    const double gm1 = gamma - 1.0;
+    const double c4 = P.inv_dx / 12.0, cko = sigma * P.inv_dx / 64.0;
+    const Euler<3> ph{gamma};
+    const int qs = q_slot(x, yy), fxs = fx_slot(x, yy), fys = fy_slot(x, yy);
+
+    // this thread's face-halo cell (threads 0 .. 12p-1): side (-x, +x, -y, +y),
+    // layer 0..2 outwards, position j along the face
+    const bool halo = work && t < 12 * p;
+    int hq = 0, hf = 0;
+    bool hflux = false, hx = false;
+    const double *hsrc = y;   // unknown 0 of the halo cell's source column, plane 0
+    if (halo) {
+        const int side = t / (3 * p), r = t - side * 3 * p, layer = r / p, j = r - layer * p;
+        int dx_, dy_, sx, sy;
+        if (side == 0)      { dx_ = -1 - layer; dy_ = j; sx = p - 1 - layer; sy = j; }
+        else if (side == 1) { dx_ = p + layer;  dy_ = j; sx = layer;         sy = j; }
+        else if (side == 2) { dx_ = j; dy_ = -1 - layer; sx = j; sy = p - 1 - layer; }
+        else                { dx_ = j; dy_ = p + layer;  sx = j; sy = layer; }
+        // (a select, not P.nbr[side]: a lane-varying index would send the
+        // patch record to scratch memory)
+        const int nb = side == 0 ? P.nbr[0] : side == 1 ? P.nbr[1] : side == 2 ? P.nbr[2] : P.nbr[3];
+        hsrc = y + patches[nb].off * N + (sy * p + sx);
+        hq = q_slot(dx_, dy_);
+        hflux = layer < 2;
+        hx = side < 2;
+        hf = hx ? fx_slot(dx_, dy_) : fy_slot(dx_, dy_);
+    }
+    // this thread's column on plane zz (zz in [-3, p + 3): the planes outside
+    // the patch come from the z neighbours; the choice is uniform)
+    auto col = [&](int zz, double *out) {
+        const double *b = zz < 0 ? ylo : (zz >= p ? yhi : yo);
+        const int zl = zz < 0 ? zz + p : (zz >= p ? zz - p : zz);
+        load5(b, (unsigned)zl * pp + cxy, C, out);
+    };
+
+    double qr[7][N];    // Q of planes z-3 .. z+3
+    double ar[5][2];    // 1/rho and p of planes z-2 .. z+2
+    double rl[N], hr[N];   // loads in flight: own plane z+3, halo cell of plane z
+    double lm[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) col(z0 - 3 + i, qr[i]);
+        col(z0 + 3, rl);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) euler_ip(qr[1 + i], gm1, ar[i]);
+    }
+    if (halo) load5(hsrc, (unsigned)z0 * pp, C, hr);
+
+#pragma unroll 1
+    for (int z = z0; z < z1; ++z) {
+        const unsigned own = (unsigned)z * pp + cxy;
+        double q0v[N], accv[N];
+        if (active) {
+            // plane z+3 enters the window; the load of plane z+4 replaces it
+#pragma unroll
+            for (int v = 0; v < N; ++v) qr[6][v] = rl[v];
+            if (z + 1 < z1) col(z + 4, rl);
+            if (kReadQ0) load5(q0o, own, C, q0v);
+            if (kReadAcc) load5(acco, own, C, accv);
+            euler_ip(qr[5], gm1, ar[4]);
+            double fx[N], fy[N];
+            ph.flux<0>(qr[3], ar[2], fx);
+            ph.flux<1>(qr[3], ar[2], fy);
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                sQ[v][qs] = qr[3][v];
+                sFx[v][fxs] = fx[v];
+                sFy[v][fys] = fy[v];
+            }
+        }
+        if (halo) {
+            double hv[N];
+#pragma unroll
+            for (int v = 0; v < N; ++v) hv[v] = hr[v];
+            if (z + 1 < z1) load5(hsrc, (unsigned)(z + 1) * pp, C, hr);
+#pragma unroll
+            for (int v = 0; v < N; ++v) sQ[v][hq] = hv[v];
+            if (hflux) {
+                double a[2], F[N];
+                euler_ip(hv, gm1, a);
+                if (hx) {
+                    ph.flux<0>(hv, a, F);
+#pragma unroll
+                    for (int v = 0; v < N; ++v) sFx[v][hf] = F[v];
+                } else {
+                    ph.flux<1>(hv, a, F);
+#pragma unroll
+                    for (int v = 0; v < N; ++v) sFy[v][hf] = F[v];
+                }
+            }
+        }
+        __syncthreads();
+        double R[N];
+        if (active) {
+            // u_z of planes z-2, z-1, z+1, z+2 (window slots 1, 2, 4, 5); the
+            // components of F_z are formed per unknown below
+            double uz[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int w = i < 2 ? i + 1 : i + 2;
+                uz[i] = qr[w][3] * ar[w - 1][0];
+            }
+            auto fzv = [&](int i, int v) -> double {
+                const int w = i < 2 ? i + 1 : i + 2;
+                const double pr = ar[w - 1][1];
+                if (v == 0) return qr[w][3];
+                if (v == 3) return qr[w][3] * uz[i] + pr;
+                if (v == 4) return (qr[w][4] + pr) * uz[i];
+                return qr[w][v] * uz[i];
+            };
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                const double *u = sQ[v], *fxv = sFx[v], *fyv = sFy[v];
+                const double dfx = d4(fxv[fxs - 2], fxv[fxs - 1], fxv[fxs + 1], fxv[fxs + 2]);
+                const double dfy = d4(fyv[fys - 2 * kFvPmax], fyv[fys - kFvPmax], fyv[fys + kFvPmax],
+                                      fyv[fys + 2 * kFvPmax]);
+                const double dfz = d4(fzv(0, v), fzv(1, v), fzv(2, v), fzv(3, v));
+                const double c = qr[3][v];
+                const double kx = ko6(u[qs - 3], u[qs - 2], u[qs - 1], c, u[qs + 1], u[qs + 2], u[qs + 3]);
+                const double ky = ko6(u[qs - 3 * kQS], u[qs - 2 * kQS], u[qs - kQS], c, u[qs + kQS],
+                                      u[qs + 2 * kQS], u[qs + 3 * kQS]);
+                const double kz = ko6(qr[0][v], qr[1][v], qr[2][v], c, qr[4][v], qr[5][v], qr[6][v]);
+                R[v] = cko * ((kx + ky) + kz) - c4 * ((dfx + dfy) + dfz);
+                // one unknown's 20 LDS reads at a time: hoisting all of them
+                // would not fit the register budget
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        __syncthreads();   // the plane's LDS is free for the next one
+        if (active) {
+            double nv[N];
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                const unsigned g = own + v * C;
+                if (S == 0) {
+                    yno[g] = qr[3][v] + (0.5 * dt) * R[v];
+                    nv[v] = qr[3][v] + (dt / 6.0) * R[v];
+                } else if (S == 1) {
+                    yno[g] = q0v[v] + (0.5 * dt) * R[v];
+                    nv[v] = accv[v] + (dt / 3.0) * R[v];
+                } else if (S == 2) {
+                    yno[g] = q0v[v] + dt * R[v];
+                    nv[v] = accv[v] + (dt / 3.0) * R[v];
+                } else if (S == 3) {
+                    nv[v] = accv[v] + (dt / 6.0) * R[v];
+                } else {
+                    nv[v] = qr[3][v] + dt * R[v];
+                }
+                accw[g] = nv[v];
+            }
+            if (kFinal) {
+#pragma unroll
+                for (int v = 0; v < N; ++v) bad |= !isfinite(nv[v]);
+                if (kLam) {
+                    double a[3];
+                    ph.aux_fast(nv, nullptr, a);
+                    lm[0] = fmax(lm[0], ph.eig<0>(nv, a));
+                    lm[1] = fmax(lm[1], ph.eig<1>(nv, a));
+                    lm[2] = fmax(lm[2], ph.eig<2>(nv, a));
+                }
+            }
+            // slide the windows up one plane
+#pragma unroll
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int v = 0; v < N; ++v) qr[i][v] = qr[i + 1][v];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { ar[i][0] = ar[i + 1][0]; ar[i][1] = ar[i + 1][1]; }
+        }
+    }
+    if (kFinal) {
+        if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
+        if (kLam) store_partial<3>(part, lm, unit, n_units);
+    }
+}
+
+// ------------------------------------------------------------------ host --
+
+namespace {
+
+template <int S, bool kLam>
+void launch_s(dim3 g, hipStream_t s, const double *y, const double *q0, double *yn, double *acc, const pb_batch *b,
+              int n_units, int n_slabs, int slab, Ctrl *ctrl, double *part, int slot, double dt_fixed, double sigma)
+{
+    hipLaunchKernelGGL((fd_euler_stage_kernel<S, kLam>), g, dim3(kFvThreads), 0, s, y, q0, yn, acc, b->d_patches,
+                       n_units, n_slabs, slab, b->fd_xcd_remap, ctrl, part, slot, dt_fixed, b->params[0], sigma);
+}
+
+}  // namespace
+
+pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const void *q0, const void *y, void *ynext,
+                                void *acc, int slot, double dt_fixed, double cfl, double sigma, hipStream_t s)
+{
+    if (b->pmax > kFvPmax) { set_error("fd_ko_step: p > 16 is not supported for EULER"); return PB_EUNSUPPORTED; }
+    const int slab = b->pmax, n_slabs = 1, n_units = b->K * n_slabs;
+    Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
+    const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
+    double *part = reinterpret_cast<double *>(b->ws + L.part);
+    const int S = rk_stages == 1 ? 4 : stage;
+    const bool final_stage = S == 3 || S == 4;
+    const bool lam = final_stage && !(dt_fixed > 0.0);
+    const double *yi = static_cast<const double *>(y), *q0i = static_cast<const double *>(q0);
+    double *yn = static_cast<double *>(ynext), *ac = static_cast<double *>(acc);
+    const dim3 g(n_units);
+#define PB_FDE_ARGS g, s, yi, q0i, yn, ac, b, n_units, n_slabs, slab, ctrl, part, slot, dt_fixed, sigma
+    switch (S) {
+    case 0: launch_s<0, false>(PB_FDE_ARGS); break;
+    case 1: launch_s<1, false>(PB_FDE_ARGS); break;
+    case 2: launch_s<2, false>(PB_FDE_ARGS); break;
+    case 3: lam ? launch_s<3, true>(PB_FDE_ARGS) : launch_s<3, false>(PB_FDE_ARGS); break;
+    default: lam ? launch_s<4, true>(PB_FDE_ARGS) : launch_s<4, false>(PB_FDE_ARGS); break;
+    }
+#undef PB_FDE_ARGS
+    PB_HIP(hipGetLastError());
+    if (lam) return launch_dt_reduce(b, part, n_units, 3, slot ^ 1, cfl, true, false, s);
+    return PB_OK;
+}
+
+}  // namespace pb

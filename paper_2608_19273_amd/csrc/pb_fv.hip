@@ -64,28 +64,6 @@ __device__ __forceinline__ void cell_speeds_fast(const Ph &ph, const double *q, 
     cell_speeds<Ph, DIM>(ph, q, a, lm);
 }
 
-// Work-group max of lm[0..DIM) stored as this unit's partial (plain stores,
-// no atomics and no fence: the kernel boundary makes them visible to the
-// reduction kernel that follows).  Layout: part[d * n_units + unit].
-template <int DIM>
-__device__ __forceinline__ void store_partial(double *__restrict__ part, const double *lm, int unit,
-                                              int n_units)
-{
-    __shared__ double red[3][kFvThreads / kWave];
-    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
-#pragma unroll
-    for (int d = 0; d < DIM; ++d) {
-        const double m = wave_max(lm[d]);
-        if (lane == 0) red[d][w] = m;
-    }
-    __syncthreads();
-    if (t < DIM) {
-        double m = red[t][0];
-        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[t][i]);
-        part[(long long)t * n_units + unit] = m;
-    }
-}
-
 }  // namespace
 
 #ifndef PB_FV_NTLOAD
@@ -737,7 +715,7 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     const int n_slabs = (DIM == 3) ? (b->pmax + slab - 1) / slab : 1;
     const int n_units = b->K * n_slabs;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
-    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     double *part = reinterpret_cast<double *>(b->ws + L.part);
     const T *qi = static_cast<const T *>(qin);
     T *qo = static_cast<T *>(qout);
@@ -778,7 +756,7 @@ template <class Ph, int DIM, typename T>
 pb_status launch_lambda_typed(pb_batch *b, const Ph &ph, const void *q, double cfl, hipStream_t s)
 {
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
-    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     double *part = reinterpret_cast<double *>(b->ws + L.part);
     hipLaunchKernelGGL((fv_lambda_kernel<Ph, DIM, T>), dim3(b->K), dim3(kFvThreads), 0, s,
                        static_cast<const T *>(q), b->d_patches, part, ph);

@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kC2pThreads, 4) void con2prim_learned_kernel(
 
 pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt, double cfl, hipStream_t s)
 {
-    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     double *pres = reinterpret_cast<double *>(b->ws + L.pres);
     double *part = reinterpret_cast<double *>(b->ws + L.part);
     const long long cmax = (long long)b->pmax * b->pmax * b->pmax;

@@ -98,7 +98,7 @@ pb_status trial(pb_batch *b, int kind, double cfl, double dt_fixed, double sigma
 {
     void *qin = b->state[b->cur], *qout = b->state[b->cur ^ 1];
     if (kind == 0) return launch_fv_step(b, qin, qout, 0, dt_fixed, cfl, s);
-    const WsLayout L = ws_layout(b->pde, b->total_cells, b->N, b->storage, b->K);
+    const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     return launch_fd_stage(b, 0, 4, qin, qin, b->ws + L.yA, qout, fd_dt(b, cfl, dt_fixed), sigma, s);
 }
 

@@ -1,0 +1,134 @@
+"""GPU parity of the Euler FD4 + KO6 + RK4 stage kernel (flux differencing,
+patches joined through their face neighbours, halo of width 3 read from the
+neighbours inside each stage) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2608_19273_amd as pb
+from paper_2608_19273_amd import inputs as I
+
+from gpu_helpers import announce, need_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def run_fd(batch, n_steps=1, cfl=0.5, dt_fixed=0.0, sigma=0.1, rk=4, use_graph=False):
+    need_gpu()
+    B = pb.PatchBatch(batch)
+    dt = B.fd_ko_step(cfl=cfl, dt_fixed=dt_fixed, sigma_ko=sigma, rk_stages=rk, n_steps=n_steps,
+                      use_graph=use_graph, want_dt=True)
+    g = B.download()
+    st = B.stats()
+    B.close()
+    return g, dt, st
+
+
+@pytest.mark.parametrize("p,grid", [(4, (2, 2, 2)), (8, (2, 2, 1)), (16, (2, 1, 2))])
+def test_config1_fd_parity(p, grid):
+    """Seeded smooth 3D Euler on a periodic patch grid, CFL 0.5, sigma 0.1,
+    three RK4 steps (dt reduced on the device from each step's state)."""
+    announce(f"fd euler p={p} grid={grid}")
+    b = I.config1(grid=grid, p=p, halo=3, seed=40 + p)
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=3)
+    g, dt, st = run_fd(b, n_steps=3)
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+    assert st["nonfinite_units"] == 0 and st["steps"] == 3
+
+
+@pytest.mark.parametrize("sigma", [0.0, 0.05])
+def test_forward_euler_fixed_dt(sigma):
+    """rk_stages = 1 with a fixed dt (no reduction), with and without
+    dissipation."""
+    announce(f"fd euler rk1 sigma={sigma}")
+    b = I.config1(grid=(2, 2, 2), p=8, halo=3, seed=7)
+    o, _ = oracle.fd_step(b, dt_fixed=2e-4, sigma=sigma, rk_stages=1, n_steps=2)
+    g, dt, _ = run_fd(b, n_steps=2, dt_fixed=2e-4, sigma=sigma, rk=1)
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert dt == 2e-4
+
+
+def test_ragged_components():
+    """Patch sizes 3 (the smallest a halo of 3 allows), 5, 11 and 16 in one
+    batch: two 5^3 patches joined along x, the others periodic on
+    themselves (a 3^3 patch reads its whole halo from itself)."""
+    announce("fd euler ragged")
+    ps = np.array([5, 5, 11, 16, 3], np.int32)
+    nbr = np.array([[1, 1, 0, 0, 0, 0], [0, 0, 1, 1, 1, 1], [2] * 6, [3] * 6, [4] * 6], np.int32)
+    K = len(ps)
+    cells = int((ps.astype(np.int64) ** 3).sum())
+    rho = I.uniform(15, cells, 0.8, 1.2)
+    vel = [I.uniform(16 + i, cells, -0.3, 0.3) for i in range(3)]
+    pr = I.uniform(19, cells, 0.8, 1.2)
+    cons = np.stack(I.euler_prim_to_state(rho, vel, pr, 1.4))
+    off = np.concatenate([[0], np.cumsum(ps.astype(np.int64) ** 3)])
+    state = np.concatenate([cons[:, off[k]:off[k + 1]].reshape(-1) for k in range(K)])
+    b = I.Batch(dim=3, p=ps, dx=1.0 / (4.0 * ps), nbr=nbr, halo=3, pde="euler", params=np.array([1.4]),
+                n_unknowns=5, state=state)
+    o, dts = oracle.fd_step(b, cfl=0.4, sigma=0.1, n_steps=2)
+    g, dt, _ = run_fd(b, n_steps=2, cfl=0.4)
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+
+
+def test_free_stream_conservation_graph():
+    """A uniform state stays uniform; a random one keeps its totals; three
+    steps replayed from a HIP graph (with eager work between replays) equal
+    the eager steps bitwise."""
+    announce("fd euler free stream / conservation / graph")
+    torch = need_gpu()
+    b = I.config1(grid=(2, 2, 2), p=8, halo=3, seed=3)
+    uni = b.copy()
+    uni.state = b.from_global(np.stack([np.full((16, 16, 16), v) for v in
+                                        I.euler_prim_to_state(1.3, [0.4, -0.2, 0.1], 0.9, 1.4)]), (2, 2, 2))
+    g, _, _ = run_fd(uni, n_steps=2)
+    np.testing.assert_allclose(g, uni.state, rtol=0, atol=1e-14 * np.max(np.abs(uni.state)))
+    eager = pb.PatchBatch(b)
+    graph = pb.PatchBatch(b)
+    for rep in range(3):
+        eager.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=3)
+        graph.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=3, use_graph=True)
+        torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(graph.download(), eager.download())
+    g = eager.download()
+    eager.close()
+    graph.close()
+    s0 = b.to_global(b.state, (2, 2, 2)).reshape(5, -1)
+    s1 = b.to_global(g, (2, 2, 2)).reshape(5, -1)
+    for v in range(5):
+        assert abs(s1[v].sum() - s0[v].sum()) <= 1e-13 * np.abs(s0[v]).sum()
+    o, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=9)
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+
+
+def test_unsupported_shapes_rejected():
+    """Halo 1 (the FV shape) and FP32 storage are refused before any launch,
+    leaving the state alone."""
+    announce("fd euler rejects")
+    need_gpu()
+    b = I.config1(grid=(2, 1, 1), p=8, halo=1)
+    B = pb.PatchBatch(b)
+    with pytest.raises(pb.PbError, match="halo"):
+        B.fd_ko_step(cfl=0.5, sigma_ko=0.1)
+    np.testing.assert_array_equal(B.download(), b.state)
+    B.close()
+    b3 = I.config1(grid=(2, 1, 1), p=8, halo=3)
+    B = pb.PatchBatch(b3, storage="fp32")
+    with pytest.raises(pb.PbError, match="FP64"):
+        B.fd_ko_step(cfl=0.5, sigma_ko=0.1)
+    B.close()
+
+
+@pytest.mark.slow
+def test_config1_full_size_fd_parity():
+    """The full 2048 x 16^3 batch with a halo of 3 in the benchmark's launch
+    configuration, one RK4 step, against the full oracle."""
+    announce("fd euler config1 full size")
+    b = I.config1(halo=3)
+    g, dt, st = run_fd(b, n_steps=1)
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=1)
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+    assert st["nonfinite_units"] == 0
