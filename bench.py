@@ -13,7 +13,8 @@ dt on the device.  State is resident in HBM for the whole timed region.
 Further workloads are reported under "workloads": the same Euler batch with
 FP32 storage, the 2D Euler entropy wave (64x64 as 8x8 patches of 8^2) eager
 and graph-replayed, the uneven 4096-patch batch of the 58-unknown linear
-system (FD4 + KO6 + RK4, FP64 matrix cores), and special-relativistic
+system (FD4 + KO6 + RK4, FP64 matrix cores), the 3D Euler batch advanced by
+FD4 + KO6 + RK4 (halo 3, flux differencing), and special-relativistic
 hydrodynamics on 2048 x 16^3 with the plain, warm and learned con2prim guess.
 
 Prints one JSON line on stdout; progress goes to stderr.
@@ -189,6 +190,35 @@ def bench_fd(torch, pb, I, steps, warmup):
             "autotune": tuned}
 
 
+def bench_fd_euler(torch, pb, I, steps, warmup):
+    log("config-1 IC with a halo of 3 (Euler FD4 + KO6 + RK4)")
+    b = I.config1(seed=1, halo=3)
+    cells = b.total_cells
+    B = pb.PatchBatch(b)
+    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=warmup)
+    B.profile(True)
+    el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
+    kern_ms, launches = B.profile_read()
+    B.profile(False)
+    st = B.stats()
+    B.close()
+    N = b.n_unknowns
+    # per RK4 step, state-sized arrays in + out: stage 1 reads Q^n, writes the
+    # next stage value and the running sum; stages 2-3 read the stage value,
+    # Q^n and the sum, write two; stage 4 reads the stage value and the sum,
+    # writes Q^{n+1}: (1+2) + (3+2) + (3+2) + (2+1) = 16 arrays of N doubles
+    bytes_cell = 16 * N * 8
+    step_kernel_s = kern_ms / 1e3 / max(launches, 1) * 4
+    return {"workload": "3D Euler, FD4 + KO6 (sigma 0.1) + RK4, CFL 0.5, 2048 patches of 16^3 "
+                        f"({cells} cells) joined by face neighbours, halo 3, FP64, seeded Fourier-mode IC",
+            "cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
+            "stage_kernel_avg_us": kern_ms * 1e3 / max(launches, 1), "launches": launches,
+            "algorithmic_bytes_per_cell_step": bytes_cell,
+            "kernel_GBs": cells * bytes_cell / step_kernel_s / 1e9,
+            "hbm_frac": cells * bytes_cell / step_kernel_s / 1e9 / HBM_PEAK_GBS,
+            "nonfinite_units": st["nonfinite_units"]}
+
+
 def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     from paper_2608_19273_amd import mlp_train
     log("config-3 IC (SRHD, 2048 x 16^3)")
@@ -231,6 +261,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
+    ap.add_argument("--workloads", default="fp32,config0,linsym,fdeuler,srhd",
+                    help="comma list of the further workloads to run")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--mlp-pairs", type=int, default=1 << 22)
     ap.add_argument("--tuning-file", default=os.path.join(ROOT, "paper_2608_19273_amd", "tuning_gfx950.txt"),
@@ -290,17 +322,25 @@ def main():
     }
     if not args.only_headline:
         wl = {}
-        log("3D Euler FP32 storage")
-        f32 = bench_euler3d(torch, pb, b1, "fp32", args.steps, args.warmup)
-        f32["hbm_frac"] = f32["kernel_GBs"] / HBM_PEAK_GBS
-        wl["euler3d_fp32_storage"] = f32
+        want = set(args.workloads.split(","))
+        if "fp32" in want:
+            log("3D Euler FP32 storage")
+            f32 = bench_euler3d(torch, pb, b1, "fp32", args.steps, args.warmup)
+            f32["hbm_frac"] = f32["kernel_GBs"] / HBM_PEAK_GBS
+            wl["euler3d_fp32_storage"] = f32
         del b1
-        log("2D Euler entropy wave")
-        wl["euler2d_64x64_config0"] = bench_config0(torch, pb, I, 10)
-        log("FD4 + KO6 + RK4, 58 unknowns")
-        wl["linsym58_fd4_rk4"] = bench_fd(torch, pb, I, max(2, args.steps // 4), 1)
-        log("SRHD plain / warm / learned con2prim")
-        wl["srhd"] = bench_srhd(torch, pb, I, max(2, args.steps // 2), args.mlp_epochs, args.mlp_pairs)
+        if "config0" in want:
+            log("2D Euler entropy wave")
+            wl["euler2d_64x64_config0"] = bench_config0(torch, pb, I, 10)
+        if "linsym" in want:
+            log("FD4 + KO6 + RK4, 58 unknowns")
+            wl["linsym58_fd4_rk4"] = bench_fd(torch, pb, I, max(2, args.steps // 4), 1)
+        if "fdeuler" in want:
+            log("FD4 + KO6 + RK4, 3D Euler")
+            wl["euler3d_fd4_rk4"] = bench_fd_euler(torch, pb, I, max(2, args.steps // 4), 1)
+        if "srhd" in want:
+            log("SRHD plain / warm / learned con2prim")
+            wl["srhd"] = bench_srhd(torch, pb, I, max(2, args.steps // 2), args.mlp_epochs, args.mlp_pairs)
         result["workloads"] = wl
     if args.save_tuning:
         pb.pb_autotune_cache_save(args.save_tuning)

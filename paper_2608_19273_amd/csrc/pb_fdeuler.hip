@@ -71,6 +71,19 @@ __device__ __forceinline__ double ko6(double m3, double m2, double m1, double c,
 // the 5 unknowns of one cell: base points at unknown 0 of the patch block,
 // o is the cell's offset in it, C the unknown stride (all offsets fit 32
 // bits: p <= 16)
+// Work-group barrier for the LDS exchange only: wait for this wave's LDS
+// writes, then the bare barrier instruction (the compiler memory clobber
+// keeps LDS accesses on their side of it).  __syncthreads() would also wait
+// for every global load and store the wave has in flight (its fence covers
+// global memory), draining the prefetch of the next planes and the stores of
+// the last one at every barrier.  No thread reads global data another thread
+// of the launch writes, so nothing else needs ordering.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), vmcnt and expcnt unconstrained
+    __asm__ volatile("s_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ void load5(const double *__restrict__ base, unsigned o, unsigned C, double *out)
 {
 #pragma unroll
@@ -124,13 +137,17 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     const int qs = q_slot(x, yy), fxs = fx_slot(x, yy), fys = fy_slot(x, yy);
 
     // this thread's face-halo cell (threads 0 .. 12p-1): side (-x, +x, -y, +y),
-    // layer 0..2 outwards, position j along the face
+    // layer 0..2 outwards, position j along the face.  Every lane loads (the
+    // others a valid cell they do not use), so no load sits in a divergent
+    // branch: a load under one makes the compiler copy its target registers
+    // at the join, which waits for the load there and then.
     const bool halo = work && t < 12 * p;
-    int hq = 0, hf = 0;
-    bool hflux = false, hx = false;
-    const double *hsrc = y;   // unknown 0 of the halo cell's source column, plane 0
-    if (halo) {
-        const int side = t / (3 * p), r = t - side * 3 * p, layer = r / p, j = r - layer * p;
+    int hq, hf;
+    bool hflux, hx;
+    const double *hsrc;   // unknown 0 of the halo cell's source column, plane 0
+    {
+        const int th = halo ? t : 0;
+        const int side = th / (3 * p), r = th - side * 3 * p, layer = r / p, j = r - layer * p;
         int dx_, dy_, sx, sy;
         if (side == 0)      { dx_ = -1 - layer; dy_ = j; sx = p - 1 - layer; sy = j; }
         else if (side == 1) { dx_ = p + layer;  dy_ = j; sx = layer;         sy = j; }
@@ -159,27 +176,31 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     double lm[3] = {0.0, 0.0, 0.0};
     bool bad = false;
 
-    if (active) {
+    if (work) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) col(z0 - 3 + i, qr[i]);
         col(z0 + 3, rl);
 #pragma unroll
         for (int i = 0; i < 4; ++i) euler_ip(qr[1 + i], gm1, ar[i]);
+        load5(hsrc, (unsigned)z0 * pp, C, hr);
     }
-    if (halo) load5(hsrc, (unsigned)z0 * pp, C, hr);
 
 #pragma unroll 1
     for (int z = z0; z < z1; ++z) {
         const unsigned own = (unsigned)z * pp + cxy;
         double q0v[N], accv[N];
-        if (active) {
+        {
             // plane z+3 enters the window; the load of plane z+4 replaces it
+            // (at the slab's top a plane inside the window's reach is
+            // loaded again instead, unused)
 #pragma unroll
             for (int v = 0; v < N; ++v) qr[6][v] = rl[v];
-            if (z + 1 < z1) col(z + 4, rl);
+            col(min(z + 4, z1 + 2), rl);
             if (kReadQ0) load5(q0o, own, C, q0v);
             if (kReadAcc) load5(acco, own, C, accv);
             euler_ip(qr[5], gm1, ar[4]);
+        }
+        if (active) {
             double fx[N], fy[N];
             ph.flux<0>(qr[3], ar[2], fx);
             ph.flux<1>(qr[3], ar[2], fy);
@@ -190,11 +211,11 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 sFy[v][fys] = fy[v];
             }
         }
-        if (halo) {
-            double hv[N];
+        double hv[N];
 #pragma unroll
-            for (int v = 0; v < N; ++v) hv[v] = hr[v];
-            if (z + 1 < z1) load5(hsrc, (unsigned)(z + 1) * pp, C, hr);
+        for (int v = 0; v < N; ++v) hv[v] = hr[v];
+        load5(hsrc, (unsigned)min(z + 1, z1 - 1) * pp, C, hr);
+        if (halo) {
 #pragma unroll
             for (int v = 0; v < N; ++v) sQ[v][hq] = hv[v];
             if (hflux) {
@@ -211,7 +232,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 }
             }
         }
-        __syncthreads();
+        lds_barrier();
         double R[N];
         if (active) {
             // u_z of planes z-2, z-1, z+1, z+2 (window slots 1, 2, 4, 5); the
@@ -248,7 +269,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
-        __syncthreads();   // the plane's LDS is free for the next one
+        lds_barrier();   // the plane's LDS is free for the next one
         if (active) {
             double nv[N];
 #pragma unroll
