@@ -115,6 +115,19 @@ __device__ __forceinline__ void store_partial(double *__restrict__ part, const d
     }
 }
 
+// Work-group barrier for the LDS exchange only: wait for this wave's LDS
+// writes, then the bare barrier instruction (the compiler memory clobber
+// keeps LDS accesses on their side of it).  __syncthreads() would also wait
+// for every global load and store the wave has in flight (its fence covers
+// global memory), draining the prefetch of the next planes and the stores of
+// the last one at every barrier.  Only for kernels in which no thread reads
+// global data another thread of the launch writes.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), vmcnt and expcnt unconstrained
+    __asm__ volatile("s_barrier" ::: "memory");
+}
+
 __device__ __forceinline__ int xcd_remap(int bid, int n)
 {
     const int q = n >> 3, r = n & 7;

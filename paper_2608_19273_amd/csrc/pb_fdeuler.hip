@@ -71,19 +71,6 @@ __device__ __forceinline__ double ko6(double m3, double m2, double m1, double c,
 // the 5 unknowns of one cell: base points at unknown 0 of the patch block,
 // o is the cell's offset in it, C the unknown stride (all offsets fit 32
 // bits: p <= 16)
-// Work-group barrier for the LDS exchange only: wait for this wave's LDS
-// writes, then the bare barrier instruction (the compiler memory clobber
-// keeps LDS accesses on their side of it).  __syncthreads() would also wait
-// for every global load and store the wave has in flight (its fence covers
-// global memory), draining the prefetch of the next planes and the stores of
-// the last one at every barrier.  No thread reads global data another thread
-// of the launch writes, so nothing else needs ordering.
-__device__ __forceinline__ void lds_barrier()
-{
-    __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0), vmcnt and expcnt unconstrained
-    __asm__ volatile("s_barrier" ::: "memory");
-}
-
 __device__ __forceinline__ void load5(const double *__restrict__ base, unsigned o, unsigned C, double *out)
 {
 #pragma unroll

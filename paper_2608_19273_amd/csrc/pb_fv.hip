@@ -185,7 +185,12 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     auto own_plane_off = [&](int zz) -> long long { return zz >= p ? onb[5] : P.off; };
     auto own_plane_c = [&](int zz) -> long long { return (zz >= p ? zz - p : zz) * pp + cxy; };
 
-    if (active) {
+    // Every lane issues every load (idle lanes at a valid address they do not
+    // use), and the prefetch at the slab's top reloads a plane in reach
+    // instead of skipping: a load under a divergent or conditional branch
+    // makes the compiler copy its target registers at the join, which waits
+    // for the load right there and empties the prefetch ring.
+    if (work) {
         RawCell<Ph, T> rc;
         issue_load<Ph>(qin, ex, P.off, C, z0 * pp + cxy, rc);
         if (DIM == 3) {
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
             const int zm = (z0 == 0) ? p - 1 : z0 - 1;
             issue_load<Ph>(qin, ex, om, C, zm * pp + cxy, rm);
             issue_load<Ph>(qin, ex, own_plane_off(z0 + 1), C, own_plane_c(z0 + 1), rnA);
-            if (z0 + 1 < z1) issue_load<Ph>(qin, ex, own_plane_off(z0 + 2), C, own_plane_c(z0 + 2), rnB);
+            issue_load<Ph>(qin, ex, own_plane_off(min(z0 + 2, z1)), C, own_plane_c(min(z0 + 2, z1)), rnB);
             double qm[N], am[AA], fzm[N];
             unpack<Ph>(rm, qm, e);
             ph.aux(qm, e, am);
@@ -209,9 +214,9 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
             ph.aux(qc, e, ac);
         }
     }
-    if (halo) {
+    if (work) {
         issue_load<Ph>(qin, ex, hoff, C, z0 * pp + hsrc, hrA);
-        if (z0 + 1 < z1) issue_load<Ph>(qin, ex, hoff, C, (z0 + 1) * pp + hsrc, hrB);
+        issue_load<Ph>(qin, ex, hoff, C, min(z0 + 1, z1 - 1) * pp + hsrc, hrB);
     }
 
     // one plane: consumes rn (own plane z+1) and hr (halo of plane z), then
@@ -220,18 +225,19 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
         double(*buf)[PH * PH] = lds[z & 1];
         double qn[N], an[AA], fzn[N];
         double lzn = 0.0;
-        if (DIM == 3 && active) {
+        if (DIM == 3) {
             unpack<Ph>(rn, qn, e);
-            if (z + 2 < z1) issue_load<Ph>(qin, ex, own_plane_off(z + 3), C, own_plane_c(z + 3), rn);
+            issue_load<Ph>(qin, ex, own_plane_off(min(z + 3, z1)), C, own_plane_c(min(z + 3, z1)), rn);
             ph.aux(qn, e, an);
             phys_flux_or_zero<Ph, DZ>(ph, qn, an, fzn);
             lzn = ph.template eig<DZ>(qn, an);
         }
+        double hq[N], he[1];
+        unpack<Ph>(hr, hq, he);
+        issue_load<Ph>(qin, ex, hoff, C, min(z + 2, z1 - 1) * pp + hsrc, hr);
         if (halo) {
-            double hq[N], ha[AA];
-            unpack<Ph>(hr, hq, e);
-            if (z + 2 < z1) issue_load<Ph>(qin, ex, hoff, C, (z + 2) * pp + hsrc, hr);
-            ph.aux(hq, e, ha);
+            double ha[AA];
+            ph.aux(hq, he, ha);
 #pragma unroll
             for (int v = 0; v < N; ++v) buf[v][hdst] = hq[v];
 #pragma unroll
@@ -243,7 +249,7 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
 #pragma unroll
             for (int a = 0; a < A; ++a) buf[N + a][li] = ac[a];
         }
-        __syncthreads();
+        lds_barrier();   // (no thread reads what another writes to global memory)
         if (active) {
             double acc2[N];
 #pragma unroll
