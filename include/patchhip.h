@@ -142,6 +142,10 @@ pb_status pb_batch_stats(pb_batch *b, pb_stats *out);
  * use_graph != 0 captures the n_steps launches once into a HIP graph and
  * replays it on later calls with the same n_steps.
  * dt_last_host (nullable): receives the last step's dt (synchronises).
+ * 3D batches whose patches all have one p with p^3 <= 256 run a kernel that
+ * packs several whole patches into a work-group (one thread per cell); the
+ * others march z-slabs of a patch plane by plane.  Both give the same
+ * results to roundoff.
  * Supported: ADVECTION_F/B (N = 1), EULER, SRHD; 1 <= p <= 16; halo >= 1.
  */
 pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_steps,
@@ -306,6 +310,8 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  * dt_fixed as there).  Candidates:
  *   FV 3D: fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0}
  *          x fv_dma {1, 0} (only 0 where the DMA-fed kernel does not apply);
+ *          a batch of one p with p^3 <= 256 runs the small-patch kernel,
+ *          which has no launch-shape choice: one candidate, the current one;
  *   FV 2D: fv_xcd_remap {1, 0};
  *   FD:    fd_xcd_remap {1, 0} x fd_wg_per_cu {2, 1}.
  * Each candidate runs one untimed launch and then `trials` timed launches

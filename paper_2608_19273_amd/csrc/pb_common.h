@@ -223,6 +223,11 @@ pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const voi
 // the DMA-fed FV kernel applies to this batch (3D, no extra per-cell input,
 // every p a multiple of 4, 16-byte aligned state buffers)
 bool fv_dma_eligible(const pb_batch *b);
+// the small-patch FV kernel applies (3D, one p, p^3 <= 256 threads); its
+// work-groups take as many patches as fit 256 threads and an LDS box of
+// (p+2)^3 slots of N + A doubles per patch within kFvSmallLds bytes
+constexpr size_t kFvSmallLds = 64 * 1024;
+bool fv_small_eligible(const pb_batch *b);
 // dt of an FD step: dt_fixed if > 0, else cfl / sum_d (rho(B_d) / dx_min)
 double fd_dt(const pb_batch *b, double cfl, double dt_fixed);
 // uploads the FD work list and B_d (library-owned; done once, before any capture)

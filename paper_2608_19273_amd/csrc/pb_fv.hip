@@ -593,6 +593,112 @@ __global__ __launch_bounds__(kFvThreads, 2) void fv_step_dma_kernel(
     if (kLam) store_partial<3>(part, lm, unit, n_units);
 }
 
+// ---------------------------------------------------------------------------
+// Small patches (3D, one p for the whole batch, p^3 <= 256).  The plane march
+// leaves most of a work-group idle when p^2 is small (9 of 256 threads for
+// p = 3).  Here a work-group takes G whole patches, one thread per cell:
+//   1. every thread stages its cell's Q and aux in an LDS box of (p+2)^3
+//      slots per patch (edges and corners unused), and the work-group stages
+//      the G * 6p^2 face-halo cells read from the neighbours (the halo
+//      gather, again fused into the load);
+//   2. after one barrier every thread evaluates the three directions in the
+//      difference form of the plane kernel from its six face neighbours,
+//      updates, stores and folds the speeds of the new state.
+// G = min(256 / p^3, 64 KB / box) is chosen by the launcher.
+template <class Ph, typename T, bool kLam>
+__global__ __launch_bounds__(kFvThreads) void fv_small_kernel(
+    const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
+    const PatchDev *__restrict__ patches, int K, int p, int G, Ctrl *__restrict__ ctrl,
+    double *__restrict__ part, int slot_in, double dt_fixed, Ph ph)
+{
+    constexpr int N = Ph::N, A = Ph::A, AA = A > 0 ? A : 1;
+    extern __shared__ double box[];   // [N + A][G * B]
+    const int t = threadIdx.x;
+    const int P3 = p * p * p, pb = p + 2, B = pb * pb * pb, SL = G * B;
+    const int k0 = blockIdx.x * G;
+    const int g = t / P3, l = t - g * P3;
+    const bool active = g < G && k0 + g < K;
+    const int x = l % p, y = (l / p) % p, z = l / (p * p);
+    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot_in];
+    auto slot = [&](int gg, int xx, int yy, int zz) { return gg * B + ((zz + 1) * pb + (yy + 1)) * pb + (xx + 1); };
+
+    double qc[N], ac[AA], e[1] = {0.0};
+    double inv_dx = 0.0;
+    const int s = slot(active ? g : 0, x, y, z);
+    if (active) {
+        const PatchDev P = patches[k0 + g];
+        inv_dx = P.inv_dx;
+        load_cell<Ph>(qin, ex, P.off, P3, l, qc, e);
+        ph.aux(qc, e, ac);
+#pragma unroll
+        for (int v = 0; v < N; ++v) box[v * SL + s] = qc[v];
+#pragma unroll
+        for (int a = 0; a < A; ++a) box[(N + a) * SL + s] = ac[a];
+    }
+    // face halos: face f = 2 dir + side of patch gg, position (i, j) on it
+    const int HF = p * p, HP = 6 * HF;
+    for (int h = t; h < G * HP; h += blockDim.x) {
+        const int gg = h / HP, r = h - gg * HP, f = r / HF, ij = r - f * HF, i = ij % p, j = ij / p;
+        if (k0 + gg >= K) break;   // h only grows, and so does gg
+        const int dir = f >> 1, side = f & 1;
+        const int nb = patches[k0 + gg].nbr[f];
+        const int at = side ? p : -1, from = side ? 0 : p - 1;
+        int dx_, dy_, dz_, sx, sy, sz;
+        if (dir == 0)      { dx_ = at; sx = from; dy_ = sy = i; dz_ = sz = j; }
+        else if (dir == 1) { dy_ = at; sy = from; dx_ = sx = i; dz_ = sz = j; }
+        else               { dz_ = at; sz = from; dx_ = sx = i; dy_ = sy = j; }
+        double hq[N], ha[AA], he[1] = {0.0};
+        load_cell<Ph>(qin, ex, patches[nb].off, P3, (sz * p + sy) * p + sx, hq, he);
+        ph.aux(hq, he, ha);
+        const int d = slot(gg, dx_, dy_, dz_);
+#pragma unroll
+        for (int v = 0; v < N; ++v) box[v * SL + d] = hq[v];
+#pragma unroll
+        for (int a = 0; a < A; ++a) box[(N + a) * SL + d] = ha[a];
+    }
+    lds_barrier();   // (no thread reads what another writes to global memory)
+
+    double lm[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    if (active) {
+        double acc2[N];
+#pragma unroll
+        for (int v = 0; v < N; ++v) acc2[v] = 0.0;
+        auto dirn = [&](auto D, int st) {
+            double qL[N], aL[AA], qR[N], aR[AA];
+#pragma unroll
+            for (int v = 0; v < N; ++v) { qL[v] = box[v * SL + s - st]; qR[v] = box[v * SL + s + st]; }
+#pragma unroll
+            for (int a = 0; a < A; ++a) { aL[a] = box[(N + a) * SL + s - st]; aR[a] = box[(N + a) * SL + s + st]; }
+            rusanov_pair2<Ph, decltype(D)::value>(ph, qL, aL, qc, ac, qR, aR, acc2);
+        };
+        dirn(std::integral_constant<int, 0>(), 1);
+        dirn(std::integral_constant<int, 1>(), pb);
+        dirn(std::integral_constant<int, 2>(), pb * pb);
+        double S[N];
+        if (Ph::kSrc) {
+            ph.source(qc, ac, S);
+        } else {
+#pragma unroll
+            for (int v = 0; v < N; ++v) S[v] = 0.0;
+        }
+        const double hr_ = 0.5 * dt * inv_dx;
+        const PatchDev P = patches[k0 + g];
+        T *dst = qout + P.off * N + l;
+        double qw[N];
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+            const T st = (T)(qc[v] - hr_ * acc2[v] + dt * S[v]);
+            __builtin_nontemporal_store(st, dst + (long long)v * P3);
+            qw[v] = (double)st;
+            bad |= !isfinite(qw[v]);
+        }
+        if (kLam) cell_speeds_fast<Ph, 3>(ph, qw, lm);
+    }
+    if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
+    if (kLam) store_partial<3>(part, lm, blockIdx.x, gridDim.x);
+}
+
 // Largest speeds of the current state (first step of a call in CFL mode):
 // one work-group per patch, partial maxima per patch.
 template <class Ph, int DIM, typename T>
@@ -727,6 +833,25 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     T *qo = static_cast<T *>(qout);
     const double *ex = Ph::E ? reinterpret_cast<const double *>(b->ws + L.pres)
                              : nullptr;
+    if constexpr (DIM == 3) {
+      if (fv_small_eligible(b)) {
+        const int p = b->p[0], box = (p + 2) * (p + 2) * (p + 2);
+        const int G = std::max(1, std::min(kFvThreads / (p * p * p),
+                                           (int)(kFvSmallLds / ((Ph::N + Ph::A) * box * sizeof(double)))));
+        const int nwg = (b->K + G - 1) / G;
+        const size_t lds = (size_t)(Ph::N + Ph::A) * G * (p + 2) * (p + 2) * (p + 2) * sizeof(double);
+        const bool lam = !(dt_fixed > 0.0) && Ph::E == 0;
+        if (lam)
+            hipLaunchKernelGGL((fv_small_kernel<Ph, T, true>), dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
+                               b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, ph);
+        else
+            hipLaunchKernelGGL((fv_small_kernel<Ph, T, false>), dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
+                               b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, ph);
+        PB_HIP(hipGetLastError());
+        if (lam) return launch_dt_reduce(b, part, nwg, DIM, slot_in ^ 1, cfl, true, false, s);
+        return PB_OK;
+      }
+    }
     if constexpr (Ph::E > 0) {  // SRHD: dt comes from the con2prim pass
         hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                            ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
@@ -808,6 +933,11 @@ pb_status dispatch(pb_batch *b, F &&f)
 }
 
 }  // namespace
+
+bool fv_small_eligible(const pb_batch *b)
+{
+    return b->dim == 3 && b->uniform_p && b->p[0] * b->p[0] * b->p[0] <= kFvThreads;
+}
 
 bool fv_dma_eligible(const pb_batch *b)
 {

@@ -62,7 +62,9 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
 {
     std::vector<pb_tuning> c;
     const pb_tuning base = current(b);
-    if (kind == 0) {
+    if (kind == 0 && fv_small_eligible(b)) {
+        c.push_back(base);   // the small-patch kernel has no launch-shape choices
+    } else if (kind == 0) {
         std::vector<int> slabs;
         if (b->dim == 3) {
             for (int s = b->pmax; s >= 2; s /= 2) slabs.push_back(s);

@@ -65,6 +65,41 @@ def test_euler3d_fp32_storage():
     assert np.all(rel_err(b, g, o64) <= 1e-5), rel_err(b, g, o64)
 
 
+@pytest.mark.parametrize("p,grid", [(1, (3, 2, 2)), (2, (3, 3, 2)), (3, (4, 3, 3)), (4, (3, 2, 1)),
+                                    (5, (2, 2, 3)), (6, (3, 2, 2))])
+def test_small_patch_kernel(p, grid):
+    """3D batches of one p with p^3 <= 256 run the kernel that packs whole
+    patches into a work-group (one thread per cell, halos staged in an LDS
+    box); patch counts that are not a multiple of the group size leave a
+    partly filled last work-group.  Three CFL steps, FP64 and FP32 storage."""
+    announce(f"small patches p={p} grid={grid}")
+    b = I.config1(grid=grid, p=p, seed=50 + p)
+    o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=3)
+    g, dt, st = run_gpu(b, n_steps=3)
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+    assert st["nonfinite_units"] == 0
+    b32 = b.copy()
+    b32.state = b.state.astype(np.float32).astype(np.float64)
+    o32, _, _ = oracle.fv_step(b32, cfl=0.4, n_steps=3, round_fp32=True)
+    g32, _, _ = run_gpu(b32, storage="fp32", n_steps=3)
+    assert np.all(rel_err(b32, g32, o32) <= 1e-5), rel_err(b32, g32, o32)
+
+
+def test_small_patch_advection_exact_shift():
+    """Advection at CFL 1 along each axis is an exact shift by one cell, also
+    through the small-patch kernel's halo staging (3^3 patches, 2x2x2 grid)."""
+    announce("small patches exact shift")
+    for axis in range(3):
+        a = [0.0, 0.0, 0.0]
+        a[axis] = 1.0
+        b = I.make_uniform_batch((2, 2, 2), 3, 1, "adv_f", a + [0.0], 1, 1.0 / 6)
+        b.state = I.uniform(90 + axis, b.state.size, -1.0, 1.0)
+        g, _, _ = run_gpu(b, n_steps=1, cfl=1.0)
+        ref = b.to_global(b.state, (2, 2, 2))
+        np.testing.assert_allclose(b.to_global(g, (2, 2, 2)), np.roll(ref, 1, axis=3 - axis), rtol=0, atol=1e-14)
+
+
 @pytest.mark.parametrize("form", ["adv_f", "adv_b"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_exact_shift_gpu(form, dim):
