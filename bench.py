@@ -14,8 +14,10 @@ Further workloads are reported under "workloads": the same Euler batch with
 FP32 storage, the 2D Euler entropy wave (64x64 as 8x8 patches of 8^2) eager
 and graph-replayed, the uneven 4096-patch batch of the 58-unknown linear
 system (FD4 + KO6 + RK4, FP64 matrix cores), the 3D Euler batch advanced by
-FD4 + KO6 + RK4 (halo 3, flux differencing), and special-relativistic
-hydrodynamics on 2048 x 16^3 with the plain, warm and learned con2prim guess.
+FD4 + KO6 + RK4 (halo 3, flux differencing), special-relativistic
+hydrodynamics on 2048 x 16^3 with the plain, warm and learned con2prim guess,
+and the K sweep (runtime per cell against the number of independent patches
+for p = 3, 6, 16, FV and FD4).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -219,6 +221,47 @@ def bench_fd_euler(torch, pb, I, steps, warmup):
             "nonfinite_units": st["nonfinite_units"]}
 
 
+KSWEEP_K = (1, 4, 16, 64, 256, 1024, 4096, 8694, 16384)
+
+
+def bench_ksweep(torch, pb, I, k_max_16=8694):
+    """Runtime per cell against the batch size K (the shape of the paper's
+    main experiment): K independent 3D Euler patches of p^3 cells for
+    p in {3, 6, 16}, the FV step (CFL 0.4) and the FD4 + KO6 + RK4 step (CFL
+    0.5, sigma 0.1), eager launches and the same steps replayed from a HIP
+    graph, each timed by wall clock and events; per cell means per
+    cell-update (FV) and per cell-step of all four RK stages (FD)."""
+    out = {}
+    for scheme in ("fv", "fd"):
+        for p in (3, 6, 16):
+            rows = []
+            for K in KSWEEP_K:
+                if p == 16 and K > k_max_16:
+                    continue
+                b = I.independent_euler_patches(7, K, p, halo=3 if scheme == "fd" else 1)
+                cells = b.total_cells
+                B = pb.PatchBatch(b)
+                if scheme == "fv":
+                    step = lambda n, g: B.fv_rusanov_step(cfl=0.4, n_steps=n, use_graph=g)
+                else:
+                    step = lambda n, g: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n, use_graph=g)
+                n = int(min(200, max(3, round(5e7 / (cells * (4 if scheme == "fd" else 1))))))
+                step(1, False)
+                el = timed(torch, lambda: step(n, False))
+                step(n, True)   # capture (and one replay) outside the timed region
+                elg = timed(torch, lambda: step(n, True))
+                st = B.stats()
+                B.close()
+                rows.append({"K": K, "cells": cells, "steps": n, "ns_per_cell": el / (n * cells) * 1e9,
+                             "us_per_step": el / n * 1e6, "ns_per_cell_graph": elg / (n * cells) * 1e9,
+                             "us_per_step_graph": elg / n * 1e6, "nonfinite_units": st["nonfinite_units"]})
+                del b
+            out[f"{scheme}_p{p}"] = rows
+            log(f"k-sweep {scheme} p={p}: " + ", ".join(f"K={r['K']}: {r['ns_per_cell']:.3f}/{r['ns_per_cell_graph']:.3f} ns"
+                                                      for r in rows))
+    return out
+
+
 def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     from paper_2608_19273_amd import mlp_train
     log("config-3 IC (SRHD, 2048 x 16^3)")
@@ -261,7 +304,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="fp32,config0,linsym,fdeuler,srhd",
+    ap.add_argument("--workloads", default="fp32,config0,linsym,fdeuler,srhd,ksweep",
                     help="comma list of the further workloads to run")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--mlp-pairs", type=int, default=1 << 22)
@@ -341,6 +384,9 @@ def main():
         if "srhd" in want:
             log("SRHD plain / warm / learned con2prim")
             wl["srhd"] = bench_srhd(torch, pb, I, max(2, args.steps // 2), args.mlp_epochs, args.mlp_pairs)
+        if "ksweep" in want:
+            log("K sweep: runtime per cell against the batch size, p in {3, 6, 16}, FV and FD4")
+            wl["k_sweep"] = bench_ksweep(torch, pb, I)
         result["workloads"] = wl
     if args.save_tuning:
         pb.pb_autotune_cache_save(args.save_tuning)

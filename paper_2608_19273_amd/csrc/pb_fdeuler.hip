@@ -304,16 +304,210 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     }
 }
 
+// ---------------------------------------------------------------------------
+// Small patches (one p for the batch, p^3 <= 256, so 3 <= p <= 6 with the
+// halo of 3).  The plane march would leave all but p^2 threads of a
+// work-group idle; here a work-group takes G whole patches, one thread per
+// cell, and stages each patch with its face halos in LDS in a cross layout:
+// the p^3 interior slots, then for faces -x, +x, -y, +y, -z, +z three
+// layers of p^2 slots each (layer 0 touching the patch), 7 doubles per slot
+// (Q, 1/rho, p).  Every thread then reads its 18 stencil slots, evaluates
+// the 12 fluxes its D4 terms need (F_d at +-1, +-2 along d) from the staged
+// Q and aux, and updates as the plane kernel does.
+namespace {
+
+struct SmallGeom {
+    int p, p2, p3, slots;   // slots per patch: p^3 + 18 p^2
+};
+
+// slot of tile-local (x, y, z), at most one coordinate outside [0, p)
+__device__ __forceinline__ int cross_slot(const SmallGeom &g, int x, int y, int z)
+{
+    const int lay = 3 * g.p2;
+    if (x < 0) return g.p3 + 0 * lay + (-x - 1) * g.p2 + z * g.p + y;
+    if (x >= g.p) return g.p3 + 1 * lay + (x - g.p) * g.p2 + z * g.p + y;
+    if (y < 0) return g.p3 + 2 * lay + (-y - 1) * g.p2 + z * g.p + x;
+    if (y >= g.p) return g.p3 + 3 * lay + (y - g.p) * g.p2 + z * g.p + x;
+    if (z < 0) return g.p3 + 4 * lay + (-z - 1) * g.p2 + y * g.p + x;
+    if (z >= g.p) return g.p3 + 5 * lay + (z - g.p) * g.p2 + y * g.p + x;
+    return (z * g.p + y) * g.p + x;
+}
+
+constexpr int kSmallW = 7;   // Q (5), 1/rho, p per slot
+
+}  // namespace
+
+template <int S, bool kLam>
+__global__ __launch_bounds__(kFvThreads) void fd_euler_small_kernel(
+    const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
+    double *__restrict__ acc, const PatchDev *__restrict__ patches, int K, int p, int G, Ctrl *__restrict__ ctrl,
+    double *__restrict__ part, int slot, double dt_fixed, double gamma, double sigma)
+{
+    constexpr int N = kEN;
+    constexpr bool kReadQ0 = S == 1 || S == 2;
+    constexpr bool kReadAcc = S == 1 || S == 2 || S == 3;
+    constexpr bool kFinal = S == 3 || S == 4;
+    extern __shared__ double sm[];   // [kSmallW][G * slots]
+    const SmallGeom geo{p, p * p, p * p * p, p * p * p + 18 * p * p};
+    const int SL = G * geo.slots;
+    const int t = threadIdx.x;
+    const int k0 = blockIdx.x * G;
+    const int g = t / geo.p3, l = t - g * geo.p3;
+    const bool active = g < G && k0 + g < K;
+    const int x = l % p, yy = (l / p) % p, z = l / geo.p2;
+    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot];
+    const double gm1 = gamma - 1.0;
+    const Euler<3> ph{gamma};
+    const unsigned C = (unsigned)geo.p3;
+
+    // 1. stage the interior cells and the face halos
+    double qc[N];
+    long long off = 0;
+    double inv_dx = 0.0;
+    if (active) {
+        const PatchDev P = patches[k0 + g];
+        off = P.off;
+        inv_dx = P.inv_dx;
+        load5(y + off * N, (unsigned)l, C, qc);
+        double a[2];
+        euler_ip(qc, gm1, a);
+        const int s0 = g * geo.slots + l;
+#pragma unroll
+        for (int v = 0; v < N; ++v) sm[v * SL + s0] = qc[v];
+        sm[5 * SL + s0] = a[0];
+        sm[6 * SL + s0] = a[1];
+    }
+    const int HP = 18 * geo.p2;   // halo cells per patch
+    for (int h = t; h < G * HP; h += blockDim.x) {
+        const int gg = h / HP, r = h - gg * HP;
+        if (k0 + gg >= K) break;   // h only grows, and so does gg
+        const int f = r / (3 * geo.p2), rr = r - f * 3 * geo.p2, L = rr / geo.p2, ab = rr - L * geo.p2;
+        const int a_ = ab / p, b_ = ab - a_ * p;
+        const int in = L, out = p - 1 - L;   // source layer for the + and - faces
+        int sx, sy, sz;
+        switch (f) {
+        case 0: sx = out; sy = b_; sz = a_; break;
+        case 1: sx = in;  sy = b_; sz = a_; break;
+        case 2: sx = b_; sy = out; sz = a_; break;
+        case 3: sx = b_; sy = in;  sz = a_; break;
+        case 4: sx = b_; sy = a_; sz = out; break;
+        default: sx = b_; sy = a_; sz = in; break;
+        }
+        const int nb = patches[k0 + gg].nbr[f];
+        double hq[N], a[2];
+        load5(y + patches[nb].off * N, (unsigned)((sz * p + sy) * p + sx), C, hq);
+        euler_ip(hq, gm1, a);
+        const int d = gg * geo.slots + geo.p3 + r;
+#pragma unroll
+        for (int v = 0; v < N; ++v) sm[v * SL + d] = hq[v];
+        sm[5 * SL + d] = a[0];
+        sm[6 * SL + d] = a[1];
+    }
+    lds_barrier();
+
+    double lm[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    if (active) {
+        const int base = g * geo.slots;
+        // stencil slots along each direction: offsets -3, -2, -1, +1, +2, +3
+        int st[3][6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) {
+            const int o = k < 3 ? k - 3 : k - 2;
+            st[0][k] = base + cross_slot(geo, x + o, yy, z);
+            st[1][k] = base + cross_slot(geo, x, yy + o, z);
+            st[2][k] = base + cross_slot(geo, x, yy, z + o);
+        }
+        const double c4 = inv_dx / 12.0, cko = sigma * inv_dx / 64.0;
+        double R[N], kox[N];
+#pragma unroll
+        for (int v = 0; v < N; ++v) { R[v] = 0.0; kox[v] = 0.0; }
+        auto dir = [&](auto D) {
+            constexpr int d = decltype(D)::value;
+            // D4 of F_d from the fluxes at -2, -1, +1, +2 (slots 1, 2, 3, 4)
+            double F[4][N];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int sl = st[d][i + 1];
+                double q[N], a[2];
+#pragma unroll
+                for (int v = 0; v < N; ++v) q[v] = sm[v * SL + sl];
+                a[0] = sm[5 * SL + sl];
+                a[1] = sm[6 * SL + sl];
+                ph.flux<d>(q, a, F[i]);
+            }
+#pragma unroll
+            for (int v = 0; v < N; ++v) {
+                R[v] += d4(F[0][v], F[1][v], F[2][v], F[3][v]);
+                kox[v] += ko6(sm[v * SL + st[d][0]], sm[v * SL + st[d][1]], sm[v * SL + st[d][2]], qc[v],
+                              sm[v * SL + st[d][3]], sm[v * SL + st[d][4]], sm[v * SL + st[d][5]]);
+            }
+        };
+        dir(std::integral_constant<int, 0>());
+        dir(std::integral_constant<int, 1>());
+        dir(std::integral_constant<int, 2>());
+        const unsigned own = (unsigned)l;
+        double q0v[N], accv[N], nv[N];
+        if (kReadQ0) load5(q0 + off * N, own, C, q0v);
+        if (kReadAcc) load5(acc + off * N, own, C, accv);
+        double *yno = ynext + off * N, *accw = acc + off * N;
+#pragma unroll
+        for (int v = 0; v < N; ++v) {
+            const double Rv = cko * kox[v] - c4 * R[v];
+            const unsigned gi = own + v * C;
+            if (S == 0) {
+                yno[gi] = qc[v] + (0.5 * dt) * Rv;
+                nv[v] = qc[v] + (dt / 6.0) * Rv;
+            } else if (S == 1) {
+                yno[gi] = q0v[v] + (0.5 * dt) * Rv;
+                nv[v] = accv[v] + (dt / 3.0) * Rv;
+            } else if (S == 2) {
+                yno[gi] = q0v[v] + dt * Rv;
+                nv[v] = accv[v] + (dt / 3.0) * Rv;
+            } else if (S == 3) {
+                nv[v] = accv[v] + (dt / 6.0) * Rv;
+            } else {
+                nv[v] = qc[v] + dt * Rv;
+            }
+            accw[gi] = nv[v];
+        }
+        if (kFinal) {
+#pragma unroll
+            for (int v = 0; v < N; ++v) bad |= !isfinite(nv[v]);
+            if (kLam) {
+                double a[3];
+                ph.aux_fast(nv, nullptr, a);
+                lm[0] = fmax(lm[0], ph.eig<0>(nv, a));
+                lm[1] = fmax(lm[1], ph.eig<1>(nv, a));
+                lm[2] = fmax(lm[2], ph.eig<2>(nv, a));
+            }
+        }
+    }
+    if (kFinal) {
+        if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
+        if (kLam) store_partial<3>(part, lm, blockIdx.x, gridDim.x);
+    }
+}
+
 // ------------------------------------------------------------------ host --
 
 namespace {
 
+// G > 0: the small-patch kernel with G patches per work-group (n_units = work-groups)
 template <int S, bool kLam>
 void launch_s(dim3 g, hipStream_t s, const double *y, const double *q0, double *yn, double *acc, const pb_batch *b,
-              int n_units, int n_slabs, int slab, Ctrl *ctrl, double *part, int slot, double dt_fixed, double sigma)
+              int n_units, int n_slabs, int slab, int G, Ctrl *ctrl, double *part, int slot, double dt_fixed,
+              double sigma)
 {
-    hipLaunchKernelGGL((fd_euler_stage_kernel<S, kLam>), g, dim3(kFvThreads), 0, s, y, q0, yn, acc, b->d_patches,
-                       n_units, n_slabs, slab, b->fd_xcd_remap, ctrl, part, slot, dt_fixed, b->params[0], sigma);
+    if (G > 0) {
+        const int p = b->p[0];
+        const size_t lds = (size_t)kSmallW * G * (p * p * p + 18 * p * p) * sizeof(double);
+        hipLaunchKernelGGL((fd_euler_small_kernel<S, kLam>), g, dim3(kFvThreads), lds, s, y, q0, yn, acc,
+                           b->d_patches, b->K, p, G, ctrl, part, slot, dt_fixed, b->params[0], sigma);
+    } else {
+        hipLaunchKernelGGL((fd_euler_stage_kernel<S, kLam>), g, dim3(kFvThreads), 0, s, y, q0, yn, acc, b->d_patches,
+                           n_units, n_slabs, slab, b->fd_xcd_remap, ctrl, part, slot, dt_fixed, b->params[0], sigma);
+    }
 }
 
 }  // namespace
@@ -322,7 +516,16 @@ pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const voi
                                 void *acc, int slot, double dt_fixed, double cfl, double sigma, hipStream_t s)
 {
     if (b->pmax > kFvPmax) { set_error("fd_ko_step: p > 16 is not supported for EULER"); return PB_EUNSUPPORTED; }
-    const int slab = b->pmax, n_slabs = 1, n_units = b->K * n_slabs;
+    const int slab = b->pmax, n_slabs = 1;
+    // one p with p^3 <= 256: whole patches per work-group (LDS cross layout
+    // of 7 doubles per slot, at most 64 KB per work-group)
+    int G = 0;
+    if (b->uniform_p && b->p[0] * b->p[0] * b->p[0] <= kFvThreads) {
+        const int p = b->p[0];
+        const size_t per = (size_t)kSmallW * (p * p * p + 18 * p * p) * sizeof(double);
+        G = std::max(1, std::min(kFvThreads / (p * p * p), (int)(kFvSmallLds / per)));
+    }
+    const int n_units = G > 0 ? (b->K + G - 1) / G : b->K * n_slabs;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
     const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     double *part = reinterpret_cast<double *>(b->ws + L.part);
@@ -332,7 +535,7 @@ pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const voi
     const double *yi = static_cast<const double *>(y), *q0i = static_cast<const double *>(q0);
     double *yn = static_cast<double *>(ynext), *ac = static_cast<double *>(acc);
     const dim3 g(n_units);
-#define PB_FDE_ARGS g, s, yi, q0i, yn, ac, b, n_units, n_slabs, slab, ctrl, part, slot, dt_fixed, sigma
+#define PB_FDE_ARGS g, s, yi, q0i, yn, ac, b, n_units, n_slabs, slab, G, ctrl, part, slot, dt_fixed, sigma
     switch (S) {
     case 0: launch_s<0, false>(PB_FDE_ARGS); break;
     case 1: launch_s<1, false>(PB_FDE_ARGS); break;

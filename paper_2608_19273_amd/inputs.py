@@ -264,6 +264,21 @@ def config1(seed: int = 1, grid=C1_GRID, p: int = 16, gamma: float = 1.4, halo: 
     return b
 
 
+def independent_euler_patches(seed: int, K: int, p: int, halo: int = 1, gamma: float = 1.4) -> Batch:
+    """K independent 3D Euler patches of p^3 cells (each periodic on itself,
+    dx = 1/p), i.i.d. primitives per cell: rho, p ~ U[0.8, 1.2], each
+    velocity component ~ U[-0.3, 0.3].  The batch shape of the K sweep
+    (many small patches handed over at once, each with its own halo)."""
+    n = K * p ** 3
+    rho = uniform(substream(seed, 1), n, 0.8, 1.2)
+    vel = [uniform(substream(seed, 2 + d), n, -0.3, 0.3) for d in range(3)]
+    pr = uniform(substream(seed, 5), n, 0.8, 1.2)
+    cons = np.stack(euler_prim_to_state(rho, vel, pr, gamma))            # [5, K p^3]
+    state = np.ascontiguousarray(cons.reshape(5, K, p ** 3).transpose(1, 0, 2)).reshape(-1)
+    return Batch(dim=3, p=np.full(K, p, np.int32), dx=np.full(K, 1.0 / p), nbr=self_periodic(K, 3), halo=halo,
+                 pde="euler", params=np.array([gamma]), n_unknowns=5, state=state)
+
+
 # ------------------------------------------------------------------- SRHD --
 
 

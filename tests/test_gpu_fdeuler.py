@@ -37,6 +37,26 @@ def test_config1_fd_parity(p, grid):
     assert st["nonfinite_units"] == 0 and st["steps"] == 3
 
 
+@pytest.mark.parametrize("p,grid", [(3, (3, 2, 2)), (5, (2, 1, 3)), (6, (2, 2, 1))])
+def test_small_patch_fd_kernel(p, grid):
+    """Batches of one p with p^3 <= 256 run the kernel that packs whole
+    patches into a work-group (halos staged in an LDS cross layout): periodic
+    patch grids for 3 RK4 steps with dt on the device, and 7 independent 3^3
+    patches (a partly filled last work-group) with forward Euler."""
+    announce(f"fd euler small p={p} grid={grid}")
+    b = I.config1(grid=grid, p=p, halo=3, seed=60 + p)
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=3)
+    g, dt, st = run_fd(b, n_steps=3)
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+    assert st["nonfinite_units"] == 0
+    if p == 3:
+        bi = I.independent_euler_patches(9, 7, 3, halo=3)
+        o1, _ = oracle.fd_step(bi, dt_fixed=1e-3, sigma=0.1, rk_stages=1, n_steps=2)
+        g1, _, _ = run_fd(bi, n_steps=2, dt_fixed=1e-3, rk=1)
+        assert np.all(rel_err(bi, g1, o1) <= 1e-12), rel_err(bi, g1, o1)
+
+
 @pytest.mark.parametrize("sigma", [0.0, 0.05])
 def test_forward_euler_fixed_dt(sigma):
     """rk_stages = 1 with a fixed dt (no reduction), with and without
