@@ -350,6 +350,66 @@ pb_status pb_autotune_cache_save(const char *path);
 pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded);
 pb_status pb_autotune_cache_clear(void);
 
+/* ---------------------------------------------------------- offload mode -- */
+
+/*
+ * Pure kernel offloading, as ExaHyPE ships a bundle of K cells to the
+ * accelerator (paper Sec. IV): no cell data stays on the device between
+ * calls.  The caller hands K separate host chunks (the AoAoS of Sec. II-B):
+ * chunk k is patch k with its halo, the (p+2h)^3 points of the halo box in
+ * per-point order (the N unknowns of one point contiguous, points x fastest,
+ * then y, then z), and receives K host chunks of the p^3 updated interior
+ * points in the same per-point order.  The gather prologue and scatter
+ * epilogue of Sec. III-C, Eq. (4) are the packing of the chunks into pinned
+ * staging buffers and back; the host-device mapping of Sec. III-D is a copy
+ * pipeline: batches of patches go through two slots (pinned staging, device
+ * buffers, a stream each), so the packing of one batch, the copies and the
+ * kernel of another overlap.  Edges and corners of the halo box are never
+ * read (the Rusanov stencil is axis-aligned); only the innermost halo layer
+ * is read.
+ */
+typedef struct pb_offload pb_offload;
+
+typedef struct {
+    int32_t dim;              /* 3 */
+    int32_t p;                /* cells per direction, 1..16 */
+    int32_t halo;             /* h >= 1: width of the halo in each chunk */
+    int32_t pde;              /* ADVECTION_F, ADVECTION_B or EULER */
+    const double *pde_params; /* host, copied at create */
+    int64_t n_pde_params;
+    int32_t n_unknowns;       /* N (as in pb_batch_desc) */
+    int32_t batch_patches;    /* patches per pipeline batch, 0 = the library's
+                                 choice (about 32 MiB of input per batch) */
+} pb_offload_desc;
+
+/* Allocates the two pipeline slots (pinned host staging, device buffers,
+ * streams).  Errors: PB_EINVAL for a bad description, PB_EUNSUPPORTED for
+ * another PDE or dim, PB_ENOMEM / PB_EHIP for failed allocations. */
+pb_status pb_offload_create(const pb_offload_desc *desc, pb_offload **out);
+pb_status pb_offload_destroy(pb_offload *o);
+
+typedef struct {
+    double total_ms;          /* wall clock of the whole call */
+    double pack_ms;           /* host: chunks -> pinned staging (summed over batches) */
+    double h2d_ms;            /* device copy engine time, host -> device (summed) */
+    double compute_ms;        /* kernel time (summed) */
+    double d2h_ms;            /* device -> host copies (summed) */
+    double unpack_ms;         /* host: pinned staging -> output chunks (summed) */
+    int64_t batches;
+} pb_offload_timing;
+
+/*
+ * One Rusanov finite-volume step (as fv_rusanov_step) of K patches in
+ * offload mode, with the step size dt given (the caller's time stepping):
+ * in_chunks[k] (host, (p+2h)^3 * N doubles) -> out_chunks[k] (host,
+ * p^3 * N doubles); dx[k] (host) is the cell width of patch k.  Blocking:
+ * returns when every output chunk is written.  timing is nullable.
+ * Errors (before any copy): PB_EINVAL for K < 0, NULL arrays or chunks,
+ * dt or dx not finite and > 0.  K = 0 returns at once.
+ */
+pb_status pb_offload_fv_step(pb_offload *o, int32_t K, const double *const *in_chunks, double *const *out_chunks,
+                             const double *dx, double dt, pb_offload_timing *timing);
+
 const char *pb_last_error(void);
 
 #ifdef __cplusplus

@@ -70,6 +70,21 @@ class AutotuneResult(C.Structure):
                 ("pad_", C.c_int32), ("cand", Tuning * PB_TUNE_MAX), ("cand_us", C.c_double * PB_TUNE_MAX)]
 
 
+class OffloadDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("p", C.c_int32), ("halo", C.c_int32), ("pde", C.c_int32),
+                ("pde_params", C.POINTER(C.c_double)), ("n_pde_params", C.c_int64), ("n_unknowns", C.c_int32),
+                ("batch_patches", C.c_int32)]
+
+
+class OffloadTiming(C.Structure):
+    _fields_ = [("total_ms", C.c_double), ("pack_ms", C.c_double), ("h2d_ms", C.c_double),
+                ("compute_ms", C.c_double), ("d2h_ms", C.c_double), ("unpack_ms", C.c_double),
+                ("batches", C.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -113,6 +128,12 @@ def lib():
         L.pb_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.pb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                                         C.c_int32, vp, vp]
+        L.pb_offload_create.argtypes = [C.POINTER(OffloadDesc), C.POINTER(vp)]
+        L.pb_offload_destroy.argtypes = [vp]
+        L.pb_offload_fv_step.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), dp, C.c_double,
+                                         C.POINTER(OffloadTiming)]
+        for name in ("pb_offload_create", "pb_offload_destroy", "pb_offload_fv_step"):
+            getattr(L, name).restype = C.c_int
         for name in ("pb_workspace_size", "patch_batch_create", "patch_batch_destroy", "pb_batch_reset",
                      "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_get_tuning", "pb_autotune",
                      "pb_autotune_cache_save", "pb_autotune_cache_load", "pb_autotune_cache_clear", "pb_batch_set_c2p_guess", "pb_batch_profile",
@@ -379,3 +400,46 @@ class PatchBatch:
     def set_c2p_guess(self, guess="plain", mlp=None):
         _check(lib().pb_batch_set_c2p_guess(self.handle, GUESS[guess], None if mlp is None else mlp.handle),
                "pb_batch_set_c2p_guess")
+
+
+class Offload:
+    """Offload mode (pb_offload_*): K patches handed over as K host arrays,
+    each the (p+2h)^3 halo box in per-point order [z][y][x][N], returned as K
+    host arrays [p][p][p][N] of updated interiors."""
+
+    def __init__(self, p, halo, pde, params, n_unknowns, batch_patches=0):
+        self._prm = np.ascontiguousarray(params, dtype=np.float64)
+        d = OffloadDesc(3, p, halo, PDE[pde], self._prm.ctypes.data_as(C.POINTER(C.c_double)), self._prm.size,
+                        n_unknowns, batch_patches)
+        h = C.c_void_p()
+        _check(lib().pb_offload_create(C.byref(d), C.byref(h)), "pb_offload_create")
+        self.handle = h
+        self.p, self.halo, self.N = p, halo, n_unknowns
+
+    def fv_step(self, chunks_in, chunks_out, dx, dt) -> dict:
+        """chunks_in / chunks_out: lists of C-contiguous float64 numpy arrays
+        ((p+2h)^3 * N and p^3 * N values); dx: K cell widths"""
+        K = len(chunks_in)
+        if len(chunks_out) != K:
+            raise ValueError("chunks_in and chunks_out differ in length")
+        for a in list(chunks_in) + list(chunks_out):
+            if a.dtype != np.float64 or not a.flags["C_CONTIGUOUS"]:
+                raise ValueError("chunks must be C-contiguous float64 arrays")
+        ins = (C.c_void_p * max(K, 1))(*[a.ctypes.data for a in chunks_in])
+        outs = (C.c_void_p * max(K, 1))(*[a.ctypes.data for a in chunks_out])
+        dxa = np.ascontiguousarray(dx, dtype=np.float64)
+        t = OffloadTiming()
+        _check(lib().pb_offload_fv_step(self.handle, K, ins, outs, dxa.ctypes.data_as(C.POINTER(C.c_double)),
+                                        dt, C.byref(t)), "pb_offload_fv_step")
+        return t.as_dict()
+
+    def close(self):
+        if self.handle is not None:
+            _check(lib().pb_offload_destroy(self.handle), "pb_offload_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -150,3 +150,29 @@ def test_autotune_cache_file_round_trip(tmp_path):
     pb.pb_autotune_cache_clear()
     pb.pb_autotune_cache_save(str(out))
     assert out.read_text() == ""
+
+
+def test_offload_create_rejects_bad_descriptions():
+    """pb_offload_create checks its description before allocating anything."""
+    L = pb.lib()
+    prm = np.array([1.4, 0.0, 0.0, 0.0])
+
+    def create(**kw):
+        f = dict(dim=3, p=8, halo=1, pde=pb.PDE["euler"], n_unknowns=5, batch_patches=0, n=1)
+        f.update(kw)
+        d = pb.OffloadDesc(f["dim"], f["p"], f["halo"], f["pde"], prm.ctypes.data_as(C.POINTER(C.c_double)),
+                           f["n"], f["n_unknowns"], f["batch_patches"])
+        h = C.c_void_p()
+        return L.pb_offload_create(C.byref(d), C.byref(h))
+
+    assert create(dim=2) == pb.PB_EUNSUPPORTED
+    assert create(p=0) == pb.PB_EINVAL
+    assert create(p=17) == pb.PB_EINVAL
+    assert create(halo=0) == pb.PB_EINVAL
+    assert create(pde=pb.PDE["linsym"]) == pb.PB_EUNSUPPORTED
+    assert create(pde=pb.PDE["srhd"]) == pb.PB_EUNSUPPORTED
+    assert create(n_unknowns=4) == pb.PB_EINVAL
+    assert create(n=0) == pb.PB_EINVAL
+    assert create(batch_patches=-1) == pb.PB_EINVAL
+    assert L.pb_offload_fv_step(None, 1, None, None, None, 1e-3, None) == pb.PB_EINVAL
+    assert L.pb_offload_destroy(None) == pb.PB_EINVAL
