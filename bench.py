@@ -16,8 +16,9 @@ and graph-replayed, the uneven 4096-patch batch of the 58-unknown linear
 system (FD4 + KO6 + RK4, FP64 matrix cores), the 3D Euler batch advanced by
 FD4 + KO6 + RK4 (halo 3, flux differencing), special-relativistic
 hydrodynamics on 2048 x 16^3 with the plain, warm and learned con2prim guess,
-and the K sweep (runtime per cell against the number of independent patches
-for p = 3, 6, 16, FV and FD4).
+the K sweep (runtime per cell against the number of independent patches
+for p = 3, 6, 16, FV and FD4), and offload mode (host chunks in and out
+through pinned staging and PCIe: total runtime against kernel time).
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -262,6 +263,37 @@ def bench_ksweep(torch, pb, I, k_max_16=8694):
     return out
 
 
+def bench_offload(pb, I):
+    """Offload mode (the paper's pure kernel offloading): K host chunks of 3D
+    Euler patches with a halo of 1 in, updated interiors out, one FV step per
+    call, dt fixed; total runtime (wall clock of the call, host packing and
+    PCIe copies included) against the kernel time, per cell.  Median of 5
+    calls after one warm-up call."""
+    import numpy as np
+    out = {}
+    for p, Ks in ((3, (1024, 16384)), (6, (256, 4096)), (16, (64, 512, 2048))):
+        rows = []
+        for K in Ks:
+            chunks = I.independent_halo_chunks(11, K, p, 1)
+            outs = [np.empty((p, p, p, 5)) for _ in range(K)]
+            dx = np.full(K, 1.0 / p)
+            o = pb.Offload(p, 1, "euler", [1.4], 5)
+            o.fv_step(chunks, outs, dx, 1e-3)
+            ts = [o.fv_step(chunks, outs, dx, 1e-3) for _ in range(5)]
+            o.close()
+            ts.sort(key=lambda t: t["total_ms"])
+            t = ts[2]
+            cells = K * p ** 3
+            rows.append({"K": K, "cells": cells, "total_ns_per_cell": t["total_ms"] * 1e6 / cells,
+                         "compute_ns_per_cell": t["compute_ms"] * 1e6 / cells,
+                         **{k: round(v, 4) for k, v in t.items()}})
+            del chunks, outs
+        out[f"p{p}"] = rows
+        log(f"offload p={p}: " + ", ".join(f"K={r['K']}: total {r['total_ns_per_cell']:.3f} ns, "
+                                          f"compute {r['compute_ns_per_cell']:.3f} ns" for r in rows))
+    return out
+
+
 def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     from paper_2608_19273_amd import mlp_train
     log("config-3 IC (SRHD, 2048 x 16^3)")
@@ -304,7 +336,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="fp32,config0,linsym,fdeuler,srhd,ksweep",
+    ap.add_argument("--workloads", default="fp32,config0,linsym,fdeuler,srhd,ksweep,offload",
                     help="comma list of the further workloads to run")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--mlp-pairs", type=int, default=1 << 22)
@@ -387,6 +419,9 @@ def main():
         if "ksweep" in want:
             log("K sweep: runtime per cell against the batch size, p in {3, 6, 16}, FV and FD4")
             wl["k_sweep"] = bench_ksweep(torch, pb, I)
+        if "offload" in want:
+            log("offload mode: total runtime against kernel time")
+            wl["offload"] = bench_offload(pb, I)
         result["workloads"] = wl
     if args.save_tuning:
         pb.pb_autotune_cache_save(args.save_tuning)

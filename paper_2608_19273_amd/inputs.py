@@ -279,6 +279,20 @@ def independent_euler_patches(seed: int, K: int, p: int, halo: int = 1, gamma: f
                  pde="euler", params=np.array([gamma]), n_unknowns=5, state=state)
 
 
+def independent_halo_chunks(seed: int, K: int, p: int, halo: int = 1, gamma: float = 1.4) -> list:
+    """K offload-mode input chunks of 3D Euler: each the (p+2h)^3 halo box in
+    per-point order [z][y][x][5], i.i.d. primitives at every point (halo
+    included: in offload mode the caller supplies the halo values):
+    rho, p ~ U[0.8, 1.2], velocity components ~ U[-0.3, 0.3]."""
+    pb = p + 2 * halo
+    n = K * pb ** 3
+    rho = uniform(substream(seed, 1), n, 0.8, 1.2)
+    vel = [uniform(substream(seed, 2 + d), n, -0.3, 0.3) for d in range(3)]
+    pr = uniform(substream(seed, 5), n, 0.8, 1.2)
+    cons = np.stack(euler_prim_to_state(rho, vel, pr, gamma), axis=-1)      # [n, 5]
+    return [np.ascontiguousarray(c) for c in cons.reshape(K, pb, pb, pb, 5)]
+
+
 # ------------------------------------------------------------------- SRHD --
 
 
