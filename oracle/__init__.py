@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-PDE_IDS = {"adv_f": 0, "adv_b": 1, "euler": 2, "linsym": 3, "srhd": 4}
+PDE_IDS = {"adv_f": 0, "adv_b": 1, "euler": 2, "linsym": 3, "srhd": 4, "adv_var": 5}
 
 
 def build(force: bool = True) -> str:
@@ -39,7 +39,7 @@ class _Desc(C.Structure):
     _fields_ = [("dim", C.c_int), ("K", C.c_int), ("N", C.c_int), ("h", C.c_int),
                 ("p", C.POINTER(C.c_int)), ("dx", C.POINTER(C.c_double)),
                 ("nbr", C.POINTER(C.c_int)), ("pde", C.c_int), ("prm", C.POINTER(C.c_double)),
-                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int)]
+                ("c2p_tol", C.c_double), ("c2p_maxit", C.c_int), ("M", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -98,8 +98,9 @@ class _Keep:
             self.prm = np.zeros(1)
         if batch.pde == "srhd" and batch.params.size >= 3:
             tol, maxit = float(batch.params[1]), int(batch.params[2])
+        M = batch.dim if batch.pde == "adv_var" else 0   # material parameters: the velocity field
         self.desc = _Desc(batch.dim, batch.K, batch.n_unknowns, batch.halo, _ip(self.p), _dp(self.dx),
-                          _ip(self.nbr), PDE_IDS[batch.pde], _dp(self.prm), tol, maxit)
+                          _ip(self.nbr), PDE_IDS[batch.pde], _dp(self.prm), tol, maxit, M)
 
 
 class OracleError(RuntimeError):

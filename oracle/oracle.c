@@ -35,7 +35,7 @@
 
 /* ---------------------------------------------------------------- types -- */
 
-enum { ORC_ADV_F = 0, ORC_ADV_B = 1, ORC_EULER = 2, ORC_LINSYM = 3, ORC_SRHD = 4 };
+enum { ORC_ADV_F = 0, ORC_ADV_B = 1, ORC_EULER = 2, ORC_LINSYM = 3, ORC_SRHD = 4, ORC_ADV_VAR = 5 };
 
 enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
 
@@ -55,6 +55,10 @@ typedef struct {
     /* SRHD con2prim settings used inside the FV step */
     double c2p_tol;
     int c2p_maxit;
+    /* material parameters (Sec. II: N evolving unknowns plus M parameters
+     * per point that are fixed in time): the last M of the N values per cell
+     * are read by the physics and copied through every update unchanged */
+    int M;
 } orc_desc;
 
 typedef struct {
@@ -213,6 +217,9 @@ static void fill_halo(const orc_desc *b, hblocks *hb, int W)
  *   ORC_LINSYM            : rho_x, rho_y, rho_z, B_x[N][N], B_y[N][N],
  *                           B_z[N][N] (row-major)     (rho_d = spectral radius)
  *   ORC_SRHD              : Gamma                     (N = 5, dim = 3)
+ *   ORC_ADV_VAR           : kappa                     (N = 1 + dim, M = dim:
+ *                           q and the velocity field a(x) as material
+ *                           parameters; F_d = a_d(x) q, S = -kappa q)
  */
 
 /*
@@ -371,6 +378,10 @@ static void phys_flux(const orc_desc *b, int d, const double *Q, const double *a
     case ORC_ADV_F:
         for (int v = 0; v < N; v++) F[v] = b->prm[d] * Q[v];
         break;
+    case ORC_ADV_VAR:
+        F[0] = Q[1 + d] * Q[0];
+        for (int v = 1; v < N; v++) F[v] = 0.0;
+        break;
     case ORC_EULER: {
         /* Q = (rho, m, E); F_d = (m_d, m_d m / rho + p e_d, (E + p) m_d / rho) */
         double gam = b->prm[0];
@@ -400,7 +411,7 @@ static void phys_flux(const orc_desc *b, int d, const double *Q, const double *a
 
 static int has_flux(const orc_desc *b)
 {
-    return b->pde == ORC_ADV_F || b->pde == ORC_EULER || b->pde == ORC_SRHD;
+    return b->pde == ORC_ADV_F || b->pde == ORC_EULER || b->pde == ORC_SRHD || b->pde == ORC_ADV_VAR;
 }
 
 static int has_ncp(const orc_desc *b) { return b->pde == ORC_ADV_B || b->pde == ORC_LINSYM; }
@@ -435,6 +446,8 @@ static double phys_eig(const orc_desc *b, int d, const double *Q, const double *
     case ORC_ADV_F:
     case ORC_ADV_B:
         return fabs(b->prm[d]);
+    case ORC_ADV_VAR:
+        return fabs(Q[1 + d]);
     case ORC_EULER: {
         double gam = b->prm[0];
         double rho = Q[0];
@@ -474,6 +487,7 @@ static void phys_source(const orc_desc *b, const double *Q, double *S)
         double kappa = b->prm[3];
         for (int v = 0; v < b->N; v++) S[v] = -kappa * Q[v];
     }
+    if (b->pde == ORC_ADV_VAR) S[0] = -b->prm[0] * Q[0];
 }
 
 /* ------------------------------------------------------- time step size -- */
@@ -521,6 +535,7 @@ static int check_desc(const orc_desc *b, int stencil_radius)
     if (b->h < stencil_radius) return ORC_EINVAL;
     if (b->pde == ORC_EULER && b->N != b->dim + 2) return ORC_EINVAL;
     if (b->pde == ORC_SRHD && (b->N != 5 || b->dim != 3)) return ORC_EINVAL;
+    if (b->pde == ORC_ADV_VAR ? (b->N != 1 + b->dim || b->M != b->dim) : b->M != 0) return ORC_EINVAL;
     for (int k = 0; k < b->K; k++) {
         if (b->p[k] < b->h || !(b->dx[k] > 0.0)) return ORC_EINVAL;
         for (int f = 0; f < 2 * b->dim; f++) {
@@ -653,7 +668,7 @@ int orc_fv_step(const orc_desc *b, double *Q, double cfl, double dt_fixed, int n
                 for (int v = 0; v < N; v++) {
                     double q = Qi[v] - r * acc[v] + dt * S[v];
                     if (round_fp32) q = (double)(float)q;
-                    Qo[v] = q;
+                    Qo[v] = v < N - b->M ? q : Qi[v];   /* material parameters: copied */
                 }
             } while (next_index(b->dim, i, lo, hi));
         }
@@ -736,6 +751,7 @@ static void fd_rhs(const orc_desc *b, hblocks *hb, hblocks *rhs, double sigma)
             }
             phys_source(b, Qi, S);
             for (int v = 0; v < N; v++) r[v] += S[v];
+            for (int v = N - b->M; v < N; v++) r[v] = 0.0;   /* material parameters do not evolve */
         } while (next_index(b->dim, i, lo, hi));
     }
 }

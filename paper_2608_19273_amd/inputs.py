@@ -264,6 +264,40 @@ def config1(seed: int = 1, grid=C1_GRID, p: int = 16, gamma: float = 1.4, halo: 
     return b
 
 
+def adv_var_batch(grid, p: int, kappa: float = 0.0, field: str = "random", seed: int = 31, halo: int = 1,
+                  q0=None) -> Batch:
+    """Linear advection with a velocity field carried as material parameters:
+    per cell (q, a_x, a_y(, a_z)) on a periodic patch grid over [0,1)^dim.
+    field "random": every a_d varies in every direction (compressive);
+    "shear": a_d does not depend on x_d (discretely divergence-free);
+    "const": a = (0.6, -0.3, 0.2).  q defaults to 1 + sin(2 pi x) cos(2 pi y)/2."""
+    dim = len(grid)
+    cells = tuple(g * p for g in grid)
+    dx = 1.0 / cells[0]
+    b = make_uniform_batch(grid, p, halo, "adv_var", [kappa], 1 + dim, dx)
+    c = _centres(cells, dx)
+    if dim == 3:
+        Z, Y, X = np.meshgrid(c[2], c[1], c[0], indexing="ij")
+    else:
+        Y, X = np.meshgrid(c[1], c[0], indexing="ij")
+        Z = np.zeros_like(X)
+    ph = 2 * np.pi * uniform(seed, 6)
+    tp = 2 * np.pi
+    if field == "random":
+        a = [0.5 + 0.3 * np.sin(tp * Y + ph[0]) + 0.2 * np.sin(tp * X + ph[1]) + 0.1 * np.cos(tp * Z + ph[2]),
+             -0.3 + 0.3 * np.cos(tp * X + ph[3]) + 0.2 * np.sin(tp * Y + ph[4]),
+             0.2 + 0.25 * np.sin(tp * (X + Z) + ph[5])]
+    elif field == "shear":
+        a = [0.5 + 0.3 * np.sin(tp * Y + ph[0]) + 0.1 * np.cos(tp * Z + ph[2]),
+             -0.3 + 0.3 * np.cos(tp * X + ph[3]) + 0.1 * np.sin(tp * Z + ph[1]),
+             0.2 + 0.25 * np.sin(tp * (X + Y) + ph[5])]
+    else:
+        a = [np.full_like(X, 0.6), np.full_like(X, -0.3), np.full_like(X, 0.2)]
+    q = 1.0 + 0.5 * np.sin(tp * X) * np.cos(tp * Y) if q0 is None else q0(X, Y, Z)
+    b.state = b.from_global(np.stack([q] + a[:dim]), grid)
+    return b
+
+
 def independent_euler_patches(seed: int, K: int, p: int, halo: int = 1, gamma: float = 1.4) -> Batch:
     """K independent 3D Euler patches of p^3 cells (each periodic on itself,
     dx = 1/p), i.i.d. primitives per cell: rho, p ~ U[0.8, 1.2], each
