@@ -68,6 +68,14 @@ typedef enum {
     PB_PDE_SRHD = 4,        /* special-relativistic hydrodynamics, dim = 3,
                                N = 5, Q = (D, S_x, S_y, S_z, tau).
                                params: Gamma, con2prim tol, con2prim max_iter */
+    PB_PDE_ADVECTION_VAR = 5, /* linear advection by a velocity field held as
+                               material parameters (paper Sec. II: N evolving
+                               plus M fixed values per point): n_unknowns =
+                               1 + dim, Q = (q, a_x, a_y(, a_z)); F_d = a_d(x) q,
+                               S = -kappa q.  The dim field values of every
+                               cell are read by the fluxes and speeds and
+                               carried through every step unchanged (bitwise).
+                               FV only.  params: kappa */
 } pb_pde;
 
 typedef enum { PB_STORE_FP64 = 0, PB_STORE_FP32 = 1 } pb_storage;
@@ -146,7 +154,8 @@ pb_status pb_batch_stats(pb_batch *b, pb_stats *out);
  * packs several whole patches into a work-group (one thread per cell); the
  * others march z-slabs of a patch plane by plane.  Both give the same
  * results to roundoff.
- * Supported: ADVECTION_F/B (N = 1), EULER, SRHD; 1 <= p <= 16; halo >= 1.
+ * Supported: ADVECTION_F/B (N = 1), ADVECTION_VAR (N = 1 + dim), EULER, SRHD;
+ * 1 <= p <= 16; halo >= 1.
  */
 pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_steps,
                           int32_t use_graph, double *dt_last_host);

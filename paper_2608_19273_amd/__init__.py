@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libpatchhip.so")
 
 PB_OK, PB_EINVAL, PB_ENOMEM, PB_EHIP, PB_EUNSUPPORTED = 0, -1, -2, -3, -4
 STATUS = {0: "PB_OK", -1: "PB_EINVAL", -2: "PB_ENOMEM", -3: "PB_EHIP", -4: "PB_EUNSUPPORTED"}
-PDE = {"adv_f": 0, "adv_b": 1, "euler": 2, "linsym": 3, "srhd": 4}
+PDE = {"adv_f": 0, "adv_b": 1, "euler": 2, "linsym": 3, "srhd": 4, "adv_var": 5}
 STORAGE = {"fp64": 0, "fp32": 1}
 GUESS = {"plain": 0, "learned": 1, "warm": 2}
 MLP_IN, MLP_HID = 5, 64

@@ -57,6 +57,7 @@ static int n_params_needed(int pde, int N)
     case PB_PDE_EULER: return 1;
     case PB_PDE_LINSYM: return 3 + 3 * N * N;
     case PB_PDE_SRHD: return 3;
+    case PB_PDE_ADVECTION_VAR: return 1;
     }
     return -1;
 }
@@ -70,7 +71,7 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
     if (d->n_patches < 1) { set_error("n_patches must be >= 1"); return PB_EINVAL; }
     if (!d->p || !d->dx || !d->neighbor) { set_error("p, dx and neighbor tables are required"); return PB_EINVAL; }
     if (d->halo < 1) { set_error("halo must be >= 1"); return PB_EINVAL; }
-    if (d->pde < PB_PDE_ADVECTION_F || d->pde > PB_PDE_SRHD) { set_error("unknown pde"); return PB_EINVAL; }
+    if (d->pde < PB_PDE_ADVECTION_F || d->pde > PB_PDE_ADVECTION_VAR) { set_error("unknown pde"); return PB_EINVAL; }
     if (d->storage != PB_STORE_FP64 && d->storage != PB_STORE_FP32) { set_error("unknown storage"); return PB_EINVAL; }
     const int N = d->n_unknowns;
     switch (d->pde) {
@@ -86,6 +87,9 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
         break;
     case PB_PDE_SRHD:
         if (N != 5 || d->dim != 3) { set_error("SRHD needs dim = 3 and n_unknowns = 5"); return PB_EINVAL; }
+        break;
+    case PB_PDE_ADVECTION_VAR:
+        if (N != 1 + d->dim) { set_error("variable advection needs n_unknowns = 1 + dim"); return PB_EINVAL; }
         break;
     }
     const int np = n_params_needed(d->pde, N);

@@ -291,7 +291,7 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
             T *dst = qout + P.off * N + z * pp + cxy;
 #pragma unroll
             for (int v = 0; v < N; ++v) {
-                const double nv = qc[v] - hr_ * acc2[v] + dt * S[v];
+                const double nv = v < N - Ph::M ? qc[v] - hr_ * acc2[v] + dt * S[v] : qc[v];   // material: carried
                 const T st = (T)nv;
                 __builtin_nontemporal_store(st, dst + (long long)v * C);
                 qw[v] = (double)st;
@@ -564,7 +564,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fv_step_dma_kernel(
                 T *dst = qout + P.off * N + (long long)z * pp + li;
 #pragma unroll
                 for (int v = 0; v < N; ++v) {
-                    const double nv = qc[v] - hr_ * acc2[v] + dt * S[v];
+                    const double nv = v < N - Ph::M ? qc[v] - hr_ * acc2[v] + dt * S[v] : qc[v];   // material: carried
                     const T st = (T)nv;
                     __builtin_nontemporal_store(st, dst + (long long)v * C);
                     qw[v] = (double)st;
@@ -688,7 +688,7 @@ __global__ __launch_bounds__(kFvThreads) void fv_small_kernel(
         double qw[N];
 #pragma unroll
         for (int v = 0; v < N; ++v) {
-            const T st = (T)(qc[v] - hr_ * acc2[v] + dt * S[v]);
+            const T st = (T)(v < N - Ph::M ? qc[v] - hr_ * acc2[v] + dt * S[v] : qc[v]);
             __builtin_nontemporal_store(st, dst + (long long)v * P3);
             qw[v] = (double)st;
             bad |= !isfinite(qw[v]);
@@ -913,6 +913,14 @@ pb_status dispatch(pb_batch *b, F &&f)
         if (b->dim == 2) return f32 ? f(ph, std::integral_constant<int, 2>(), float()) : f(ph, std::integral_constant<int, 2>(), double());
         return f32 ? f(ph, std::integral_constant<int, 3>(), float()) : f(ph, std::integral_constant<int, 3>(), double());
     }
+    case PB_PDE_ADVECTION_VAR:
+        if (b->dim == 2) {
+            AdvVar<2> ph{pr[0]};
+            return f32 ? f(ph, std::integral_constant<int, 2>(), float()) : f(ph, std::integral_constant<int, 2>(), double());
+        } else {
+            AdvVar<3> ph{pr[0]};
+            return f32 ? f(ph, std::integral_constant<int, 3>(), float()) : f(ph, std::integral_constant<int, 3>(), double());
+        }
     case PB_PDE_EULER:
         if (b->dim == 2) {
             Euler<2> ph{pr[0]};

@@ -11,6 +11,9 @@
 //
 // Functor interface:
 //   N, A, E            unknowns, aux values, extra per-cell inputs (SRHD: p)
+//   M                  material parameters: the last M of the N values per
+//                      point, read by the physics and carried through every
+//                      update unchanged (fixed in time)
 //   kFlux, kNcp, kSrc  which terms exist
 //   aux(q, e, a)       a[0..A) from Q and the extra inputs
 //   eig<D>(q, a)       largest |characteristic speed| along D
@@ -57,7 +60,7 @@ __device__ __forceinline__ double root(double a)
 
 // Linear advection, conservative form: F_d = a_d q, S = -kappa q.
 struct AdvF {
-    static constexpr int N = 1, A = 0, E = 0, DIMS = 3;
+    static constexpr int N = 1, A = 0, E = 0, M = 0, DIMS = 3;
     static constexpr bool kFlux = true, kNcp = false, kSrc = true;
     double a[3];
     double kappa;
@@ -80,7 +83,7 @@ struct AdvF {
 
 // Linear advection, non-conservative form: B_d = a_d, F = 0.
 struct AdvB {
-    static constexpr int N = 1, A = 0, E = 0, DIMS = 3;
+    static constexpr int N = 1, A = 0, E = 0, M = 0, DIMS = 3;
     static constexpr bool kFlux = false, kNcp = true, kSrc = true;
     double a[3];
     double kappa;
@@ -104,12 +107,43 @@ struct AdvB {
     }
 };
 
+// Linear advection by a velocity field carried as material parameters (the
+// N + M values per point of paper Sec. II, here N = 1 evolving, M = DIM):
+// Q = (q, a_1..a_DIM), F_d = a_d(x) q, speed |a_d(x)|, S = -kappa q.  The
+// Rusanov face uses the speeds and fluxes of the two adjacent cells, so a
+// field that varies in space gives the usual variable-coefficient flux.
+template <int DIM>
+struct AdvVar {
+    static constexpr int N = 1 + DIM, A = 0, E = 0, M = DIM, DIMS = DIM;
+    static constexpr bool kFlux = true, kNcp = false, kSrc = true;
+    double kappa;
+    __device__ __forceinline__ void aux(const double *, const double *, double *) const {}
+    __device__ __forceinline__ void aux_fast(const double *, const double *, double *) const {}
+    template <int D> __device__ __forceinline__ double eig(const double *q, const double *) const
+    {
+        return fabs(q[1 + D]);
+    }
+    template <int D> __device__ __forceinline__ void flux(const double *q, const double *, double *F) const
+    {
+        F[0] = q[1 + D] * q[0];
+#pragma unroll
+        for (int v = 1; v < N; ++v) F[v] = 0.0;
+    }
+    template <int D> __device__ __forceinline__ void ncp(const double *, const double *, double *) const {}
+    __device__ __forceinline__ void source(const double *q, const double *, double *S) const
+    {
+        S[0] = -kappa * q[0];
+#pragma unroll
+        for (int v = 1; v < N; ++v) S[v] = 0.0;
+    }
+};
+
 // Compressible Euler, ideal gas: Q = (rho, m, E), p = (gamma-1)(E - |m|^2/(2 rho)),
 // F_d = (m_d, m_d m/rho + p e_d, (E + p) m_d/rho), speed |m_d/rho| + sqrt(gamma p/rho).
 // aux = (1/rho, p, c).
 template <int DIM>
 struct Euler {
-    static constexpr int N = DIM + 2, A = 3, E = 0, DIMS = DIM;
+    static constexpr int N = DIM + 2, A = 3, E = 0, M = 0, DIMS = DIM;
     static constexpr bool kFlux = true, kNcp = false, kSrc = false;
     double gamma;
     __device__ __forceinline__ void aux(const double *q, const double *, double *a) const
@@ -165,7 +199,7 @@ struct Euler {
 //   F_d = (D v_d, S v_d + p e_d, S_d - D v_d).
 // aux = (p, v_x, v_y, v_z, lambda_x, lambda_y, lambda_z).
 struct Srhd {
-    static constexpr int N = 5, A = 7, E = 1, DIMS = 3;
+    static constexpr int N = 5, A = 7, E = 1, M = 0, DIMS = 3;
     static constexpr bool kFlux = true, kNcp = false, kSrc = false;
     double gam;
     __device__ __forceinline__ void aux(const double *q, const double *e, double *a) const

@@ -100,6 +100,30 @@ def test_small_patch_advection_exact_shift():
         np.testing.assert_allclose(b.to_global(g, (2, 2, 2)), np.roll(ref, 1, axis=3 - axis), rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("dim,p,field,storage,dma", [(3, 8, "random", "fp64", 0), (3, 16, "shear", "fp64", 0),
+                                                      (3, 16, "random", "fp64", 1), (3, 4, "random", "fp32", 0),
+                                                      (3, 5, "random", "fp64", 0), (2, 8, "random", "fp64", 0)])
+def test_material_parameters_advection(dim, p, field, storage, dma):
+    """Advection by a velocity field held as material parameters (N = 1
+    evolving, M = dim carried) through the plane kernel (8^3, 16^3; also the
+    DMA-fed one), the small-patch kernel (4^3, 5^3) and the 2D kernel: the
+    field comes back bitwise, q matches the oracle, dt comes from the field."""
+    announce(f"adv_var dim={dim} p={p} {field} {storage} dma={dma}")
+    grid = (2, 2, 2) if dim == 3 else (3, 2)
+    b = I.adv_var_batch(grid, p, kappa=0.1, field=field, seed=80 + p)
+    f32 = storage == "fp32"
+    if f32:
+        b.state = b.state.astype(np.float32).astype(np.float64)
+    o, dts, _ = oracle.fv_step(b, cfl=0.5, n_steps=4, round_fp32=f32)
+    g, dt, st = run_gpu(b, storage=storage, n_steps=4, cfl=0.5, tuning={"fv_dma": dma} if dma else None)
+    tol = 1e-5 if f32 else 1e-12
+    assert rel_err(b, g, o)[0] <= tol, rel_err(b, g, o)
+    for k in range(b.K):
+        np.testing.assert_array_equal(b.patch_view(g, k)[1:], b.patch_view(b.state, k)[1:])
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
+    assert st["nonfinite_units"] == 0
+
+
 @pytest.mark.parametrize("form", ["adv_f", "adv_b"])
 @pytest.mark.parametrize("dim", [2, 3])
 def test_exact_shift_gpu(form, dim):
