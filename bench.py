@@ -16,6 +16,7 @@ and graph-replayed, the uneven 4096-patch batch of the 58-unknown linear
 system (FD4 + KO6 + RK4, FP64 matrix cores), the 3D Euler batch advanced by
 FD4 + KO6 + RK4 (halo 3, flux differencing), special-relativistic
 hydrodynamics on 2048 x 16^3 with the plain, warm and learned con2prim guess,
+advection by a velocity field held as material parameters,
 the K sweep (runtime per cell against the number of independent patches
 for p = 3, 6, 16, FV and FD4), and offload mode (host chunks in and out
 through pinned staging and PCIe: total runtime against kernel time).
@@ -294,6 +295,30 @@ def bench_offload(pb, I):
     return out
 
 
+def bench_adv_var(torch, pb, I, steps, warmup):
+    """Advection by a velocity field held as material parameters on 2048
+    patches of 16^3 (the headline grid), FP64: the three field values per
+    cell are read and carried through, so a cell-update moves 4 values in
+    and 4 out (64 B)."""
+    log("variable-coefficient advection IC (2048 x 16^3, field as material parameters)")
+    b = I.adv_var_batch((16, 16, 8), 16, kappa=0.0, field="random")
+    cells = b.total_cells
+    B = pb.PatchBatch(b)
+    B.fv_rusanov_step(cfl=0.5, n_steps=warmup)
+    B.profile(True)
+    el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.5, n_steps=steps))
+    kern_ms, launches = B.profile_read()
+    B.profile(False)
+    st = B.stats()
+    B.close()
+    avg_s = kern_ms / 1e3 / max(launches, 1)
+    return {"workload": "3D linear advection, velocity field as M = 3 material parameters per cell, Rusanov FV, "
+                        f"CFL 0.5, 2048 patches of 16^3 ({cells} cells), FP64",
+            "cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
+            "kernel_avg_us": avg_s * 1e6, "bytes_per_cell": 64, "kernel_GBs": cells * 64 / avg_s / 1e9,
+            "hbm_frac": cells * 64 / avg_s / 1e9 / HBM_PEAK_GBS, "nonfinite_units": st["nonfinite_units"]}
+
+
 def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     from paper_2608_19273_amd import mlp_train
     log("config-3 IC (SRHD, 2048 x 16^3)")
@@ -336,7 +361,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
-    ap.add_argument("--workloads", default="fp32,config0,linsym,fdeuler,srhd,ksweep,offload",
+    ap.add_argument("--workloads", default="fp32,config0,advvar,linsym,fdeuler,srhd,ksweep,offload",
                     help="comma list of the further workloads to run")
     ap.add_argument("--mlp-epochs", type=int, default=20)
     ap.add_argument("--mlp-pairs", type=int, default=1 << 22)
@@ -407,6 +432,9 @@ def main():
         if "config0" in want:
             log("2D Euler entropy wave")
             wl["euler2d_64x64_config0"] = bench_config0(torch, pb, I, 10)
+        if "advvar" in want:
+            log("advection by a material-parameter velocity field")
+            wl["advection_material_field"] = bench_adv_var(torch, pb, I, args.steps, args.warmup)
         if "linsym" in want:
             log("FD4 + KO6 + RK4, 58 unknowns")
             wl["linsym58_fd4_rk4"] = bench_fd(torch, pb, I, max(2, args.steps // 4), 1)
