@@ -232,7 +232,9 @@ def bench_ksweep(torch, pb, I, k_max_16=8694):
     p in {3, 6, 16}, the FV step (CFL 0.4) and the FD4 + KO6 + RK4 step (CFL
     0.5, sigma 0.1), eager launches and the same steps replayed from a HIP
     graph, each timed by wall clock and events; per cell means per
-    cell-update (FV) and per cell-step of all four RK stages (FD)."""
+    cell-update (FV) and per cell-step of all four RK stages (FD).  Also the
+    58-unknown linear system (FD4 + KO6 + RK4 on the FP64 matrix cores) on K
+    independent patches of p in {4, 8, 16}."""
     out = {}
     for scheme in ("fv", "fd"):
         for p in (3, 6, 16):
@@ -261,6 +263,30 @@ def bench_ksweep(torch, pb, I, k_max_16=8694):
             out[f"{scheme}_p{p}"] = rows
             log(f"k-sweep {scheme} p={p}: " + ", ".join(f"K={r['K']}: {r['ns_per_cell']:.3f}/{r['ns_per_cell_graph']:.3f} ns"
                                                       for r in rows))
+    # the 58-unknown linear system (the FD4 path on the FP64 matrix cores) on
+    # K independent patches of one size, i.i.d. U(-1, 1) state
+    import numpy as np
+    Bs, rhos = I.linsym_matrices(2, 58)
+    prm = I.linsym_params(Bs, rhos)
+    for p in (4, 8, 16):
+        rows = []
+        for K in (1, 16, 256, 1024, 4096):
+            if p == 16 and K > 1024:
+                continue
+            cells = K * p ** 3
+            b = I.Batch(dim=3, p=np.full(K, p, np.int32), dx=np.full(K, 1.0 / p), nbr=I.self_periodic(K, 3),
+                        halo=3, pde="linsym", params=prm, n_unknowns=58,
+                        state=I.uniform(13, cells * 58, -1.0, 1.0))
+            B = pb.PatchBatch(b)
+            n = int(min(50, max(2, round(2e6 / cells))))
+            B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=1)
+            el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n))
+            B.close()
+            rows.append({"K": K, "cells": cells, "steps": n, "ns_per_cell": el / (n * cells) * 1e9,
+                         "us_per_step": el / n * 1e6})
+            del b
+        out[f"fd_linsym58_p{p}"] = rows
+        log(f"k-sweep linsym58 p={p}: " + ", ".join(f"K={r['K']}: {r['ns_per_cell']:.2f} ns" for r in rows))
     return out
 
 

@@ -414,7 +414,9 @@ typedef struct {
  * p^3 * N doubles); dx[k] (host) is the cell width of patch k.  Blocking:
  * returns when every output chunk is written.  timing is nullable.
  * Errors (before any copy): PB_EINVAL for K < 0, NULL arrays or chunks,
- * dt or dx not finite and > 0.  K = 0 returns at once.
+ * dt or dx not finite and > 0.  K = 0 returns at once.  Calls on one
+ * pb_offload object must not overlap (its staging buffers and streams are
+ * reused); separate objects are independent.
  */
 pb_status pb_offload_fv_step(pb_offload *o, int32_t K, const double *const *in_chunks, double *const *out_chunks,
                              const double *dx, double dt, pb_offload_timing *timing);

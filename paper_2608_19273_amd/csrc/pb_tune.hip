@@ -118,7 +118,10 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
     if (kind != 0 && kind != 1) { set_error("pb_autotune: kind must be 0 (FV) or 1 (FD)"); return PB_EINVAL; }
     if (trials < 1 || trials > 1000) { set_error("pb_autotune: trials must be in [1, 1000]"); return PB_EINVAL; }
     if (kind == 0 && b->pde == PB_PDE_LINSYM) { set_error("pb_autotune: the linear system has no FV step"); return PB_EINVAL; }
-    if (kind == 1 && b->pde != PB_PDE_LINSYM) { set_error("pb_autotune: the FD step runs the linear system only"); return PB_EINVAL; }
+    if (kind == 1 && b->pde != PB_PDE_LINSYM) {
+        set_error("pb_autotune: FD tuning applies to the linear system (the Euler FD kernels have no launch-shape choice)");
+        return PB_EINVAL;
+    }
     if (kind == 0 && b->pde == PB_PDE_SRHD && b->storage != PB_STORE_FP64) { set_error("SRHD runs in FP64 storage"); return PB_EUNSUPPORTED; }
     if (kind == 0 && b->pmax > kFvPmax) { set_error("fv_rusanov_step: p > 16 is not supported"); return PB_EUNSUPPORTED; }
     if (!std::isfinite(dt_fixed) || (!(dt_fixed > 0.0) && !(cfl > 0.0 && std::isfinite(cfl)))) {
