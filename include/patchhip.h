@@ -382,7 +382,7 @@ typedef struct pb_offload pb_offload;
 typedef struct {
     int32_t dim;              /* 3 */
     int32_t p;                /* cells per direction, 1..16 */
-    int32_t halo;             /* h >= 1: width of the halo in each chunk */
+    int32_t halo;             /* 1 <= h <= 8: width of the halo in each chunk */
     int32_t pde;              /* ADVECTION_F, ADVECTION_B or EULER */
     const double *pde_params; /* host, copied at create */
     int64_t n_pde_params;
