@@ -738,6 +738,45 @@ def test_srhd_contact_keeps_v_and_p():
         np.testing.assert_allclose(prim[1 + i], v[i], rtol=0, atol=1e-12)
 
 
+def _srhd_sound_error(n, T=0.25, amp=1e-4, Gam=5.0 / 3.0):
+    """A small relativistic sound wave at rest: linearising the SRHD system
+    about (rho0, v = 0, p0) gives dp_t + Gamma p0 dv_x = 0 and
+    rho0 h0 dv_t + dp_x = 0, so the wave moves at c_s = sqrt(Gamma p0 / (rho0 h0))
+    with dv = dp / (rho0 h0 c_s) and drho = rho0 dv / c_s.  Returns the mean
+    pressure error against the translated wave, relative to the amplitude."""
+    rho0, p0 = 1.0, 1.0
+    h0 = 1.0 + Gam / (Gam - 1.0) * p0 / rho0
+    cs = math.sqrt(Gam * p0 / (rho0 * h0))
+    grid = (n // 4, 1, 1)
+    b = I.config3(grid=grid, p=4, Gam=Gam)
+    x = (np.arange(n) + 0.5) / n
+    dp = amp * np.sin(2 * np.pi * x)
+    dv = dp / (rho0 * h0 * cs)
+    rho = rho0 + rho0 * dv / cs
+    pr = p0 + dp
+    shape = (4, 4, n)
+    bc = [np.broadcast_to(a, shape).copy() for a in (rho, dv, np.zeros(n), np.zeros(n), pr / ((Gam - 1) * rho))]
+    cons, _ = I.srhd_prim_to_cons(*bc, Gam)
+    b.state = b.from_global(cons, grid)
+    nsteps = int(round(T / (0.4 / n)))
+    q, _, st = oracle.fv_step(b, dt_fixed=T / nsteps, n_steps=nsteps)
+    assert st.c2p_fail == 0
+    prim = oracle.con2prim(b.to_global(q, grid).reshape(5, -1))[0]
+    pnum = prim[4].reshape(shape).mean(axis=(0, 1))
+    exact = p0 + amp * np.sin(2 * np.pi * (x - cs * T))
+    return np.mean(np.abs(pnum - exact)) / amp
+
+
+def test_srhd_sound_wave_speed_and_order():
+    """The SRHD Rusanov step carries a small sound wave at the relativistic
+    sound speed, converging at first order: a wrong pressure term in the
+    momentum or energy flux, or a wrong conserved-to-primitive map inside
+    the step, changes the wave speed and the error stops falling."""
+    e = [_srhd_sound_error(n) for n in (64, 128, 256)]
+    assert e[2] < 0.05, e
+    assert 1.6 < e[0] / e[1] < 2.4 and 1.7 < e[1] / e[2] < 2.3, e
+
+
 @pytest.mark.parametrize("axis", [1, 2])
 def test_fd_plane_wave_other_axes(axis):
     """The closed-form plane wave of the FD step along y and along z."""
