@@ -108,3 +108,28 @@ def test_srhd_free_stream_and_warm_guess():
     assert W.stats()["c2p_iterations"] < P.stats()["c2p_iterations"]
     P.close()
     W.close()
+
+
+@pytest.mark.slow
+def test_config3_full_size_parity_every_guess():
+    """The full 2048 x 16^3 SRHD batch (i.i.d. primitives over the workload's
+    ranges) in the benchmark's launch configuration: two CFL steps with the
+    plain, warm and learned guess against the full oracle."""
+    announce("srhd config3 full size")
+    need_gpu()
+    from paper_2608_19273_amd import mlp_train
+    net, _ = mlp_train.train(n_pairs=1 << 16, epochs=2, batch=1024, lr=3e-3, seed=9)
+    b = I.config3()
+    o, dts, ost = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    for guess in ("plain", "warm", "learned"):
+        B = pb.PatchBatch(b)
+        if guess != "plain":
+            B.set_c2p_guess(guess, net if guess == "learned" else None)
+        dt = B.fv_rusanov_step(cfl=0.4, n_steps=2, want_dt=True)
+        g = B.download()
+        st = B.stats()
+        B.close()
+        assert np.all(rel_err(b, g, o) <= 1e-12), (guess, rel_err(b, g, o))
+        assert abs(dt - dts[-1]) <= 1e-13 * dts[-1]
+        assert st["c2p_failures"] == ost.c2p_fail and st["c2p_cells"] == 2 * b.total_cells
+    net.close()
