@@ -22,6 +22,15 @@ pb_status hip_fail(hipError_t e, const char *what)
     return PB_EHIP;
 }
 
+pb_status api_fail(const char *what, pb_status st) noexcept
+{
+    try {
+        set_error(what);
+    } catch (...) {
+    }
+    return st;
+}
+
 static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 WsLayout ws_layout(int pde, int dim, int h, long long total_cells, int N, int storage, int K)
@@ -237,16 +246,19 @@ const char *pb_last_error(void) { return g_err.c_str(); }
 
 pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes)
 {
+    PB_API_BEGIN
     if (!bytes) { set_error("bytes is NULL"); return PB_EINVAL; }
     long long cells = 0;
     pb_status st = validate(desc, false, &cells, nullptr, nullptr);
     if (st != PB_OK) return st;
     *bytes = ws_layout(desc->pde, desc->dim, desc->halo, cells, desc->n_unknowns, desc->storage, desc->n_patches).total;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status patch_batch_create(const pb_batch_desc *d, pb_batch **out)
 {
+    PB_API_BEGIN
     if (!out) { set_error("out is NULL"); return PB_EINVAL; }
     *out = nullptr;
     long long cells = 0;
@@ -302,10 +314,12 @@ pb_status patch_batch_create(const pb_batch_desc *d, pb_batch **out)
     if (st != PB_OK) { patch_batch_destroy(b); return st; }
     *out = b;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status patch_batch_destroy(pb_batch *b)
 {
+    PB_API_BEGIN
     if (!b) return PB_OK;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     for (int w = 0; w < 2; ++w)
@@ -316,20 +330,24 @@ pb_status patch_batch_destroy(pb_batch *b)
     if (b->d_fd_B) (void)hipFree(b->d_fd_B);
     delete b;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_batch_reset(pb_batch *b, int32_t which)
 {
+    PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
     if (which != 0 && which != 1) { set_error("which must be 0 or 1"); return PB_EINVAL; }
     b->cur = which;
     b->steps = 0;
     b->pres_valid = false;
     return launch_ctrl_init(b, b->stream);
+    PB_API_END
 }
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
 {
+    PB_API_BEGIN
     if (!b || !t) { set_error("NULL argument"); return PB_EINVAL; }
     if (t->fv_slab < 0 || t->fv_slab > kFvPmax) { set_error("fv_slab must be in [0, 16]"); return PB_EINVAL; }
     if (t->fd_wg_per_cu < 0 || t->fd_wg_per_cu > 2) { set_error("fd_wg_per_cu must be 0, 1 or 2"); return PB_EINVAL; }
@@ -341,10 +359,12 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
 {
+    PB_API_BEGIN
     if (!b || !out) { set_error("NULL argument"); return PB_EINVAL; }
     out->fv_slab = b->fv_slab;
     out->fv_xcd_remap = b->fv_xcd_remap;
@@ -352,10 +372,12 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
     out->fd_wg_per_cu = b->fd_wg_per_cu;
     out->fv_dma = b->fv_dma;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_batch_set_c2p_guess(pb_batch *b, int32_t guess, const pb_mlp *mlp)
 {
+    PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
     if (b->pde != PB_PDE_SRHD) { set_error("con2prim guess applies to SRHD batches"); return PB_EINVAL; }
     if (guess < PB_GUESS_PLAIN || guess > PB_GUESS_WARM) { set_error("unknown guess mode"); return PB_EINVAL; }
@@ -365,10 +387,12 @@ pb_status pb_batch_set_c2p_guess(pb_batch *b, int32_t guess, const pb_mlp *mlp)
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_batch_stats(pb_batch *b, pb_stats *out)
 {
+    PB_API_BEGIN
     if (!b || !out) { set_error("NULL argument"); return PB_EINVAL; }
     Ctrl c;
     PB_HIP(hipMemcpyAsync(&c, b->ws, sizeof c, hipMemcpyDeviceToHost, b->stream));
@@ -384,6 +408,7 @@ pb_status pb_batch_stats(pb_batch *b, pb_stats *out)
     out->current = b->cur;
     out->last_dt = b->last_dt_host > 0.0 ? b->last_dt_host : c.dt[b->last_slot];
     return PB_OK;
+    PB_API_END
 }
 
 // run or replay a step sequence; `kind` 0 = FV, 1 = FD
@@ -460,14 +485,17 @@ static pb_status finish_call(pb_batch *b, int n, double dt_fixed, double *dt_las
 
 pb_status pb_batch_profile(pb_batch *b, int32_t on)
 {
+    PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
     b->profiling = on != 0;
     b->prof_n = 0;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_batch_profile_read(pb_batch *b, double *total_ms, int64_t *launches)
 {
+    PB_API_BEGIN
     if (!b || !total_ms || !launches) { set_error("NULL argument"); return PB_EINVAL; }
     PB_HIP(hipStreamSynchronize(b->stream));
     double sum = 0.0;
@@ -480,11 +508,13 @@ pb_status pb_batch_profile_read(pb_batch *b, double *total_ms, int64_t *launches
     *launches = b->prof_n;
     b->prof_n = 0;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_steps, int32_t use_graph,
                           double *dt_last_host)
 {
+    PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
     if (n_steps < 0) { set_error("n_steps must be >= 0"); return PB_EINVAL; }
     if (!std::isfinite(dt_fixed) || (!(dt_fixed > 0.0) && !(cfl > 0.0 && std::isfinite(cfl)))) {
@@ -498,11 +528,13 @@ pb_status fv_rusanov_step(pb_batch *b, double cfl, double dt_fixed, int32_t n_st
     pb_status st = run_steps(b, 0, cfl, dt_fixed, 0.0, 0, n_steps, use_graph);
     if (st != PB_OK) return st;
     return finish_call(b, n_steps, dt_fixed, dt_last_host);
+    PB_API_END
 }
 
 pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko, int32_t rk_stages,
                      int32_t n_steps, int32_t use_graph, double *dt_last_host)
 {
+    PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
     if (n_steps < 0) { set_error("n_steps must be >= 0"); return PB_EINVAL; }
     if (rk_stages != 1 && rk_stages != 4) { set_error("rk_stages must be 1 or 4"); return PB_EINVAL; }
@@ -537,6 +569,7 @@ pb_status fd_ko_step(pb_batch *b, double cfl, double dt_fixed, double sigma_ko, 
     st = run_steps(b, 1, cfl, dt_fixed, sigma_ko, rk_stages, n_steps, use_graph);
     if (st != PB_OK) return st;
     return finish_call(b, n_steps, dt, dt_last_host);
+    PB_API_END
 }
 
 }  // extern "C"

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -45,6 +47,18 @@ static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 // thread-local error text
 void set_error(const std::string &msg);
 pb_status hip_fail(hipError_t e, const char *what);
+
+// Every C-ABI entry point runs its body between PB_API_BEGIN and PB_API_END,
+// so no C++ exception (a failed host allocation, a thread that could not
+// start) crosses the C boundary: it becomes PB_ENOMEM or PB_EINVAL with a
+// message.
+pb_status api_fail(const char *what, pb_status st) noexcept;
+#define PB_API_BEGIN try {
+#define PB_API_END                                                                                    \
+    }                                                                                                 \
+    catch (const std::bad_alloc &) { return ::pb::api_fail("out of host memory", PB_ENOMEM); }        \
+    catch (const std::exception &e_) { return ::pb::api_fail(e_.what(), PB_EINVAL); }               \
+    catch (...) { return ::pb::api_fail("unexpected host error", PB_EINVAL); }
 
 #define PB_HIP(call)                                          \
     do {                                                      \

@@ -329,6 +329,7 @@ extern "C" {
 
 pb_status pb_mlp_create(pb_mlp **out)
 {
+    PB_API_BEGIN
     if (!out) { set_error("out is NULL"); return PB_EINVAL; }
     *out = nullptr;
     pb_mlp *m = new (std::nothrow) pb_mlp();
@@ -351,20 +352,24 @@ pb_status pb_mlp_create(pb_mlp **out)
     m->partial = reinterpret_cast<float *>(take((size_t)kChunks * kMlpNParam * sizeof(float)));
     *out = m;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_destroy(pb_mlp *m)
 {
+    PB_API_BEGIN
     if (!m) return PB_OK;
     if (m->scratch) (void)hipFree(m->scratch);
     if (m->lpart) (void)hipFree(m->lpart);
     (void)hipFree(m->dev);
     delete m;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_set_params(pb_mlp *m, const float *params, const float *norm)
 {
+    PB_API_BEGIN
     if (!m || !params || !norm) { set_error("NULL argument"); return PB_EINVAL; }
     for (int i = 0; i < kMlpNParam; ++i)
         if (!std::isfinite(params[i])) { set_error("MLP parameters must be finite"); return PB_EINVAL; }
@@ -380,19 +385,23 @@ pb_status pb_mlp_set_params(pb_mlp *m, const float *params, const float *norm)
     if (st != PB_OK) return st;
     PB_HIP(hipDeviceSynchronize());
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_get_params(pb_mlp *m, float *params, float *norm)
 {
+    PB_API_BEGIN
     if (!m) { set_error("NULL argument"); return PB_EINVAL; }
     PB_HIP(hipDeviceSynchronize());
     if (params) PB_HIP(hipMemcpy(params, m->par, kMlpNParam * sizeof(float), hipMemcpyDeviceToHost));
     if (norm) PB_HIP(hipMemcpy(norm, m->norm, kMlpNNorm * sizeof(float), hipMemcpyDeviceToHost));
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_forward(const pb_mlp *m, const void *x, void *y, int64_t n, void *stream)
 {
+    PB_API_BEGIN
     if (!m || !x || !y) { set_error("NULL argument"); return PB_EINVAL; }
     if (n < 0) { set_error("n must be >= 0"); return PB_EINVAL; }
     if (n == 0) return PB_OK;
@@ -403,10 +412,12 @@ pb_status pb_mlp_forward(const pb_mlp *m, const void *x, void *y, int64_t n, voi
                        static_cast<const float *>(x), static_cast<float *>(y), (long long)n);
     PB_HIP(hipGetLastError());
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_features(const void *cons, void *x, int64_t n, void *stream)
 {
+    PB_API_BEGIN
     if (!cons || !x) { set_error("NULL argument"); return PB_EINVAL; }
     if (n < 0) { set_error("n must be >= 0"); return PB_EINVAL; }
     if (n == 0) return PB_OK;
@@ -415,10 +426,12 @@ pb_status pb_mlp_features(const void *cons, void *x, int64_t n, void *stream)
                        static_cast<const double *>(cons), static_cast<float *>(x), (long long)n);
     PB_HIP(hipGetLastError());
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_grad(const pb_mlp *m, const void *x, const void *t, int64_t n, void *grad, void *loss, void *stream)
 {
+    PB_API_BEGIN
     if (!m || !x || !t || !grad || !loss) { set_error("NULL argument"); return PB_EINVAL; }
     if (n < 1) { set_error("n must be >= 1"); return PB_EINVAL; }
     pb_mlp *mm = const_cast<pb_mlp *>(m);
@@ -429,11 +442,13 @@ pb_status pb_mlp_grad(const pb_mlp *m, const void *x, const void *t, int64_t n, 
     PB_HIP(hipMemcpyAsync(grad, mm->grad, kMlpNParam * sizeof(float), hipMemcpyDeviceToDevice, s));
     PB_HIP(hipMemcpyAsync(loss, mm->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_mlp_train_step(pb_mlp *m, const void *x, const void *t, int64_t n, float lr, float beta1, float beta2,
                             float eps, int32_t step, void *loss, void *stream)
 {
+    PB_API_BEGIN
     if (!m || !x || !t) { set_error("NULL argument"); return PB_EINVAL; }
     if (n < 1) { set_error("n must be >= 1"); return PB_EINVAL; }
     if (step < 1) { set_error("step must be >= 1"); return PB_EINVAL; }
@@ -447,6 +462,7 @@ pb_status pb_mlp_train_step(pb_mlp *m, const void *x, const void *t, int64_t n, 
     if (st != PB_OK) return st;
     if (loss) PB_HIP(hipMemcpyAsync(loss, m->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
     return PB_OK;
+    PB_API_END
 }
 
 }  // extern "C"

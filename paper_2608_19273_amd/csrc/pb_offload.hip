@@ -129,13 +129,23 @@ void parallel_for(int n, size_t bytes, F &&f)
         return;
     }
     std::vector<std::thread> th;
+    try {
+        th.reserve(T);
+    } catch (...) {
+        for (int i = 0; i < n; ++i) f(i);
+        return;
+    }
     const int per = (n + T - 1) / T;
     for (int w = 0; w < T; ++w) {
         const int a = w * per, b = std::min(n, a + per);
         if (a >= b) break;
-        th.emplace_back([&f, a, b] {
-            for (int i = a; i < b; ++i) f(i);
-        });
+        try {
+            th.emplace_back([&f, a, b] {
+                for (int i = a; i < b; ++i) f(i);
+            });
+        } catch (...) {
+            for (int i = a; i < b; ++i) f(i);   // no thread for this range: run it here
+        }
     }
     for (auto &x : th) x.join();
 }
@@ -230,6 +240,7 @@ extern "C" {
 
 pb_status pb_offload_create(const pb_offload_desc *d, pb_offload **out)
 {
+    PB_API_BEGIN
     if (!d || !out) { set_error("NULL argument"); return PB_EINVAL; }
     *out = nullptr;
     if (d->dim != 3) { set_error("offload mode: dim 3 only"); return PB_EUNSUPPORTED; }
@@ -276,18 +287,22 @@ pb_status pb_offload_create(const pb_offload_desc *d, pb_offload **out)
     }
     *out = o;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_offload_destroy(pb_offload *o)
 {
+    PB_API_BEGIN
     if (!o) { set_error("offload object is NULL"); return PB_EINVAL; }
     free_offload(o);
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_offload_fv_step(pb_offload *o, int32_t K, const double *const *in_chunks, double *const *out_chunks,
                              const double *dx, double dt, pb_offload_timing *timing)
 {
+    PB_API_BEGIN
     if (!o) { set_error("offload object is NULL"); return PB_EINVAL; }
     if (K < 0) { set_error("K must be >= 0"); return PB_EINVAL; }
     if (!(dt > 0.0) || !std::isfinite(dt)) { set_error("dt must be finite and > 0"); return PB_EINVAL; }
@@ -341,6 +356,7 @@ pb_status pb_offload_fv_step(pb_offload *o, int32_t K, const double *const *in_c
     tm.total_ms = ms_since(t_start);
     if (timing) *timing = tm;
     return st;
+    PB_API_END
 }
 
 }  // extern "C"

@@ -380,6 +380,7 @@ extern "C" pb_status con2prim(const void *cons, void *prim, int64_t n, double ga
                               int32_t guess, const pb_mlp *mlp, const void *p_prev, void *iters, void *status,
                               void *counters, void *stream)
 {
+    PB_API_BEGIN
     if (n < 0) { set_error("con2prim: n must be >= 0"); return PB_EINVAL; }
     if (n > 0 && (!cons || !prim)) { set_error("con2prim: cons and prim are required"); return PB_EINVAL; }
     if (!(gamma > 1.0 && gamma <= 2.0)) { set_error("con2prim: Gamma must be in (1, 2]"); return PB_EINVAL; }
@@ -418,4 +419,5 @@ extern "C" pb_status con2prim(const void *cons, void *prim, int64_t n, double ga
     }
     PB_HIP(hipGetLastError());
     return PB_OK;
+    PB_API_END
 }

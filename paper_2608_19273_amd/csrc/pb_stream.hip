@@ -33,6 +33,7 @@ __global__ __launch_bounds__(256) void stream_copy_kernel(const double2 *__restr
 
 extern "C" pb_status pb_stream_copy(const void *src, void *dst, size_t bytes, void *stream)
 {
+    PB_API_BEGIN
     if (!src || !dst || bytes == 0 || (bytes % 32) != 0 || ((uintptr_t)src % 32) || ((uintptr_t)dst % 32)) {
         pb::set_error("pb_stream_copy: src, dst non-NULL, 32-byte aligned; bytes a positive multiple of 32");
         return PB_EINVAL;
@@ -44,4 +45,5 @@ extern "C" pb_status pb_stream_copy(const void *src, void *dst, size_t bytes, vo
                        static_cast<const double2 *>(src), static_cast<double2 *>(dst), n);
     PB_HIP(hipGetLastError());
     return PB_OK;
+    PB_API_END
 }

@@ -114,6 +114,7 @@ extern "C" {
 pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, double sigma_ko, int32_t trials,
                       int32_t use_cache, pb_autotune_result *out)
 {
+    PB_API_BEGIN
     if (!b || !out) { set_error("NULL argument"); return PB_EINVAL; }
     if (kind != 0 && kind != 1) { set_error("pb_autotune: kind must be 0 (FV) or 1 (FD)"); return PB_EINVAL; }
     if (trials < 1 || trials > 1000) { set_error("pb_autotune: trials must be in [1, 1000]"); return PB_EINVAL; }
@@ -207,10 +208,12 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
     }
     apply(b, before);
     return pb_batch_set_tuning(b, &cand[bi]);
+    PB_API_END
 }
 
 pb_status pb_autotune_cache_save(const char *path)
 {
+    PB_API_BEGIN
     if (!path) { set_error("NULL path"); return PB_EINVAL; }
     std::ofstream f(path, std::ios::trunc);
     if (!f) { set_error(std::string("cannot open ") + path + " for writing"); return PB_EINVAL; }
@@ -220,10 +223,12 @@ pb_status pb_autotune_cache_save(const char *path)
           << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << '\n';
     if (!f) { set_error(std::string("write failed: ") + path); return PB_EINVAL; }
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
 {
+    PB_API_BEGIN
     if (!path) { set_error("NULL path"); return PB_EINVAL; }
     if (n_loaded) *n_loaded = 0;
     std::ifstream f(path);
@@ -250,13 +255,16 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
     }
     if (n_loaded) *n_loaded = n;
     return PB_OK;
+    PB_API_END
 }
 
 pb_status pb_autotune_cache_clear(void)
 {
+    PB_API_BEGIN
     std::lock_guard<std::mutex> lk(g_mu);
     g_cache.clear();
     return PB_OK;
+    PB_API_END
 }
 
 }  // extern "C"
