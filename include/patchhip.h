@@ -28,7 +28,8 @@
  *     tables, released by the matching destroy call.
  *   - Work is enqueued asynchronously on the caller's stream (hipStream_t
  *     passed as void*; NULL = the null stream).  Host synchronisation happens
- *     only where a host output is requested (dt_last_host, stats, weights).
+ *     only where a host output is requested (dt_last_host, stats, weights),
+ *     and in offload mode, whose inputs and outputs are host memory.
  *
  * State layout in HBM ("patch-blocked structure of arrays")
  *   patch k with p_k cells per direction owns cells [off_k, off_k + p_k^d),
