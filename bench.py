@@ -127,6 +127,8 @@ def tune(B, kind, **kw):
     def name(t):
         if kind == "fv":
             return f"slab{t['fv_slab']}/remap{t['fv_xcd_remap']}/dma{t['fv_dma']}"
+        if t["fd_ws"]:
+            return f"ws/remap{t['fd_xcd_remap']}"
         return f"remap{t['fd_xcd_remap']}/wg{t['fd_wg_per_cu']}"
     return {"chosen": name(r["best"]), "from_cache": r["from_cache"],
             "candidates_us": {name(t): round(us, 2) for t, us in r["candidates"]}}

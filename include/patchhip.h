@@ -304,6 +304,11 @@ typedef struct {
                                  allows it (no SRHD, every p a multiple of 4,
                                  16-byte aligned state), 0 = the register-prefetch
                                  kernel (the default) */
+    int32_t fd_ws;            /* FD: 1 = the wave-specialised stage kernel (one
+                                 work-group of 8 waves per CU: 4 waves compute
+                                 gradients while 4 run the matrix product; the
+                                 default), 0 = the kernel in which every wave
+                                 does every phase (fd_wg_per_cu applies to it) */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
@@ -323,7 +328,8 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  *          a batch of one p with p^3 <= 256 runs the small-patch kernel,
  *          which has no launch-shape choice: one candidate, the current one;
  *   FV 2D: fv_xcd_remap {1, 0};
- *   FD:    fd_xcd_remap {1, 0} x fd_wg_per_cu {2, 1}.
+ *   FD:    fd_ws 1 x fd_xcd_remap {1, 0}, then fd_ws 0 x fd_xcd_remap {1, 0}
+ *          x fd_wg_per_cu {2, 1}.
  * Each candidate runs one untimed launch and then `trials` timed launches
  * (HIP events on the batch's stream), over two interleaved passes; its time
  * is the smaller of the two pass averages.  The trial launches read the
@@ -351,7 +357,7 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
                       int32_t use_cache, pb_autotune_result *out);
 
 /* The process-wide tuning cache as a text file, one entry per line:
- * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma>".
+ * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws>".
  * save writes every entry (replacing the file); load adds the file's entries
  * (a later entry of the same key wins) and stores their number in *n_loaded
  * (nullable).  Host-only; PB_EINVAL on a file that cannot be opened or a

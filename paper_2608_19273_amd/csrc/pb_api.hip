@@ -356,6 +356,7 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     b->fd_xcd_remap = t->fd_xcd_remap ? 1 : 0;
     b->fd_wg_per_cu = t->fd_wg_per_cu == 0 ? 2 : t->fd_wg_per_cu;
     b->fv_dma = t->fv_dma ? 1 : 0;
+    b->fd_ws = t->fd_ws ? 1 : 0;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     return PB_OK;
@@ -371,6 +372,7 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
     out->fd_xcd_remap = b->fd_xcd_remap;
     out->fd_wg_per_cu = b->fd_wg_per_cu;
     out->fv_dma = b->fv_dma;
+    out->fd_ws = b->fd_ws;
     return PB_OK;
     PB_API_END
 }

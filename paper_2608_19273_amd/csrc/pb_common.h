@@ -177,6 +177,7 @@ struct pb_batch {
     int fv_xcd_remap = 1;
     int fd_xcd_remap = 1;
     int fd_wg_per_cu = 2;
+    int fd_ws = 1;   // linear-system FD: wave-specialised kernel
     int fv_dma = 0;
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;

@@ -114,7 +114,12 @@ __device__ __forceinline__ TileSrc tile_src(const double *y, long long off, int 
     for (int i = 0; i < 3; ++i) {
         int x, yy, z;
         piece_coord(64 * i + l, x, yy, z);
-        t.fo[i] = (((tz + z + p) % p) * p + (ty + yy + p) % p) * p + (tx + x + p) % p;
+        // tile origin + footprint offset stays within one period of the patch
+        int gx = tx + x, gy = ty + yy, gz = tz + z;
+        gx += gx < 0 ? p : (gx >= p ? -p : 0);
+        gy += gy < 0 ? p : (gy >= p ? -p : 0);
+        gz += gz < 0 ? p : (gz >= p ? -p : 0);
+        t.fo[i] = (gz * p + gy) * p + gx;
     }
     return t;
 }
@@ -363,6 +368,295 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
     }
 }
 
+// ------------------------------------------------ wave-specialised stage --
+//
+// The same stage with the phases split between the waves of one 512-thread
+// work-group per CU: waves 4..7 (producers) stage the footprint of each chunk
+// of 8 unknowns in LDS and compute its gradients and dissipation, waves 0..3
+// (consumers) hold their rows of -B_d in registers and run only the dense
+// product and the stage update.  The two roles advance in lock step over the
+// same sequence of (tile, chunk) steps, one work-group barrier per step:
+//   step s  producers: gradients of chunk s + 1 (LDS ring slot (s+1) % 2),
+//                      footprint of chunk s + 2 into LDS from registers,
+//                      global loads of chunk s + 4 into those registers;
+//           consumers: matrix-core product of chunk s (slot s % 2), and at
+//                      the last chunk of a tile the stage update, whose Q^0
+//                      and accumulator loads were issued one chunk earlier.
+// The footprint goes HBM/L2 -> registers -> LDS with ordinary loads, so the
+// compiler tracks each load by its registers and the copy two steps ahead
+// really overlaps the arithmetic.  Every step has the same amount of work in
+// every role: indexes past the last step are clamped to it (its chunk is
+// loaded, written and differentiated again, and nobody reads the result).
+namespace {
+
+constexpr int kWsThreads = 512;
+
+struct WsTile {
+    long long off;
+    int p, tile;
+    double inv_dx;
+};
+
+__device__ __forceinline__ WsTile ws_tile(const FdItem *__restrict__ items, const PatchDev *__restrict__ patches,
+                                          int it)
+{
+    const FdItem item = items[it];
+    const PatchDev P = patches[item.patch];
+    return {P.off, P.p, item.tile, P.inv_dx};
+}
+
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+struct WsLds {
+    double q[2][kCh][kFoot];       // footprint ring
+    double g[2][3][kCh][kTC];      // gradients (matrix-core B operands)
+    double k[2][kCh][kTC];         // summed dissipation
+};
+
+// producer waves: gradients and dissipation of the chunks, and the staging of
+// their footprints
+template <int NCH>
+__device__ __forceinline__ void ws_producer(WsLds &L, const double *__restrict__ y,
+                                            const FdItem *__restrict__ items, const PatchDev *__restrict__ patches,
+                                            int slot, int G, int S, int N, double sigma)
+{
+    const int t = threadIdx.x - 256, pw = t >> 6, l = t & 63;
+    const int cx = l % kT, cy = (l / kT) % kT, cz = l / (kT * kT);
+    const int sc = foot_slot(cx, cy, cz);
+    int sy[6], sz[6];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sy[k] = foot_slot(cx, cy - 3 + k, cz);
+        sy[3 + k] = foot_slot(cx, cy + 1 + k, cz);
+        sz[k] = foot_slot(cx, cy, cz - 3 + k);
+        sz[3 + k] = foot_slot(cx, cy, cz + 1 + k);
+    }
+    // tile of the load cursor (sources of this lane's pieces) and of the
+    // gradient cursor (its 1/dx)
+    int kl = -1, kg = -1;
+    TileSrc src{};
+    double inv_dx = 0.0;
+
+    auto load = [&](int c, f64x2_t (&R)[2][3]) {
+        c = c < S ? c : S - 1;
+        const int k = c / NCH, ch = c - k * NCH;
+        if (k != kl) {
+            kl = k;
+            const WsTile T = ws_tile(items, patches, slot + k * G);
+            src = tile_src(y, T.off, T.p, T.tile, N);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int v0 = ch * kCh + 2 * pw + u, v = v0 < N ? v0 : N - 1;
+            const double *s = src.base + (long long)v * src.C;
+#pragma unroll
+            for (int i = 0; i < 3; ++i) R[u][i] = *reinterpret_cast<const f64x2_t *>(s + src.fo[i]);
+        }
+    };
+    auto stage_in = [&](int b, const f64x2_t (&R)[2][3]) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u)
+#pragma unroll
+            for (int i = 0; i < 3; ++i) *reinterpret_cast<f64x2_t *>(&L.q[b][2 * pw + u][128 * i + 2 * l]) = R[u][i];
+    };
+    auto grad = [&](int c) {
+        c = c < S ? c : S - 1;
+        const int k = c / NCH, ch = c - k * NCH, b = c & 1;
+        if (k != kg) {
+            kg = k;
+            inv_dx = ws_tile(items, patches, slot + k * G).inv_dx;
+        }
+        const double c4 = inv_dx / 12.0, cko = sigma * inv_dx / 64.0;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int vl = pw + 4 * j;
+            double g0 = 0.0, g1 = 0.0, g2 = 0.0, ko = 0.0;
+            if (ch * kCh + vl < N) {
+                const double *u = L.q[b][vl];
+                const double u0 = u[sc];
+                {
+                    const double m3 = u[sc - 3], m2 = u[sc - 2], m1 = u[sc - 1], p1 = u[sc + 1], p2 = u[sc + 2],
+                                 p3 = u[sc + 3];
+                    g0 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                }
+                {
+                    const double m3 = u[sy[0]], m2 = u[sy[1]], m1 = u[sy[2]], p1 = u[sy[3]], p2 = u[sy[4]],
+                                 p3 = u[sy[5]];
+                    g1 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                }
+                {
+                    const double m3 = u[sz[0]], m2 = u[sz[1]], m1 = u[sz[2]], p1 = u[sz[3]], p2 = u[sz[4]],
+                                 p3 = u[sz[5]];
+                    g2 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                }
+            }
+            L.g[b][0][vl][l] = g0;
+            L.g[b][1][vl][l] = g1;
+            L.g[b][2][vl][l] = g2;
+            L.k[b][vl][l] = cko * ko;
+        }
+    };
+
+    f64x2_t RA[2][3], RB[2][3];
+    load(0, RA);
+    load(1, RB);
+    stage_in(0, RA);
+    load(2, RA);
+    lds_barrier();
+    grad(0);
+    stage_in(1, RB);
+    load(3, RB);
+    lds_barrier();
+    // step s: RA holds chunk s + 2, RB chunk s + 3 (s even)
+    for (int s = 0; s < S; s += 2) {
+        grad(s + 1);
+        stage_in(0, RA);
+        load(s + 4, RA);
+        lds_barrier();
+        if (s + 1 >= S) break;
+        grad(s + 2);
+        stage_in(1, RB);
+        load(s + 5, RB);
+        lds_barrier();
+    }
+}
+
+// consumer waves: -sum_d B_d G_d on the matrix cores and the stage update
+template <int NCH>
+__device__ __forceinline__ void ws_consumer(const WsLds &L, const double *__restrict__ q0, double *__restrict__ ynext,
+                                            double *__restrict__ acc, const FdItem *__restrict__ items,
+                                            const PatchDev *__restrict__ patches, int slot, int G, int n_my,
+                                            const double *__restrict__ Bmat, int N, int stage, int rk, double dt)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lg = l >> 4, lj = l & 15;
+    double a[3][kMaxN / 4];
+    {
+        const int m = 16 * w + lj;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+            for (int ks = 0; ks < kMaxN / 4; ++ks) {
+                // every lane loads (clamped index), so no load sits in a branch
+                const int k = 4 * ks + lg;
+                const double bv = Bmat[(long long)d * N * N + (long long)(m < N ? m : N - 1) * N + (k < N ? k : N - 1)];
+                a[d][ks] = (m < N && k < N) ? -bv : 0.0;
+            }
+    }
+    // the stage update, with one form for every stage:
+    //   acc <- (Q^0 or acc) + ca R,   ynext <- Q^0 + cy R (stages 1-3 of RK4)
+    // both operand loads are always issued; an operand a stage does not need
+    // is read from the other array (same addresses, served by the cache)
+    const bool need_q0 = rk == 1 || stage < 3, need_acc = rk == 4 && stage > 0;
+    const double *__restrict__ srcq = need_q0 ? q0 : acc;
+    const double *__restrict__ srca = need_acc ? acc : q0;
+    const bool from_q0 = !need_acc, write_y = rk == 4 && stage < 3;
+    const double ca = rk == 1 ? dt : ((stage == 0 || stage == 3) ? dt / 6.0 : dt / 3.0);
+    const double cy = stage == 2 ? dt : 0.5 * dt;
+    constexpr int kPre = NCH >= 2 ? NCH - 2 : 0;   // chunk at which the update operands are fetched
+    lds_barrier();
+    lds_barrier();
+    int s = 0;
+    for (int kt = 0; kt < n_my; ++kt) {
+        const WsTile T = ws_tile(items, patches, slot + kt * G);
+        const int p = T.p, ntile = p / kT;
+        const long long C = (long long)p * p * p;
+        const int tx = kT * (T.tile % ntile), ty = kT * ((T.tile / ntile) % ntile),
+                  tz = kT * (T.tile / (ntile * ntile));
+        f64x4_t accm[4];
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) accm[nt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+        long long gbase[4];
+        double q0v[4][4], accv[4][4];
+#pragma unroll
+        for (int ch = 0; ch < NCH; ++ch, ++s) {
+            const int b = s & 1;
+            if (ch == kPre) {
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const int c = nt * 16 + lj;
+                    const int x = c % kT, yy = (c / kT) % kT, z = c / (kT * kT);
+                    gbase[nt] = T.off * N + ((long long)(tz + z) * p + (ty + yy)) * p + (tx + x);
+                }
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * w + lg + 4 * i;
+                        const long long g = gbase[nt] + (long long)(r < N ? r : N - 1) * C;
+                        q0v[nt][i] = srcq[g];
+                        accv[nt][i] = srca[g];
+                    }
+            }
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int kk = 0; kk < kCh / 4; ++kk) {
+                    const int ks = ch * (kCh / 4) + kk;
+                    if (ks >= kMaxN / 4) break;
+                    const double aop = a[d][ks];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+                        accm[nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, L.g[b][d][4 * kk + lg][nt * 16 + lj],
+                                                                        accm[nt], 0, 0, 0);
+                }
+            if (w == ch / 2) {
+                const int h = ch % 2;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int ii = 0; ii < 2; ++ii) accm[nt][2 * h + ii] += L.k[b][lg + 4 * ii][nt * 16 + lj];
+            }
+            if (ch == NCH - 1) {
+                // all arithmetic first (it consumes every load), then the stores
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const double R = accm[nt][i], qv = q0v[nt][i];
+                        accv[nt][i] = (from_q0 ? qv : accv[nt][i]) + ca * R;
+                        q0v[nt][i] = qv + cy * R;
+                        // pin the results here so the arithmetic (and its
+                        // waits for the loads) is not sunk between the stores:
+                        // a wait placed after a store also waits for the store
+                        __asm__ volatile("" : "+v"(accv[nt][i]), "+v"(q0v[nt][i]));
+                    }
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = 16 * w + lg + 4 * i;
+                        if (r >= N) continue;
+                        const long long g = gbase[nt] + (long long)r * C;
+                        acc[g] = accv[nt][i];
+                        if (write_y) ynext[g] = q0v[nt][i];
+                    }
+            }
+            lds_barrier();
+        }
+    }
+}
+
+}  // namespace
+
+template <int NCH>
+__global__ __launch_bounds__(kWsThreads) void fd_stage_ws_kernel(
+    const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
+    double *__restrict__ acc, const PatchDev *__restrict__ patches, const FdItem *__restrict__ items, int n_items,
+    const double *__restrict__ Bmat, int N, int stage, int rk, double dt, double sigma, int remap)
+{
+    __shared__ WsLds L;
+    const int G = (int)gridDim.x, slot = remap ? xcd_remap((int)blockIdx.x, G) : (int)blockIdx.x;
+    if (slot >= n_items) return;
+    const int n_my = (n_items - slot + G - 1) / G;
+    if (threadIdx.x >= 256)
+        ws_producer<NCH>(L, y, items, patches, slot, G, n_my * NCH, N, sigma);
+    else
+        ws_consumer<NCH>(L, q0, ynext, acc, items, patches, slot, G, n_my, Bmat, N, stage, rk, dt);
+}
+
 // ------------------------------------------------------------------ host --
 
 pb_status fd_prepare(pb_batch *b)
@@ -397,6 +691,30 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
     int dev = 0, cus = 0;
     PB_HIP(hipGetDevice(&dev));
     PB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (b->fd_ws) {
+        // one wave-specialised work-group per CU
+        const int grid = std::max(1, std::min(b->fd_n_items, cus));
+        const int nch = (b->N + kCh - 1) / kCh;
+        auto go = [&](auto kern) {
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kWsThreads), 0, s, static_cast<const double *>(y),
+                               static_cast<const double *>(q0), static_cast<double *>(ynext),
+                               static_cast<double *>(acc), b->d_patches,
+                               reinterpret_cast<const FdItem *>(b->d_fd_items), b->fd_n_items, b->d_fd_B, b->N,
+                               stage, rk_stages, dt, sigma, b->fd_xcd_remap);
+        };
+        switch (nch) {
+        case 1: go(fd_stage_ws_kernel<1>); break;
+        case 2: go(fd_stage_ws_kernel<2>); break;
+        case 3: go(fd_stage_ws_kernel<3>); break;
+        case 4: go(fd_stage_ws_kernel<4>); break;
+        case 5: go(fd_stage_ws_kernel<5>); break;
+        case 6: go(fd_stage_ws_kernel<6>); break;
+        case 7: go(fd_stage_ws_kernel<7>); break;
+        default: go(fd_stage_ws_kernel<8>); break;
+        }
+        PB_HIP(hipGetLastError());
+        return PB_OK;
+    }
     const int grid = std::max(1, std::min(b->fd_n_items, cus * b->fd_wg_per_cu));
     hipLaunchKernelGGL(fd_stage_kernel, dim3(grid), dim3(kFdThreads), 0, s, static_cast<const double *>(y),
                        static_cast<const double *>(q0), static_cast<double *>(ynext), static_cast<double *>(acc),

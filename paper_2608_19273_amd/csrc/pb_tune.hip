@@ -46,6 +46,7 @@ pb_tuning current(const pb_batch *b)
     t.fd_xcd_remap = b->fd_xcd_remap;
     t.fd_wg_per_cu = b->fd_wg_per_cu;
     t.fv_dma = b->fv_dma;
+    t.fd_ws = b->fd_ws;
     return t;
 }
 
@@ -56,6 +57,7 @@ void apply(pb_batch *b, const pb_tuning &t)
     b->fd_xcd_remap = t.fd_xcd_remap;
     b->fd_wg_per_cu = t.fd_wg_per_cu == 0 ? 2 : t.fd_wg_per_cu;
     b->fv_dma = t.fv_dma;
+    b->fd_ws = t.fd_ws;
 }
 
 std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
@@ -83,9 +85,16 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
                     c.push_back(t);
                 }
     } else {
+        for (int remap = 1; remap >= 0; --remap) {
+            pb_tuning t = base;
+            t.fd_ws = 1;
+            t.fd_xcd_remap = remap;
+            c.push_back(t);
+        }
         for (int wg = 2; wg >= 1; --wg)
             for (int remap = 1; remap >= 0; --remap) {
                 pb_tuning t = base;
+                t.fd_ws = 0;
                 t.fd_xcd_remap = remap;
                 t.fd_wg_per_cu = wg;
                 c.push_back(t);
@@ -220,7 +229,7 @@ pb_status pb_autotune_cache_save(const char *path)
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &e : g_cache)
         f << e.first << ' ' << e.second.fv_slab << ' ' << e.second.fv_xcd_remap << ' ' << e.second.fd_xcd_remap << ' '
-          << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << '\n';
+          << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << ' ' << e.second.fd_ws << '\n';
     if (!f) { set_error(std::string("write failed: ") + path); return PB_EINVAL; }
     return PB_OK;
     PB_API_END
@@ -241,10 +250,11 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
         std::istringstream in(line);
         std::string key, extra;
         pb_tuning t{};
-        if (!(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu >> t.fv_dma) || (in >> extra) ||
+        if (!(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu >> t.fv_dma >> t.fd_ws) ||
+            (in >> extra) ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
             t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
-            t.fv_dma > 1) {
+            t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 1) {
             set_error(std::string(path) + ":" + std::to_string(lineno) + ": malformed tuning entry");
             if (n_loaded) *n_loaded = n;
             return PB_EINVAL;

@@ -131,15 +131,15 @@ def test_autotune_cache_file_round_trip(tmp_path):
     a malformed line is rejected with the entries before it kept"""
     pb.pb_autotune_cache_clear()
     src = tmp_path / "in.txt"
-    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0\n")
+    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0\n")
     assert pb.pb_autotune_cache_load(str(src)) == 2
     out = tmp_path / "out.txt"
     pb.pb_autotune_cache_save(str(out))
     lines = sorted(out.read_text().splitlines())
-    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1",
-                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0"])
+    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1",
+                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0"])
     bad = tmp_path / "bad.txt"
-    bad.write_text("fv/x 4 1 1 2 1\nfv/y 99 1 1 2 1\nfv/z 4 1 1 2 1\n")
+    bad.write_text("fv/x 4 1 1 2 1 1\nfv/y 99 1 1 2 1 1\nfv/z 4 1 1 2 1 1\n")
     with pytest.raises(pb.PbError, match="bad.txt:2"):
         pb.pb_autotune_cache_load(str(bad))
     pb.pb_autotune_cache_save(str(out))

@@ -118,3 +118,30 @@ def test_config2_full_size_sampled_patches():
         got = b.patch_view(g, k)
         err = np.max(np.abs(got - ref), axis=(1, 2, 3)) / np.max(np.abs(ref), axis=(1, 2, 3))
         assert np.all(err <= 1e-12), (k, err.max())
+
+
+@pytest.mark.parametrize("N", [1, 5, 8, 13, 20, 33, 47, 58, 60])
+def test_wave_specialised_kernel_matches(N):
+    """The wave-specialised stage kernel (the default) against the oracle and,
+    bitwise, against the kernel in which every wave does every phase, for
+    every number of 8-unknown chunks (1..8, N not a multiple of 4 or 8
+    included), on 5 uneven patches (fewer tiles than CUs, so most
+    work-groups own one tile and the pipeline runs past its last step)."""
+    announce(f"fd wave-specialised N={N}")
+    need_gpu()
+    b = I.config2(n_patches=5, N=N, sizes=np.array([8, 4, 16, 4, 8], np.int32))
+    out = {}
+    for ws in (1, 0):
+        B = pb.PatchBatch(b)
+        B.set_tuning(fd_ws=ws)
+        assert B.get_tuning()["fd_ws"] == ws
+        B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
+        B.fd_ko_step(cfl=0.5, dt_fixed=1e-3, sigma_ko=0.05, rk_stages=1, n_steps=1)
+        out[ws] = B.download()
+        B.close()
+    np.testing.assert_array_equal(out[1], out[0])
+    o, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
+    b2 = b.copy()
+    b2.state = o
+    o2, _ = oracle.fd_step(b2, dt_fixed=1e-3, sigma=0.05, rk_stages=1, n_steps=1)
+    assert np.all(rel_err(b, out[1], o2) <= 1e-12)
