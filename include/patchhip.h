@@ -305,10 +305,12 @@ typedef struct {
                                  16-byte aligned state), 0 = the register-prefetch
                                  kernel (the default) */
     int32_t fd_ws;            /* FD: 1 = the wave-specialised stage kernel (one
-                                 work-group of 8 waves per CU: 4 waves compute
-                                 gradients while 4 run the matrix product; the
-                                 default), 0 = the kernel in which every wave
-                                 does every phase (fd_wg_per_cu applies to it) */
+                                 work-group of 12 waves per CU: 8 waves stage
+                                 data and compute gradients while 4 run the
+                                 matrix product and the update; the default),
+                                 0 = the kernel in which every wave does every
+                                 phase (fd_wg_per_cu applies to it); both give
+                                 bitwise equal results */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);

@@ -327,6 +327,7 @@ pb_status patch_batch_destroy(pb_batch *b)
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     (void)hipFree(b->d_patches);
     if (b->d_fd_items) (void)hipFree(b->d_fd_items);
+    if (b->d_fd_ws_items) (void)hipFree(b->d_fd_ws_items);
     if (b->d_fd_B) (void)hipFree(b->d_fd_B);
     delete b;
     return PB_OK;

@@ -186,6 +186,7 @@ struct pb_batch {
     // FD: tile work list (largest patches first) and the B_d matrices
     bool fd_ready = false;
     void *d_fd_items = nullptr;
+    void *d_fd_ws_items = nullptr;   // per-tile geometry of the wave-specialised kernel
     int fd_n_items = 0;
     double *d_fd_B = nullptr;
     // graph cache

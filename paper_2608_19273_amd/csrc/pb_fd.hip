@@ -5,8 +5,13 @@
 //   D4 u  = [(u_-2 - u_+2) + 8 (u_+1 - u_-1)] / (12 dx),
 //   KO6 u = sigma/(64 dx) [(u_-3 + u_+3) - 6 (u_-2 + u_+2) + 15 (u_-1 + u_+1) - 20 u_0].
 //
-// Work decomposition (MI355X): one persistent launch per RK stage, two
-// work-groups of four waves per CU.  Work items are 4x4x4 cell tiles, listed
+// Two kernels compute the same stage with the same arithmetic in the same
+// order (bitwise equal results): fd_stage_kernel below, in which every wave
+// runs every phase, and fd_stage_ws_kernel further down (the default), which
+// splits the phases between producer and consumer waves.
+//
+// Work decomposition of fd_stage_kernel (MI355X): one persistent launch per
+// RK stage, two work-groups of four waves per CU.  Work items are 4x4x4 cell tiles, listed
 // largest patches first with the tiles of a patch consecutive; the launch
 // walks the list in rounds of gridDim.x items, and inside a round the
 // work-groups of one XCD take one contiguous run (one whole 16^3 patch), so a
@@ -370,56 +375,84 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
 
 // ------------------------------------------------ wave-specialised stage --
 //
-// The same stage with the phases split between the waves of one 512-thread
-// work-group per CU: waves 4..7 (producers) stage the footprint of each chunk
-// of 8 unknowns in LDS and compute its gradients and dissipation, waves 0..3
-// (consumers) hold their rows of -B_d in registers and run only the dense
-// product and the stage update.  The two roles advance in lock step over the
-// same sequence of (tile, chunk) steps, one work-group barrier per step:
-//   step s  producers: gradients of chunk s + 1 (LDS ring slot (s+1) % 2),
-//                      footprint of chunk s + 2 into LDS from registers,
-//                      global loads of chunk s + 4 into those registers;
-//           consumers: matrix-core product of chunk s (slot s % 2), and at
-//                      the last chunk of a tile the stage update, whose Q^0
-//                      and accumulator loads were issued one chunk earlier.
-// The footprint goes HBM/L2 -> registers -> LDS with ordinary loads, so the
-// compiler tracks each load by its registers and the copy two steps ahead
-// really overlaps the arithmetic.  Every step has the same amount of work in
-// every role: indexes past the last step are clamped to it (its chunk is
-// loaded, written and differentiated again, and nobody reads the result).
+// The same stage with the phases split between the waves of one 768-thread
+// work-group per CU (3 waves per SIMD): waves 0..3 (consumers) hold their
+// rows of -B_d in registers and run only the dense product and the stage
+// update; waves 4..11 (producers) move data and compute the gradients.  Both
+// roles advance in lock step over the same sequence of (tile, chunk) steps,
+// one work-group barrier per step.  With c = s + j the chunk j steps ahead:
+//   producers, step s: gradients and dissipation of chunk s + 1 (LDS slot
+//     (s+1) % 2); footprint of chunk s + 2 into LDS from registers, then the
+//     global loads of chunk s + 4 into those registers; the stage-update
+//     operands (Q^0 and accumulator rows) of chunk s + 1 into their LDS ring
+//     slot from registers, then the loads of chunk s + 3;
+//   consumers, step s: matrix-core product of chunk s (slot s % 2) and, at
+//     the last chunk of a tile, the stage update from the LDS operand ring.
+// Every copy goes HBM/L2 -> registers -> LDS with ordinary loads issued two
+// steps before the data is needed, so the compiler tracks each load by its
+// registers and the copies overlap the arithmetic.  The operand ring has one
+// slot more than a tile has chunks: a slot is written one step before its
+// chunk and read at the tile's last step, and is rewritten only after that.
+// Indexes past the last step are clamped to it (that chunk is loaded,
+// written and differentiated again and nobody reads the result), except the
+// operand ring, which is not written past the last chunk.
 namespace {
 
-constexpr int kWsThreads = 512;
+constexpr int kWsThreads = 768;
 
-struct WsTile {
-    long long off;
-    int p, tile;
+}  // namespace
+
+// one work item of the wave-specialised kernel with its geometry resolved on
+// the host (a single 32-byte scalar load per tile)
+struct alignas(32) WsItem {
+    long long off;        // first cell of the patch
+    int p, tx, ty, tz;    // patch edge, tile origin
     double inv_dx;
 };
+static_assert(sizeof(WsItem) == 32, "WsItem layout");
 
-__device__ __forceinline__ WsTile ws_tile(const FdItem *__restrict__ items, const PatchDev *__restrict__ patches,
-                                          int it)
+namespace {
+
+// footprint sources of this lane (as tile_src) for a tile given by its origin
+__device__ __forceinline__ TileSrc tile_src_at(const double *y, const WsItem &T, int N)
 {
-    const FdItem item = items[it];
-    const PatchDev P = patches[item.patch];
-    return {P.off, P.p, item.tile, P.inv_dx};
+    TileSrc t;
+    const int p = T.p;
+    t.C = (long long)p * p * p;
+    t.base = y + T.off * N;
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        int x, yy, z;
+        piece_coord(64 * i + l, x, yy, z);
+        int gx = T.tx + x, gy = T.ty + yy, gz = T.tz + z;
+        gx += gx < 0 ? p : (gx >= p ? -p : 0);
+        gy += gy < 0 ? p : (gy >= p ? -p : 0);
+        gz += gz < 0 ? p : (gz >= p ? -p : 0);
+        t.fo[i] = (gz * p + gy) * p + gx;
+    }
+    return t;
 }
 
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
 
+template <int NCH>
 struct WsLds {
-    double q[2][kCh][kFoot];       // footprint ring
-    double g[2][3][kCh][kTC];      // gradients (matrix-core B operands)
-    double k[2][kCh][kTC];         // summed dissipation
+    static constexpr int R = NCH + 1;    // operand ring slots
+    double q[2][kCh][kFoot];             // footprint ring
+    double g[2][3][kCh][kTC];            // gradients (matrix-core B operands)
+    double k[2][kCh][kTC];               // summed dissipation
+    double u[R][2][kCh][kTC];            // update operands: [slot][Q^0-side, acc-side][unknown][cell]
 };
 
-// producer waves: gradients and dissipation of the chunks, and the staging of
-// their footprints
+// producer waves: footprints, gradients and dissipation, update operands
 template <int NCH>
-__device__ __forceinline__ void ws_producer(WsLds &L, const double *__restrict__ y,
-                                            const FdItem *__restrict__ items, const PatchDev *__restrict__ patches,
-                                            int slot, int G, int S, int N, double sigma)
+__device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restrict__ y,
+                                            const double *__restrict__ srcq, const double *__restrict__ srca,
+                                            const WsItem *__restrict__ items, int slot, int G, int S, int N,
+                                            double sigma)
 {
+    constexpr int R = WsLds<NCH>::R;
     const int t = threadIdx.x - 256, pw = t >> 6, l = t & 63;
     const int cx = l % kT, cy = (l / kT) % kT, cz = l / (kT * kT);
     const int sc = foot_slot(cx, cy, cz);
@@ -431,106 +464,131 @@ __device__ __forceinline__ void ws_producer(WsLds &L, const double *__restrict__
         sz[k] = foot_slot(cx, cy, cz - 3 + k);
         sz[3 + k] = foot_slot(cx, cy, cz + 1 + k);
     }
-    // tile of the load cursor (sources of this lane's pieces) and of the
-    // gradient cursor (its 1/dx)
-    int kl = -1, kg = -1;
-    TileSrc src{};
+    // this thread's piece of the update operands of a chunk: side (Q^0 or
+    // accumulator), unknown within the chunk, two x-adjacent cells
+    const int us = t >> 8, uv = (t >> 5) & 7, uc = 2 * (t & 31);
+    const int ux = uc % kT, uy = (uc / kT) % kT, uz = uc / (kT * kT);
+    const double *__restrict__ usrc = us ? srca : srcq;
+    // tile caches of the three cursors (footprint loads, gradients, operand loads)
+    int kf = -1, kg = -1, ku = -1;
+    TileSrc fsrc{};
     double inv_dx = 0.0;
+    long long ubase = 0, uC = 0;
 
-    auto load = [&](int c, f64x2_t (&R)[2][3]) {
+    auto load_foot = [&](int c, f64x2_t (&F)[3]) {
         c = c < S ? c : S - 1;
         const int k = c / NCH, ch = c - k * NCH;
-        if (k != kl) {
-            kl = k;
-            const WsTile T = ws_tile(items, patches, slot + k * G);
-            src = tile_src(y, T.off, T.p, T.tile, N);
+        if (k != kf) {
+            kf = k;
+            fsrc = tile_src_at(y, items[slot + k * G], N);
         }
+        const int v0 = ch * kCh + pw, v = v0 < N ? v0 : N - 1;
+        const double *s = fsrc.base + (long long)v * fsrc.C;
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int v0 = ch * kCh + 2 * pw + u, v = v0 < N ? v0 : N - 1;
-            const double *s = src.base + (long long)v * src.C;
-#pragma unroll
-            for (int i = 0; i < 3; ++i) R[u][i] = *reinterpret_cast<const f64x2_t *>(s + src.fo[i]);
-        }
+        for (int i = 0; i < 3; ++i) F[i] = *reinterpret_cast<const f64x2_t *>(s + fsrc.fo[i]);
     };
-    auto stage_in = [&](int b, const f64x2_t (&R)[2][3]) {
+    auto stage_foot = [&](int b, const f64x2_t (&F)[3]) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u)
-#pragma unroll
-            for (int i = 0; i < 3; ++i) *reinterpret_cast<f64x2_t *>(&L.q[b][2 * pw + u][128 * i + 2 * l]) = R[u][i];
+        for (int i = 0; i < 3; ++i) *reinterpret_cast<f64x2_t *>(&L.q[b][pw][128 * i + 2 * l]) = F[i];
+    };
+    auto load_upd = [&](int c) -> f64x2_t {
+        c = c < S ? c : S - 1;
+        const int k = c / NCH, ch = c - k * NCH;
+        if (k != ku) {
+            ku = k;
+            const WsItem T = items[slot + k * G];
+            const int p = T.p;
+            uC = (long long)p * p * p;
+            ubase = T.off * N + ((long long)(T.tz + uz) * p + (T.ty + uy)) * p + (T.tx + ux);
+        }
+        const int v0 = ch * kCh + uv, v = v0 < N ? v0 : N - 1;
+        return *reinterpret_cast<const f64x2_t *>(usrc + ubase + (long long)v * uC);
+    };
+    auto stage_upd = [&](int c, const f64x2_t &U) {
+        if (c < S) *reinterpret_cast<f64x2_t *>(&L.u[c % R][us][uv][uc]) = U;
     };
     auto grad = [&](int c) {
         c = c < S ? c : S - 1;
         const int k = c / NCH, ch = c - k * NCH, b = c & 1;
         if (k != kg) {
             kg = k;
-            inv_dx = ws_tile(items, patches, slot + k * G).inv_dx;
+            inv_dx = items[slot + k * G].inv_dx;
         }
         const double c4 = inv_dx / 12.0, cko = sigma * inv_dx / 64.0;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int vl = pw + 4 * j;
-            double g0 = 0.0, g1 = 0.0, g2 = 0.0, ko = 0.0;
-            if (ch * kCh + vl < N) {
-                const double *u = L.q[b][vl];
-                const double u0 = u[sc];
-                {
-                    const double m3 = u[sc - 3], m2 = u[sc - 2], m1 = u[sc - 1], p1 = u[sc + 1], p2 = u[sc + 2],
-                                 p3 = u[sc + 3];
-                    g0 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
-                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
-                }
-                {
-                    const double m3 = u[sy[0]], m2 = u[sy[1]], m1 = u[sy[2]], p1 = u[sy[3]], p2 = u[sy[4]],
-                                 p3 = u[sy[5]];
-                    g1 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
-                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
-                }
-                {
-                    const double m3 = u[sz[0]], m2 = u[sz[1]], m1 = u[sz[2]], p1 = u[sz[3]], p2 = u[sz[4]],
-                                 p3 = u[sz[5]];
-                    g2 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
-                    ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
-                }
+        const int vl = pw;
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, ko = 0.0;
+        if (ch * kCh + vl < N) {
+            const double *u = L.q[b][vl];
+            const double u0 = u[sc];
+            {
+                const double m3 = u[sc - 3], m2 = u[sc - 2], m1 = u[sc - 1], p1 = u[sc + 1], p2 = u[sc + 2],
+                             p3 = u[sc + 3];
+                g0 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
             }
-            L.g[b][0][vl][l] = g0;
-            L.g[b][1][vl][l] = g1;
-            L.g[b][2][vl][l] = g2;
-            L.k[b][vl][l] = cko * ko;
+            {
+                const double m3 = u[sy[0]], m2 = u[sy[1]], m1 = u[sy[2]], p1 = u[sy[3]], p2 = u[sy[4]],
+                             p3 = u[sy[5]];
+                g1 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+            }
+            {
+                const double m3 = u[sz[0]], m2 = u[sz[1]], m1 = u[sz[2]], p1 = u[sz[3]], p2 = u[sz[4]],
+                             p3 = u[sz[5]];
+                g2 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                ko += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+            }
         }
+        L.g[b][0][vl][l] = g0;
+        L.g[b][1][vl][l] = g1;
+        L.g[b][2][vl][l] = g2;
+        L.k[b][vl][l] = cko * ko;
     };
 
-    f64x2_t RA[2][3], RB[2][3];
-    load(0, RA);
-    load(1, RB);
-    stage_in(0, RA);
-    load(2, RA);
+    // step -2 and -1 (before the consumers' first product), then steps 0..S-1;
+    // footprint sets: FA for even steps, FB for odd; operand sets: UB for
+    // even steps, UA for odd
+    f64x2_t FA[3], FB[3], UA, UB;
+    load_foot(0, FA);
+    load_foot(1, FB);
+    UA = load_upd(0);
+    // step -2
+    stage_foot(0, FA);
+    load_foot(2, FA);
+    UB = load_upd(1);
     lds_barrier();
+    // step -1
     grad(0);
-    stage_in(1, RB);
-    load(3, RB);
+    stage_foot(1, FB);
+    load_foot(3, FB);
+    stage_upd(0, UA);
+    UA = load_upd(2);
     lds_barrier();
-    // step s: RA holds chunk s + 2, RB chunk s + 3 (s even)
     for (int s = 0; s < S; s += 2) {
         grad(s + 1);
-        stage_in(0, RA);
-        load(s + 4, RA);
+        stage_foot(0, FA);
+        load_foot(s + 4, FA);
+        stage_upd(s + 1, UB);
+        UB = load_upd(s + 3);
         lds_barrier();
         if (s + 1 >= S) break;
         grad(s + 2);
-        stage_in(1, RB);
-        load(s + 5, RB);
+        stage_foot(1, FB);
+        load_foot(s + 5, FB);
+        stage_upd(s + 2, UA);
+        UA = load_upd(s + 4);
         lds_barrier();
     }
 }
 
 // consumer waves: -sum_d B_d G_d on the matrix cores and the stage update
 template <int NCH>
-__device__ __forceinline__ void ws_consumer(const WsLds &L, const double *__restrict__ q0, double *__restrict__ ynext,
-                                            double *__restrict__ acc, const FdItem *__restrict__ items,
-                                            const PatchDev *__restrict__ patches, int slot, int G, int n_my,
+__device__ __forceinline__ void ws_consumer(const WsLds<NCH> &L, double *__restrict__ ynext,
+                                            double *__restrict__ acc, const WsItem *__restrict__ items,
+                                            int slot, int G, int n_my,
                                             const double *__restrict__ Bmat, int N, int stage, int rk, double dt)
 {
+    constexpr int R = WsLds<NCH>::R;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lg = l >> 4, lj = l & 15;
     double a[3][kMaxN / 4];
     {
@@ -546,50 +604,24 @@ __device__ __forceinline__ void ws_consumer(const WsLds &L, const double *__rest
             }
     }
     // the stage update, with one form for every stage:
-    //   acc <- (Q^0 or acc) + ca R,   ynext <- Q^0 + cy R (stages 1-3 of RK4)
-    // both operand loads are always issued; an operand a stage does not need
-    // is read from the other array (same addresses, served by the cache)
-    const bool need_q0 = rk == 1 || stage < 3, need_acc = rk == 4 && stage > 0;
-    const double *__restrict__ srcq = need_q0 ? q0 : acc;
-    const double *__restrict__ srca = need_acc ? acc : q0;
-    const bool from_q0 = !need_acc, write_y = rk == 4 && stage < 3;
+    //   acc <- (Q^0-side) + ca R,   ynext <- Q^0 + cy R (stages 1-3 of RK4);
+    // the operand ring holds Q^0 (or, where a stage needs no Q^0, the
+    // accumulator) on one side and the accumulator (or Q^0) on the other
+    const bool from_q0 = !(rk == 4 && stage > 0), write_y = rk == 4 && stage < 3;
     const double ca = rk == 1 ? dt : ((stage == 0 || stage == 3) ? dt / 6.0 : dt / 3.0);
     const double cy = stage == 2 ? dt : 0.5 * dt;
-    constexpr int kPre = NCH >= 2 ? NCH - 2 : 0;   // chunk at which the update operands are fetched
     lds_barrier();
     lds_barrier();
     int s = 0;
     for (int kt = 0; kt < n_my; ++kt) {
-        const WsTile T = ws_tile(items, patches, slot + kt * G);
-        const int p = T.p, ntile = p / kT;
-        const long long C = (long long)p * p * p;
-        const int tx = kT * (T.tile % ntile), ty = kT * ((T.tile / ntile) % ntile),
-                  tz = kT * (T.tile / (ntile * ntile));
+        // the tile's geometry, fetched now for the update at its last chunk
+        const WsItem T = items[slot + kt * G];
         f64x4_t accm[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) accm[nt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
-        long long gbase[4];
-        double q0v[4][4], accv[4][4];
 #pragma unroll
         for (int ch = 0; ch < NCH; ++ch, ++s) {
             const int b = s & 1;
-            if (ch == kPre) {
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt) {
-                    const int c = nt * 16 + lj;
-                    const int x = c % kT, yy = (c / kT) % kT, z = c / (kT * kT);
-                    gbase[nt] = T.off * N + ((long long)(tz + z) * p + (ty + yy)) * p + (tx + x);
-                }
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = 16 * w + lg + 4 * i;
-                        const long long g = gbase[nt] + (long long)(r < N ? r : N - 1) * C;
-                        q0v[nt][i] = srcq[g];
-                        accv[nt][i] = srca[g];
-                    }
-            }
 #pragma unroll
             for (int d = 0; d < 3; ++d)
 #pragma unroll
@@ -610,29 +642,32 @@ __device__ __forceinline__ void ws_consumer(const WsLds &L, const double *__rest
                     for (int ii = 0; ii < 2; ++ii) accm[nt][2 * h + ii] += L.k[b][lg + 4 * ii][nt * 16 + lj];
             }
             if (ch == NCH - 1) {
-                // all arithmetic first (it consumes every load), then the stores
+                // element (nt, i) of this lane: unknown r = 16 w + lg + 4 i,
+                // cell nt * 16 + lj = (x, y, z) = (lj % 4, lj / 4, nt) of the
+                // tile; both addresses are a lane base plus uniform offsets
+                const int p = T.p;
+                const long long C = (long long)p * p * p, pp = (long long)p * p;
+                const long long gl = T.off * N + ((long long)T.tz * p + T.ty + lj / kT) * p + T.tx + lj % kT +
+                                     (long long)(16 * w + lg) * C;
+                const double *ul = &L.u[0][0][lg][lj];
+                const int c0 = s - ch;   // global index of the tile's first chunk
 #pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
+                for (int i = 0; i < 4; ++i) {
+                    // operand ring slot of unknown row r (its chunk is 2 w + i / 2)
+                    const int rc = 2 * w + i / 2 < NCH ? 2 * w + i / 2 : NCH - 1;
+                    const double *ui = ul + ((c0 + rc) % R) * (2 * kCh * kTC) + 4 * (i % 2) * kTC;
+                    const bool live = 16 * w + lg + 4 * i < N;
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const double R = accm[nt][i], qv = q0v[nt][i];
-                        accv[nt][i] = (from_q0 ? qv : accv[nt][i]) + ca * R;
-                        q0v[nt][i] = qv + cy * R;
-                        // pin the results here so the arithmetic (and its
-                        // waits for the loads) is not sunk between the stores:
-                        // a wait placed after a store also waits for the store
-                        __asm__ volatile("" : "+v"(accv[nt][i]), "+v"(q0v[nt][i]));
+                    for (int nt = 0; nt < 4; ++nt) {
+                        const double R0 = accm[nt][i], qv = ui[nt * 16], av = ui[kCh * kTC + nt * 16];
+                        const double an = (from_q0 ? qv : av) + ca * R0, yn = qv + cy * R0;
+                        if (live) {
+                            const long long g = gl + nt * pp + 4 * i * C;
+                            acc[g] = an;
+                            if (write_y) ynext[g] = yn;
+                        }
                     }
-#pragma unroll
-                for (int nt = 0; nt < 4; ++nt)
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = 16 * w + lg + 4 * i;
-                        if (r >= N) continue;
-                        const long long g = gbase[nt] + (long long)r * C;
-                        acc[g] = accv[nt][i];
-                        if (write_y) ynext[g] = q0v[nt][i];
-                    }
+                }
             }
             lds_barrier();
         }
@@ -644,17 +679,21 @@ __device__ __forceinline__ void ws_consumer(const WsLds &L, const double *__rest
 template <int NCH>
 __global__ __launch_bounds__(kWsThreads) void fd_stage_ws_kernel(
     const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
-    double *__restrict__ acc, const PatchDev *__restrict__ patches, const FdItem *__restrict__ items, int n_items,
-    const double *__restrict__ Bmat, int N, int stage, int rk, double dt, double sigma, int remap)
+    double *__restrict__ acc, const WsItem *__restrict__ items, int n_items, const double *__restrict__ Bmat, int N,
+    int stage, int rk, double dt, double sigma, int remap)
 {
-    __shared__ WsLds L;
+    __shared__ WsLds<NCH> L;
     const int G = (int)gridDim.x, slot = remap ? xcd_remap((int)blockIdx.x, G) : (int)blockIdx.x;
     if (slot >= n_items) return;
     const int n_my = (n_items - slot + G - 1) / G;
-    if (threadIdx.x >= 256)
-        ws_producer<NCH>(L, y, items, patches, slot, G, n_my * NCH, N, sigma);
-    else
-        ws_consumer<NCH>(L, q0, ynext, acc, items, patches, slot, G, n_my, Bmat, N, stage, rk, dt);
+    if (threadIdx.x >= 256) {
+        // the stage's update operands: Q^0 and the accumulator where it needs
+        // both, else the one it needs on both sides
+        const bool need_q0 = rk == 1 || stage < 3, need_acc = rk == 4 && stage > 0;
+        ws_producer<NCH>(L, y, need_q0 ? q0 : acc, need_acc ? acc : q0, items, slot, G, n_my * NCH, N, sigma);
+    } else {
+        ws_consumer<NCH>(L, ynext, acc, items, slot, G, n_my, Bmat, N, stage, rk, dt);
+    }
 }
 
 // ------------------------------------------------------------------ host --
@@ -672,6 +711,17 @@ pb_status fd_prepare(pb_batch *b)
         for (int t = 0; t < nt * nt * nt; ++t) items.push_back({k, t});
     }
     const size_t nB = (size_t)3 * b->N * b->N;
+    std::vector<WsItem> ws((size_t)items.size());
+    {
+        std::vector<long long> off((size_t)b->K + 1, 0);
+        for (int k = 0; k < b->K; ++k) off[k + 1] = off[k] + (long long)b->p[k] * b->p[k] * b->p[k];
+        for (size_t i = 0; i < items.size(); ++i) {
+            const int k = items[i].patch, p = b->p[k], nt = p / kT, t = items[i].tile;
+            ws[i] = WsItem{off[k], p, kT * (t % nt), kT * ((t / nt) % nt), kT * (t / (nt * nt)), 1.0 / b->dx[k]};
+        }
+    }
+    PB_HIP(hipMalloc(&b->d_fd_ws_items, ws.size() * sizeof(WsItem)));
+    PB_HIP(hipMemcpy(b->d_fd_ws_items, ws.data(), ws.size() * sizeof(WsItem), hipMemcpyHostToDevice));
     PB_HIP(hipMalloc(&b->d_fd_items, items.size() * sizeof(FdItem)));
     PB_HIP(hipMalloc(&b->d_fd_B, nB * sizeof(double)));
     PB_HIP(hipMemcpy(b->d_fd_items, items.data(), items.size() * sizeof(FdItem), hipMemcpyHostToDevice));
@@ -698,9 +748,8 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
         auto go = [&](auto kern) {
             hipLaunchKernelGGL(kern, dim3(grid), dim3(kWsThreads), 0, s, static_cast<const double *>(y),
                                static_cast<const double *>(q0), static_cast<double *>(ynext),
-                               static_cast<double *>(acc), b->d_patches,
-                               reinterpret_cast<const FdItem *>(b->d_fd_items), b->fd_n_items, b->d_fd_B, b->N,
-                               stage, rk_stages, dt, sigma, b->fd_xcd_remap);
+                               static_cast<double *>(acc), reinterpret_cast<const WsItem *>(b->d_fd_ws_items),
+                               b->fd_n_items, b->d_fd_B, b->N, stage, rk_stages, dt, sigma, b->fd_xcd_remap);
         };
         switch (nch) {
         case 1: go(fd_stage_ws_kernel<1>); break;
