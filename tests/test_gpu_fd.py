@@ -120,7 +120,7 @@ def test_config2_full_size_sampled_patches():
         assert np.all(err <= 1e-12), (k, err.max())
 
 
-@pytest.mark.parametrize("N", [1, 5, 8, 13, 20, 33, 47, 58, 60])
+@pytest.mark.parametrize("N", [1, 5, 8, 13, 20, 29, 33, 47, 53, 58, 60])
 def test_wave_specialised_kernel_matches(N):
     """The wave-specialised stage kernel (the default) against the oracle and,
     bitwise, against the kernel in which every wave does every phase, for
