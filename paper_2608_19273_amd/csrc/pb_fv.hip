@@ -178,9 +178,11 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     double lzc = 0.0;
     double lm[3] = {0.0, 0.0, 0.0};
     bool bad = false;
-    // two-deep prefetch rings (raw storage-type values): the own column for
-    // planes z+1, z+2 and the halo cell for planes z, z+1
-    RawCell<Ph, T> rnA, rnB, hrA, hrB;
+    // one-plane prefetch (raw storage-type values): the own column for plane
+    // z+1 and the halo cell for plane z.  One plane ahead is as fast as two or
+    // three, and with the next plane's flux evaluated after the x and y
+    // directions the kernel fits in 3 waves per SIMD without spilling.
+    RawCell<Ph, T> rnA, hrA;
 
     auto own_plane_off = [&](int zz) -> long long { return zz >= p ? onb[5] : P.off; };
     auto own_plane_c = [&](int zz) -> long long { return (zz >= p ? zz - p : zz) * pp + cxy; };
@@ -199,7 +201,6 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
             const int zm = (z0 == 0) ? p - 1 : z0 - 1;
             issue_load<Ph>(qin, ex, om, C, zm * pp + cxy, rm);
             issue_load<Ph>(qin, ex, own_plane_off(z0 + 1), C, own_plane_c(z0 + 1), rnA);
-            issue_load<Ph>(qin, ex, own_plane_off(min(z0 + 2, z1)), C, own_plane_c(min(z0 + 2, z1)), rnB);
             double qm[N], am[AA], fzm[N];
             unpack<Ph>(rm, qm, e);
             ph.aux(qm, e, am);
@@ -216,25 +217,15 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     }
     if (work) {
         issue_load<Ph>(qin, ex, hoff, C, z0 * pp + hsrc, hrA);
-        issue_load<Ph>(qin, ex, hoff, C, min(z0 + 1, z1 - 1) * pp + hsrc, hrB);
     }
 
     // one plane: consumes rn (own plane z+1) and hr (halo of plane z), then
-    // refills them with planes z+3 and z+2
+    // refills them with planes z+2 and z+1
     auto plane = [&](int z, RawCell<Ph, T> &rn, RawCell<Ph, T> &hr) {
         double(*buf)[PH * PH] = lds[z & 1];
-        double qn[N], an[AA], fzn[N];
-        double lzn = 0.0;
-        if (DIM == 3) {
-            unpack<Ph>(rn, qn, e);
-            issue_load<Ph>(qin, ex, own_plane_off(min(z + 3, z1)), C, own_plane_c(min(z + 3, z1)), rn);
-            ph.aux(qn, e, an);
-            phys_flux_or_zero<Ph, DZ>(ph, qn, an, fzn);
-            lzn = ph.template eig<DZ>(qn, an);
-        }
         double hq[N], he[1];
         unpack<Ph>(hr, hq, he);
-        issue_load<Ph>(qin, ex, hoff, C, min(z + 2, z1 - 1) * pp + hsrc, hr);
+        issue_load<Ph>(qin, ex, hoff, C, min(z + 1, z1 - 1) * pp + hsrc, hr);
         if (halo) {
             double ha[AA];
             ph.aux(hq, he, ha);
@@ -250,10 +241,10 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
             for (int a = 0; a < A; ++a) buf[N + a][li] = ac[a];
         }
         lds_barrier();   // (no thread reads what another writes to global memory)
-        if (active) {
-            double acc2[N];
+        double acc2[N];
 #pragma unroll
-            for (int v = 0; v < N; ++v) acc2[v] = 0.0;
+        for (int v = 0; v < N; ++v) acc2[v] = 0.0;
+        if (active) {
             {
                 double qL[N], aL[AA], qR[N], aR[AA];
 #pragma unroll
@@ -270,6 +261,19 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
                 for (int a = 0; a < A; ++a) { aL[a] = buf[N + a][li - PH]; aR[a] = buf[N + a][li + PH]; }
                 rusanov_pair2<Ph, 1>(ph, qL, aL, qc, ac, qR, aR, acc2);
             }
+        }
+        // the next plane's primitives, flux and speed, after the x and y
+        // directions: fewer values are live at once (3 waves per SIMD)
+        double qn[N], an[AA], fzn[N];
+        double lzn = 0.0;
+        if (DIM == 3) {
+            unpack<Ph>(rn, qn, e);
+            issue_load<Ph>(qin, ex, own_plane_off(min(z + 2, z1)), C, own_plane_c(min(z + 2, z1)), rn);
+            ph.aux(qn, e, an);
+            phys_flux_or_zero<Ph, DZ>(ph, qn, an, fzn);
+            lzn = ph.template eig<DZ>(qn, an);
+        }
+        if (active) {
             if (DIM == 3) {
                 double fs2u[N], dn2u[N];
                 rusanov_face2<Ph, DZ>(ph, qc, fzc, lzc, qn, fzn, lzn, fs2u, dn2u);
@@ -308,10 +312,7 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
         }
     };
 
-    for (int z = z0; z < z1; z += 2) {
-        plane(z, rnA, hrA);
-        if (z + 1 < z1) plane(z + 1, rnB, hrB);
-    }
+    for (int z = z0; z < z1; ++z) plane(z, rnA, hrA);
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
     if (kLam) store_partial<DIM>(part, lm, unit, n_units);
 }
