@@ -122,13 +122,26 @@ __device__ __forceinline__ void phys_flux_or_zero(const Ph &ph, const double *q,
     }
 }
 
+// The aux values an x or y neighbour's flux and speed read, which the plane
+// kernel passes through LDS: all of them, except for SRHD, whose direction d
+// reads p, v_d and lambda_d only, so v_z and lambda_z stay in the z carry
+// (10 instead of 12 values per cell: three work-groups fit a CU's LDS).
+template <class Ph> struct PlaneAux {
+    static constexpr int n = Ph::A;
+    static __device__ __forceinline__ constexpr int idx(int j) { return j; }
+};
+template <> struct PlaneAux<Srhd> {
+    static constexpr int n = 5;
+    static __device__ __forceinline__ constexpr int idx(int j) { return j < 3 ? j : j + 1; }   // p, v_x, v_y, l_x, l_y
+};
+
 template <class Ph, int DIM, typename T, bool kLam>
 __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
     const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
     Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in, double dt_fixed, Ph ph)
 {
-    constexpr int N = Ph::N, A = Ph::A, W = N + A, AA = A > 0 ? A : 1;
+    constexpr int N = Ph::N, A = Ph::A, AP = PlaneAux<Ph>::n, W = N + AP, AA = A > 0 ? A : 1;
     constexpr int PH = kFvPmax + 2;
     constexpr int DZ = DIM == 3 ? 2 : 1;   // z direction index (unused in 2D)
     __shared__ double lds[2][W][PH * PH];
@@ -232,13 +245,13 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
 #pragma unroll
             for (int v = 0; v < N; ++v) buf[v][hdst] = hq[v];
 #pragma unroll
-            for (int a = 0; a < A; ++a) buf[N + a][hdst] = ha[a];
+            for (int j = 0; j < AP; ++j) buf[N + j][hdst] = ha[PlaneAux<Ph>::idx(j)];
         }
         if (active) {
 #pragma unroll
             for (int v = 0; v < N; ++v) buf[v][li] = qc[v];
 #pragma unroll
-            for (int a = 0; a < A; ++a) buf[N + a][li] = ac[a];
+            for (int j = 0; j < AP; ++j) buf[N + j][li] = ac[PlaneAux<Ph>::idx(j)];
         }
         lds_barrier();   // (no thread reads what another writes to global memory)
         double acc2[N];
@@ -250,7 +263,12 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
 #pragma unroll
                 for (int v = 0; v < N; ++v) { qL[v] = buf[v][li - 1]; qR[v] = buf[v][li + 1]; }
 #pragma unroll
-                for (int a = 0; a < A; ++a) { aL[a] = buf[N + a][li - 1]; aR[a] = buf[N + a][li + 1]; }
+                for (int a = 0; a < AA; ++a) { aL[a] = 0.0; aR[a] = 0.0; }
+#pragma unroll
+                for (int j = 0; j < AP; ++j) {
+                    aL[PlaneAux<Ph>::idx(j)] = buf[N + j][li - 1];
+                    aR[PlaneAux<Ph>::idx(j)] = buf[N + j][li + 1];
+                }
                 rusanov_pair2<Ph, 0>(ph, qL, aL, qc, ac, qR, aR, acc2);
             }
             {
@@ -258,7 +276,12 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
 #pragma unroll
                 for (int v = 0; v < N; ++v) { qL[v] = buf[v][li - PH]; qR[v] = buf[v][li + PH]; }
 #pragma unroll
-                for (int a = 0; a < A; ++a) { aL[a] = buf[N + a][li - PH]; aR[a] = buf[N + a][li + PH]; }
+                for (int a = 0; a < AA; ++a) { aL[a] = 0.0; aR[a] = 0.0; }
+#pragma unroll
+                for (int j = 0; j < AP; ++j) {
+                    aL[PlaneAux<Ph>::idx(j)] = buf[N + j][li - PH];
+                    aR[PlaneAux<Ph>::idx(j)] = buf[N + j][li + PH];
+                }
                 rusanov_pair2<Ph, 1>(ph, qL, aL, qc, ac, qR, aR, acc2);
             }
         }
