@@ -28,6 +28,7 @@
 namespace pb {
 
 constexpr int kReduceSpan = 256;    // units per work-group of the first reduction stage
+constexpr int kReduceOne = 8192;    // up to this many units the single-work-group reduction runs alone
 
 namespace {
 
@@ -749,8 +750,10 @@ __global__ __launch_bounds__(kFvThreads) void fv_lambda_kernel(const T *__restri
 // dt = cfl / sum_d (Lambda_d / dx_min), written to ctrl->dt[slot].  With
 // stats, rows 3..7 of the partials (con2prim iterations, failures, largest
 // iteration count, fallbacks, cells) are folded into the control block.
-// One work-group; maxima are exact and the sums are of integers held exactly
-// in doubles, so the result does not depend on the order.
+// One work-group; every thread issues the loads of all rows of a unit
+// together (one memory round trip per unit, not one per row).  Maxima are
+// exact and the sums are of integers held exactly in doubles, so the result
+// does not depend on the order.
 __global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restrict__ part, int n_units, int dim,
                                                          Ctrl *__restrict__ ctrl, int slot, double cfl,
                                                          double dxmin, int want_dt, int want_stats)
@@ -758,19 +761,26 @@ __global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restric
     __shared__ double red[8][1024 / kWave];
     const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
     const int rows = want_stats ? 8 : dim;
-    for (int r = 0; r < rows; ++r) {
-        if (r >= dim && r < 3) continue;
+    // row r is used when r < dim, or r >= 3 with stats; max for rows 0-2 and 5
+    double m[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) m[r] = 0.0;
+    for (int i = t; i < n_units; i += blockDim.x) {
+        double v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) v[r] = (r < rows && !(r >= dim && r < 3)) ? part[(long long)r * n_units + i] : 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) m[r] = (r < 3 || r == 5) ? fmax(m[r], v[r]) : m[r] + v[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
         const bool mx = r < 3 || r == 5;
-        double m = 0.0;
-        for (int i = t; i < n_units; i += blockDim.x) {
-            const double v = part[(long long)r * n_units + i];
-            m = mx ? fmax(m, v) : m + v;
-        }
+        double a = m[r];
         for (int o = 32; o > 0; o >>= 1) {
-            const double u = __shfl_xor(m, o, kWave);
-            m = mx ? fmax(m, u) : m + u;
+            const double u = __shfl_xor(a, o, kWave);
+            a = mx ? fmax(a, u) : a + u;
         }
-        if (lane == 0) red[r][w] = m;
+        if (lane == 0) red[r][w] = a;
     }
     __syncthreads();
     if (t == 0) {
@@ -778,9 +788,9 @@ __global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restric
         for (int r = 0; r < rows; ++r) {
             if (r >= dim && r < 3) continue;
             const bool mx = r < 3 || r == 5;
-            double m = red[r][0];
-            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = mx ? fmax(m, red[r][i]) : m + red[r][i];
-            tot[r] = m;
+            double a = red[r][0];
+            for (int i = 1; i < (int)(blockDim.x / kWave); ++i) a = mx ? fmax(a, red[r][i]) : a + red[r][i];
+            tot[r] = a;
         }
         if (want_dt) {
             double den = 0.0;
@@ -1012,7 +1022,7 @@ pb_status launch_dt_reduce(pb_batch *b, const double *part, int n_units, int dim
 {
     if (!want_dt && !want_stats) return PB_OK;
     const int rows = want_stats ? 8 : dim;
-    if (n_units > kReduceSpan) {
+    if (n_units > kReduceOne) {
         // first stage: one work-group per kReduceSpan units, partials of the
         // partials into the tail of the partial buffer
         const int g = (n_units + kReduceSpan - 1) / kReduceSpan;
