@@ -383,16 +383,22 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
 // one work-group barrier per step.  With c = s + j the chunk j steps ahead:
 //   producers, step s: gradients and dissipation of chunk s + 1 (LDS slot
 //     (s+1) % 2); footprint of chunk s + 2 into LDS from registers, then the
-//     global loads of chunk s + 4 into those registers; the stage-update
-//     operands (Q^0 and accumulator rows) of chunk s + 1 into their LDS ring
-//     slot from registers, then the loads of chunk s + 3;
+//     global loads of chunk s + 4 into those registers; the stage results
+//     held in the ring slot of chunk s + 1 (those of chunk s + 1 - R) out to
+//     HBM, then the stage-update operands (Q^0 and accumulator rows) of
+//     chunk s + 1 into that slot from registers, then the loads of chunk
+//     s + 3;
 //   consumers, step s: matrix-core product of chunk s (slot s % 2) and, at
-//     the last chunk of a tile, the stage update from the LDS operand ring.
+//     the last chunk of a tile, the stage update from the LDS operand ring,
+//     whose results replace the operands in the ring (no consumer touches
+//     HBM after the start).
 // Every copy goes HBM/L2 -> registers -> LDS with ordinary loads issued two
 // steps before the data is needed, so the compiler tracks each load by its
 // registers and the copies overlap the arithmetic.  The operand ring has one
 // slot more than a tile has chunks: a slot is written one step before its
-// chunk and read at the tile's last step, and is rewritten only after that.
+// chunk, read and overwritten with the results at the tile's last step, and
+// its results go out to HBM right before it is refilled, at least one step
+// later (those of the last tile after the last step).
 // Indexes past the last step are clamped to it (that chunk is loaded,
 // written and differentiated again and nobody reads the result), except the
 // operand ring, which is not written past the last chunk.
@@ -449,6 +455,7 @@ struct WsLds {
 template <int NCH>
 __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restrict__ y,
                                             const double *__restrict__ srcq, const double *__restrict__ srca,
+                                            double *__restrict__ acc, double *__restrict__ ynext, bool write_y,
                                             const WsItem *__restrict__ items, int slot, int G, int S, int N,
                                             double sigma)
 {
@@ -470,10 +477,10 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
     const int ux = uc % kT, uy = (uc / kT) % kT, uz = uc / (kT * kT);
     const double *__restrict__ usrc = us ? srca : srcq;
     // tile caches of the three cursors (footprint loads, gradients, operand loads)
-    int kf = -1, kg = -1, ku = -1;
+    int kf = -1, kg = -1, ku = -1, ko = -1;
     TileSrc fsrc{};
     double inv_dx = 0.0;
-    long long ubase = 0, uC = 0;
+    long long ubase = 0, uC = 0, obase = 0, oC = 0;
 
     auto load_foot = [&](int c, f64x2_t (&F)[3]) {
         c = c < S ? c : S - 1;
@@ -506,6 +513,26 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
     };
     auto stage_upd = [&](int c, const f64x2_t &U) {
         if (c < S) *reinterpret_cast<f64x2_t *>(&L.u[c % R][us][uv][uc]) = U;
+    };
+    // the stage results of chunk c (written into its ring slot by the
+    // consumers at the tile's last step) to HBM: new accumulator (side 0)
+    // and next stage value (side 1, where the stage has one)
+    auto store_out = [&](int c) {
+        if (c < 0) return;
+        const int k = c / NCH, ch = c - k * NCH;
+        if (k != ko) {
+            ko = k;
+            const WsItem T = items[slot + k * G];
+            const int p = T.p;
+            oC = (long long)p * p * p;
+            obase = T.off * N + ((long long)(T.tz + uz) * p + (T.ty + uy)) * p + (T.tx + ux);
+        }
+        const int v = ch * kCh + uv;
+        if (v < N && (us == 0 || write_y)) {
+            const f64x2_t r = *reinterpret_cast<const f64x2_t *>(&L.u[c % R][us][uv][uc]);
+            double *dst = us ? ynext : acc;
+            *reinterpret_cast<f64x2_t *>(dst + obase + (long long)v * oC) = r;
+        }
     };
     auto grad = [&](int c) {
         c = c < S ? c : S - 1;
@@ -564,10 +591,13 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
     stage_upd(0, UA);
     UA = load_upd(2);
     lds_barrier();
+    // each step first writes out the results held in the ring slot it is
+    // about to refill (chunk c - R, whose tile ended at least one step ago)
     for (int s = 0; s < S; s += 2) {
         grad(s + 1);
         stage_foot(0, FA);
         load_foot(s + 4, FA);
+        store_out(s + 1 - R);
         stage_upd(s + 1, UB);
         UB = load_upd(s + 3);
         lds_barrier();
@@ -575,17 +605,20 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
         grad(s + 2);
         stage_foot(1, FB);
         load_foot(s + 5, FB);
+        store_out(s + 2 - R);
         stage_upd(s + 2, UA);
         UA = load_upd(s + 4);
         lds_barrier();
     }
+    // the last tile's results (its update ran at the final step, before the
+    // last barrier)
+    for (int c = S - NCH > 0 ? S - NCH : 0; c < S; ++c) store_out(c);
 }
 
 // consumer waves: -sum_d B_d G_d on the matrix cores and the stage update
 template <int NCH>
-__device__ __forceinline__ void ws_consumer(const WsLds<NCH> &L, double *__restrict__ ynext,
-                                            double *__restrict__ acc, const WsItem *__restrict__ items,
-                                            int slot, int G, int n_my,
+__device__ __forceinline__ void ws_consumer(WsLds<NCH> &L, const WsItem *__restrict__ items, int slot, int G,
+                                            int n_my,
                                             const double *__restrict__ Bmat, int N, int stage, int rk, double dt)
 {
     constexpr int R = WsLds<NCH>::R;
@@ -607,15 +640,13 @@ __device__ __forceinline__ void ws_consumer(const WsLds<NCH> &L, double *__restr
     //   acc <- (Q^0-side) + ca R,   ynext <- Q^0 + cy R (stages 1-3 of RK4);
     // the operand ring holds Q^0 (or, where a stage needs no Q^0, the
     // accumulator) on one side and the accumulator (or Q^0) on the other
-    const bool from_q0 = !(rk == 4 && stage > 0), write_y = rk == 4 && stage < 3;
+    const bool from_q0 = !(rk == 4 && stage > 0);
     const double ca = rk == 1 ? dt : ((stage == 0 || stage == 3) ? dt / 6.0 : dt / 3.0);
     const double cy = stage == 2 ? dt : 0.5 * dt;
     lds_barrier();
     lds_barrier();
     int s = 0;
     for (int kt = 0; kt < n_my; ++kt) {
-        // the tile's geometry, fetched now for the update at its last chunk
-        const WsItem T = items[slot + kt * G];
         f64x4_t accm[4];
 #pragma unroll
         for (int nt = 0; nt < 4; ++nt) accm[nt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
@@ -643,28 +674,25 @@ __device__ __forceinline__ void ws_consumer(const WsLds<NCH> &L, double *__restr
             }
             if (ch == NCH - 1) {
                 // element (nt, i) of this lane: unknown r = 16 w + lg + 4 i,
-                // cell nt * 16 + lj = (x, y, z) = (lj % 4, lj / 4, nt) of the
-                // tile; both addresses are a lane base plus uniform offsets
-                const int p = T.p;
-                const long long C = (long long)p * p * p, pp = (long long)p * p;
-                const long long gl = T.off * N + ((long long)T.tz * p + T.ty + lj / kT) * p + T.tx + lj % kT +
-                                     (long long)(16 * w + lg) * C;
-                const double *ul = &L.u[0][0][lg][lj];
+                // cell nt * 16 + lj of the tile.  The results replace the
+                // operands in the ring slot (the producers write them to HBM
+                // over the next tile's steps); rows at or beyond N are
+                // skipped (beyond the last chunk a row would alias one of it)
+                double *ul = &L.u[0][0][lg][lj];
                 const int c0 = s - ch;   // global index of the tile's first chunk
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     // operand ring slot of unknown row r (its chunk is 2 w + i / 2)
                     const int rc = 2 * w + i / 2 < NCH ? 2 * w + i / 2 : NCH - 1;
-                    const double *ui = ul + ((c0 + rc) % R) * (2 * kCh * kTC) + 4 * (i % 2) * kTC;
+                    double *ui = ul + ((c0 + rc) % R) * (2 * kCh * kTC) + 4 * (i % 2) * kTC;
                     const bool live = 16 * w + lg + 4 * i < N;
 #pragma unroll
                     for (int nt = 0; nt < 4; ++nt) {
                         const double R0 = accm[nt][i], qv = ui[nt * 16], av = ui[kCh * kTC + nt * 16];
                         const double an = (from_q0 ? qv : av) + ca * R0, yn = qv + cy * R0;
                         if (live) {
-                            const long long g = gl + nt * pp + 4 * i * C;
-                            acc[g] = an;
-                            if (write_y) ynext[g] = yn;
+                            ui[nt * 16] = an;
+                            ui[kCh * kTC + nt * 16] = yn;
                         }
                     }
                 }
@@ -690,9 +718,10 @@ __global__ __launch_bounds__(kWsThreads) void fd_stage_ws_kernel(
         // the stage's update operands: Q^0 and the accumulator where it needs
         // both, else the one it needs on both sides
         const bool need_q0 = rk == 1 || stage < 3, need_acc = rk == 4 && stage > 0;
-        ws_producer<NCH>(L, y, need_q0 ? q0 : acc, need_acc ? acc : q0, items, slot, G, n_my * NCH, N, sigma);
+        ws_producer<NCH>(L, y, need_q0 ? q0 : acc, need_acc ? acc : q0, acc, ynext, rk == 4 && stage < 3, items,
+                         slot, G, n_my * NCH, N, sigma);
     } else {
-        ws_consumer<NCH>(L, ynext, acc, items, slot, G, n_my, Bmat, N, stage, rk, dt);
+        ws_consumer<NCH>(L, items, slot, G, n_my, Bmat, N, stage, rk, dt);
     }
 }
 
