@@ -125,23 +125,47 @@ def test_wave_specialised_kernel_matches(N):
     """The wave-specialised stage kernel (the default) against the oracle and,
     bitwise, against the kernel in which every wave does every phase, for
     every number of 8-unknown chunks (1..8, N not a multiple of 4 or 8
-    included), on 5 uneven patches (fewer tiles than CUs, so most
+    included), with and without the XCD-grouped tile order, on 5 uneven
+    patches (fewer tiles than CUs, so most
     work-groups own one tile and the pipeline runs past its last step)."""
     announce(f"fd wave-specialised N={N}")
     need_gpu()
     b = I.config2(n_patches=5, N=N, sizes=np.array([8, 4, 16, 4, 8], np.int32))
     out = {}
-    for ws in (1, 0):
+    for ws, remap in ((1, 1), (1, 0), (0, 1)):
         B = pb.PatchBatch(b)
-        B.set_tuning(fd_ws=ws)
+        B.set_tuning(fd_ws=ws, fd_xcd_remap=remap)
         assert B.get_tuning()["fd_ws"] == ws
         B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
         B.fd_ko_step(cfl=0.5, dt_fixed=1e-3, sigma_ko=0.05, rk_stages=1, n_steps=1)
-        out[ws] = B.download()
+        out[(ws, remap)] = B.download()
         B.close()
-    np.testing.assert_array_equal(out[1], out[0])
+    np.testing.assert_array_equal(out[(1, 1)], out[(0, 1)])
+    np.testing.assert_array_equal(out[(1, 0)], out[(0, 1)])
+    out[1] = out[(1, 1)]
     o, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
     b2 = b.copy()
     b2.state = o
     o2, _ = oracle.fd_step(b2, dt_fixed=1e-3, sigma=0.05, rk_stages=1, n_steps=1)
     assert np.all(rel_err(b, out[1], o2) <= 1e-12)
+
+
+def test_graph_replays_match_eager():
+    """Three steps captured in a HIP graph and replayed three times, with the
+    program's own eager work and synchronisations between the replays: every
+    replay equals the same steps run eagerly, bitwise (wave-specialised
+    kernel, uneven patches, N = 58; the eager steps are held to the oracle by
+    the parity tests above)."""
+    announce("fd graph replays")
+    torch = need_gpu()
+    b = I.config2(n_patches=6, N=58, sizes=np.array([16, 4, 8, 8, 4, 16], np.int32))
+    eager = pb.PatchBatch(b)
+    graph = pb.PatchBatch(b)
+    for rep in range(3):
+        eager.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=3)
+        graph.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=3, use_graph=True)
+        torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(graph.download(), eager.download())
+    eager.close()
+    graph.close()
