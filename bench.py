@@ -399,7 +399,7 @@ def main():
     ap.add_argument("--save-tuning", default=None, help="write the autotuner cache here at the end")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; there is no multi-GPU path (--gpus must be 1)"}))
+        print(json.dumps({"error": "bench.py runs on one GPU; there is no multi-GPU path (--gpus must be 1)"}))
         sys.exit(2)
 
     import torch

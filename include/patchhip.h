@@ -53,7 +53,7 @@ typedef enum {
     PB_EINVAL = -1,        /* bad argument; nothing was enqueued */
     PB_ENOMEM = -2,        /* a library-owned allocation failed */
     PB_EHIP = -3,          /* a HIP runtime call failed (text in pb_last_error) */
-    PB_EUNSUPPORTED = -4,  /* valid request this build does not implement */
+    PB_EUNSUPPORTED = -4,  /* valid request the library does not implement */
 } pb_status;
 
 typedef enum {
