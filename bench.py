@@ -347,6 +347,24 @@ def bench_adv_var(torch, pb, I, steps, warmup):
             "hbm_frac": cells * 64 / avg_s / 1e9 / HBM_PEAK_GBS, "nonfinite_units": st["nonfinite_units"]}
 
 
+def newton_distribution(torch, pb, B, b, guess, net):
+    """Newton iteration counts per cell on the batch's current state through
+    the con2prim entry point with the same guess (outside any timed region):
+    mean, p99, max, and the per-wave maximum (64 consecutive cells of a
+    patch, the lanes of one wave of the con2prim pass), which sets a wave's
+    cost"""
+    import numpy as np
+    K, c3 = int(b.p.size), int(b.p[0]) ** 3
+    cons = B.current().view(K, 5, c3).permute(1, 0, 2).contiguous().view(5, -1)
+    prim = torch.empty_like(cons)
+    it = torch.empty(cons.shape[1], dtype=torch.int32, device=cons.device)
+    pb.con2prim(cons, prim, guess=guess, mlp=net if guess == "learned" else None, iters=it)
+    a = it.cpu().numpy().astype(np.int64)
+    wave = a.reshape(-1, 64).max(axis=1)
+    return {"cells": int(a.size), "mean": float(a.mean()), "p99": float(np.percentile(a, 99)), "max": int(a.max()),
+            "per_wave_max_mean": float(wave.mean()), "per_wave_max_p99": float(np.percentile(wave, 99))}
+
+
 def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     from paper_2608_19273_amd import mlp_train
     log("config-3 IC (SRHD, 2048 x 16^3)")
@@ -369,6 +387,7 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
         st0 = B.stats()
         el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.4, n_steps=steps))
         st = B.stats()
+        dist = newton_distribution(torch, pb, B, b, guess, net) if guess != "warm" else None
         B.close()
         solves = st["c2p_cells"] - st0["c2p_cells"]
         res[guess] = {"cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
@@ -376,6 +395,8 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
                       "newton_iterations_max": st["c2p_max_iterations"],
                       "c2p_failures": st["c2p_failures"] - st0["c2p_failures"],
                       "fallbacks": st["c2p_fallbacks"] - st0["c2p_fallbacks"], "autotune": tuned}
+        if dist is not None:
+            res[guess]["newton_distribution_final_state"] = dist
     res["learned_over_plain_speedup"] = res["learned"]["cell_updates_per_s"] / res["plain"]["cell_updates_per_s"]
     net.close()
     return res
