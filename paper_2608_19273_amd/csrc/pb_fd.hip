@@ -380,7 +380,8 @@ __global__ __launch_bounds__(kFdThreads, 2) void fd_stage_kernel(
 // rows of -B_d in registers and run only the dense product and the stage
 // update; waves 4..11 (producers) move data and compute the gradients.  Both
 // roles advance in lock step over the same sequence of (tile, chunk) steps,
-// one work-group barrier per step.  With c = s + j the chunk j steps ahead:
+// one work-group barrier per step (R = chunks per tile + 1 is the size of
+// the operand ring below):
 //   producers, step s: gradients and dissipation of chunk s + 1 (LDS slot
 //     (s+1) % 2); footprint of chunk s + 2 into LDS from registers, then the
 //     global loads of chunk s + 4 into those registers; the stage results
