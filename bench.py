@@ -105,6 +105,35 @@ def cpu_baseline(target_s: float):
                       f"{steps} steps, {el:.1f} s, single thread"}
 
 
+def cpu_oracle_sample(kind: str, target_s: float):
+    """The oracle (single-threaded FP64 C) on a bounded sample of a further
+    workload, for context beside its GPU rate: the linear system on one 4^3,
+    two 8^3 and one 16^3 patch of the uneven batch (its 1:2:1 size mix), SRHD
+    on 2 x 2 x 1 patches of 16^3 with the same primitive recipe."""
+    import oracle
+    from paper_2608_19273_amd import inputs as I
+    if kind == "linsym":
+        b = I.config2(subset=I.config2_subset(n_per_size=(1, 2, 1)))
+        step = lambda q: oracle.fd_step(b, q, cfl=0.5, sigma=0.1, n_steps=1)[0]
+        unit, what = "cell-steps/s", "FD4 + KO6 + RK4 steps of the 58-unknown linear system"
+    else:
+        b = I.config3(grid=(2, 2, 1))
+        step = lambda q: oracle.fv_step(b, q, cfl=0.4, n_steps=1)[0]
+        unit, what = "cell-updates/s", "SRHD Rusanov FV steps with plain-guess con2prim"
+    q = b.state
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        q = step(q)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s or steps >= 1000:
+            break
+    return {"value": b.total_cells * steps / el, "unit": unit, "cores": 1, "kind": "oracle",
+            "sample": f"{what} on {b.p.size} patches ({b.total_cells} cells), {steps} steps, {el:.1f} s, "
+                      f"single thread"}
+
+
 def attainable_copy(torch, pb):
     """the library's streaming copy, 512 MiB read + 512 MiB written per launch"""
     src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
@@ -405,8 +434,8 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
@@ -492,7 +521,9 @@ def main():
             wl["euler3d_fd4_rk4"] = bench_fd_euler(torch, pb, I, max(2, args.steps // 4), 1)
         if "srhd" in want:
             log("SRHD plain / warm / learned con2prim")
-            wl["srhd"] = bench_srhd(torch, pb, I, max(2, args.steps // 2), args.mlp_epochs, args.mlp_pairs)
+            # 10 steps per guess (the configuration's step count): longer runs smooth
+            # the i.i.d. initial state and change the Newton workload being compared
+            wl["srhd"] = bench_srhd(torch, pb, I, min(10, args.steps), args.mlp_epochs, args.mlp_pairs)
         if "ksweep" in want:
             log("K sweep: runtime per cell against the batch size, p in {3, 6, 16}, FV and FD4")
             wl["k_sweep"] = bench_ksweep(torch, pb, I)
@@ -506,6 +537,11 @@ def main():
     if not args.no_cpu:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        wl = result.get("workloads", {})
+        for kind, key in (("linsym", "linsym58_fd4_rk4"), ("srhd", "srhd")):
+            if key in wl:
+                log(f"timing the CPU oracle on a {kind} sample")
+                wl[key]["cpu_oracle"] = cpu_oracle_sample(kind, 6.0)
     print(json.dumps(result), flush=True)
 
 
