@@ -276,8 +276,11 @@ pb_status pb_mlp_train_step(pb_mlp *m, const void *x, const void *t, int64_t n, 
 
 /* ---------------------------------------------------------- measurement -- */
 
-/* on != 0: record a HIP event pair on the batch stream around every step
- * kernel launch (FV step kernel; FD stage kernel) of later eager calls. */
+/* on != 0: time every step kernel launch (FV step kernel; FD stage kernel)
+ * of later eager calls by a HIP event pair that the kernel's own dispatch sets
+ * to its start and end (the dt reduction and launch gaps are not included).
+ * Step calls with use_graph != 0 fail with PB_EINVAL while it is on; on == 0
+ * stops it and drops what was recorded. */
 pb_status pb_batch_profile(pb_batch *b, int32_t on);
 /* Sum of the recorded launch durations (ms) and the number of launches since
  * the last read; synchronises the batch stream and clears the record. */

@@ -151,6 +151,22 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
     return PB_OK;
 }
 
+// profiling: hand the next pair of events to the next main-kernel launch
+// (launch_main), then count it once the launch has been enqueued
+static void arm_events(pb_batch *b)
+{
+    if (!b->profiling) return;
+    b->kev[0] = b->prof_ev[0][b->prof_n];
+    b->kev[1] = b->prof_ev[1][b->prof_n];
+}
+
+static pb_status disarm_events(pb_batch *b, pb_status st)
+{
+    if (b->kev[0] && st == PB_OK) ++b->prof_n;
+    b->kev[0] = b->kev[1] = nullptr;
+    return st;
+}
+
 // enqueue n FV steps on stream s starting from buffer `cur`; returns the new cur
 static pb_status enqueue_fv(pb_batch *b, double cfl, double dt_fixed, int n, hipStream_t s, int *cur_io)
 {
@@ -163,10 +179,9 @@ static pb_status enqueue_fv(pb_batch *b, double cfl, double dt_fixed, int n, hip
         const int slot = i & 1;
         if (b->pde == PB_PDE_SRHD)
             if ((st = launch_srhd_c2p(b, b->state[cur], slot, cfl_mode, cfl, s)) != PB_OK) return st;
-        if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
-        if ((st = launch_fv_step(b, b->state[cur], b->state[cur ^ 1], slot, dt_fixed, cfl, s)) != PB_OK)
-            return st;
-        if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
+        arm_events(b);
+        st = disarm_events(b, launch_fv_step(b, b->state[cur], b->state[cur ^ 1], slot, dt_fixed, cfl, s));
+        if (st != PB_OK) return st;
         cur ^= 1;
     }
     *cur_io = cur;
@@ -201,11 +216,10 @@ static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sig
             void *ys[4] = {q0, yA, yB, yA};
             void *yn[4] = {yA, yB, yA, nullptr};
             for (int sg = 0; sg < (rk == 1 ? 1 : 4); ++sg) {
-                if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
-                if ((st = launch_fd_euler_stage(b, sg, rk, q0, ys[sg], rk == 1 ? nullptr : yn[sg], acc, slot,
-                                                dt_fixed, cfl, sigma, s)) != PB_OK)
-                    return st;
-                if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
+                arm_events(b);
+                st = disarm_events(b, launch_fd_euler_stage(b, sg, rk, q0, ys[sg], rk == 1 ? nullptr : yn[sg], acc,
+                                                            slot, dt_fixed, cfl, sigma, s));
+                if (st != PB_OK) return st;
             }
             cur ^= 1;
         }
@@ -216,18 +230,17 @@ static pb_status enqueue_fd(pb_batch *b, double cfl, double dt_fixed, double sig
     for (int i = 0; i < n; ++i) {
         void *q0 = b->state[cur], *acc = b->state[cur ^ 1];
         if (rk == 1) {
-            if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
-            if ((st = launch_fd_stage(b, 0, 1, q0, q0, nullptr, acc, dt, sigma, s)) != PB_OK) return st;
-            if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
+            arm_events(b);
+            st = disarm_events(b, launch_fd_stage(b, 0, 1, q0, q0, nullptr, acc, dt, sigma, s));
+            if (st != PB_OK) return st;
         } else {
             // stage 1 reads Q^n, stages 2-4 read the previous stage value
             void *ys[4] = {q0, yA, yB, yA};
             void *yn[4] = {yA, yB, yA, nullptr};
             for (int sg = 0; sg < 4; ++sg) {
-                if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[0][b->prof_n], s));
-                if ((st = launch_fd_stage(b, sg, 4, q0, ys[sg], yn[sg], acc, dt, sigma, s)) != PB_OK)
-                    return st;
-                if (b->profiling) PB_HIP(hipEventRecord(b->prof_ev[1][b->prof_n++], s));
+                arm_events(b);
+                st = disarm_events(b, launch_fd_stage(b, sg, 4, q0, ys[sg], yn[sg], acc, dt, sigma, s));
+                if (st != PB_OK) return st;
             }
         }
         cur ^= 1;

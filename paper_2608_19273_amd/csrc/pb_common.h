@@ -3,11 +3,13 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cstdint>
 #include <exception>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/patchhip.h"
@@ -203,6 +205,9 @@ struct pb_batch {
     bool profiling = false;
     int prof_n = 0;
     std::vector<hipEvent_t> prof_ev[2];
+    // events the next main-kernel launch sets from its own start and end
+    // (null when not profiling)
+    hipEvent_t kev[2] = {nullptr, nullptr};
 };
 
 namespace pb {
@@ -223,6 +228,26 @@ inline bool fd_buffers(int pde, int dim, int h)
 WsLayout ws_layout(int pde, int dim, int h, long long total_cells, int N, int storage, int K);
 // largest number of work units any launch uses (partials are sized for it)
 inline long long max_units(int K) { return (long long)K * kFvPmax; }
+
+// launches a step's main kernel (the FV step, an FD stage) with its arguments
+// converted to the kernel's parameter types; when the batch is profiling, the
+// dispatch itself sets the two events to its start and end
+// (hipExtLaunchKernel), so their elapsed time is the kernel alone, without the
+// launch gap or the dt reduction that may follow it on the stream
+template <typename... P, typename... Args>
+inline void launch_main(const pb_batch *b, void (*kern)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s,
+                        Args... args)
+{
+    static_assert(sizeof...(P) == sizeof...(Args), "kernel argument count");
+    std::tuple<P...> a{static_cast<P>(args)...};
+    void *ptrs[sizeof...(P)];
+    std::apply([&ptrs](auto &...x) { int i = 0; ((ptrs[i++] = static_cast<void *>(&x)), ...); }, a);
+    if (b->kev[0])
+        (void)hipExtLaunchKernel(reinterpret_cast<const void *>(kern), grid, block, ptrs, lds, s, b->kev[0],
+                                 b->kev[1], 0);
+    else
+        (void)hipLaunchKernel(reinterpret_cast<const void *>(kern), grid, block, ptrs, lds, s);
+}
 
 // launchers (implemented in the kernel translation units)
 pb_status launch_fv_lambda(pb_batch *b, const void *q, double cfl, hipStream_t s);

@@ -776,7 +776,7 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
         const int grid = std::max(1, std::min(b->fd_n_items, cus));
         const int nch = (b->N + kCh - 1) / kCh;
         auto go = [&](auto kern) {
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(kWsThreads), 0, s, static_cast<const double *>(y),
+            launch_main(b, kern, dim3(grid), dim3(kWsThreads), 0, s, static_cast<const double *>(y),
                                static_cast<const double *>(q0), static_cast<double *>(ynext),
                                static_cast<double *>(acc), reinterpret_cast<const WsItem *>(b->d_fd_ws_items),
                                b->fd_n_items, b->d_fd_B, b->N, stage, rk_stages, dt, sigma, b->fd_xcd_remap);
@@ -795,7 +795,7 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
         return PB_OK;
     }
     const int grid = std::max(1, std::min(b->fd_n_items, cus * b->fd_wg_per_cu));
-    hipLaunchKernelGGL(fd_stage_kernel, dim3(grid), dim3(kFdThreads), 0, s, static_cast<const double *>(y),
+    launch_main(b, fd_stage_kernel, dim3(grid), dim3(kFdThreads), 0, s, static_cast<const double *>(y),
                        static_cast<const double *>(q0), static_cast<double *>(ynext), static_cast<double *>(acc),
                        b->d_patches, reinterpret_cast<const FdItem *>(b->d_fd_items), b->fd_n_items,
                        b->d_fd_B, b->N, stage, rk_stages, dt, sigma, b->fd_xcd_remap);

@@ -502,10 +502,10 @@ void launch_s(dim3 g, hipStream_t s, const double *y, const double *q0, double *
     if (G > 0) {
         const int p = b->p[0];
         const size_t lds = (size_t)kSmallW * G * (p * p * p + 18 * p * p) * sizeof(double);
-        hipLaunchKernelGGL((fd_euler_small_kernel<S, kLam>), g, dim3(kFvThreads), lds, s, y, q0, yn, acc,
+        launch_main(b, fd_euler_small_kernel<S, kLam>, g, dim3(kFvThreads), lds, s, y, q0, yn, acc,
                            b->d_patches, b->K, p, G, ctrl, part, slot, dt_fixed, b->params[0], sigma);
     } else {
-        hipLaunchKernelGGL((fd_euler_stage_kernel<S, kLam>), g, dim3(kFvThreads), 0, s, y, q0, yn, acc, b->d_patches,
+        launch_main(b, fd_euler_stage_kernel<S, kLam>, g, dim3(kFvThreads), 0, s, y, q0, yn, acc, b->d_patches,
                            n_units, n_slabs, slab, b->fd_xcd_remap, ctrl, part, slot, dt_fixed, b->params[0], sigma);
     }
 }

@@ -876,10 +876,10 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
         const size_t lds = (size_t)(Ph::N + Ph::A) * G * (p + 2) * (p + 2) * (p + 2) * sizeof(double);
         const bool lam = !(dt_fixed > 0.0) && Ph::E == 0;
         if (lam)
-            hipLaunchKernelGGL((fv_small_kernel<Ph, T, true>), dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
+            launch_main(b, fv_small_kernel<Ph, T, true>, dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
                                b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, ph);
         else
-            hipLaunchKernelGGL((fv_small_kernel<Ph, T, false>), dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
+            launch_main(b, fv_small_kernel<Ph, T, false>, dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
                                b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, ph);
         PB_HIP(hipGetLastError());
         if (lam) return launch_dt_reduce(b, part, nwg, DIM, slot_in ^ 1, cfl, true, false, s);
@@ -887,25 +887,25 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
       }
     }
     if constexpr (Ph::E > 0) {  // SRHD: dt comes from the con2prim pass
-        hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
+        launch_main(b, fv_step_kernel<Ph, DIM, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                            ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
                            slot_in, dt_fixed, ph);
     } else if (DIM == 3 && b->fv_dma && fv_dma_eligible(b)) {
         if (dt_fixed > 0.0)
-            hipLaunchKernelGGL((fv_step_dma_kernel<Ph, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
+            launch_main(b, fv_step_dma_kernel<Ph, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                                b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part, slot_in, dt_fixed,
                                ph);
         else
-            hipLaunchKernelGGL((fv_step_dma_kernel<Ph, T, true>), dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
+            launch_main(b, fv_step_dma_kernel<Ph, T, true>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                                b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part, slot_in, dt_fixed,
                                ph);
     } else {
         if (dt_fixed > 0.0)
-            hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, false>), dim3(n_units), dim3(kFvThreads), 0, s, qi,
+            launch_main(b, fv_step_kernel<Ph, DIM, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi,
                                qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
                                slot_in, dt_fixed, ph);
         else
-            hipLaunchKernelGGL((fv_step_kernel<Ph, DIM, T, true>), dim3(n_units), dim3(kFvThreads), 0, s, qi,
+            launch_main(b, fv_step_kernel<Ph, DIM, T, true>, dim3(n_units), dim3(kFvThreads), 0, s, qi,
                                qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
                                slot_in, dt_fixed, ph);
     }

@@ -1,0 +1,74 @@
+"""Per-launch timing of the step kernels (pb_batch_profile): one timed launch
+per FV step and per FD stage, each timed by the kernel's own dispatch (so the
+sum stays below the wall-clock time of the steps, which also holds the dt
+reductions and launch gaps), results bitwise equal to an unprofiled run, and
+profiling refused in graph mode."""
+import time
+
+import numpy as np
+import pytest
+
+import paper_2608_19273_amd as pb
+from paper_2608_19273_amd import inputs as I
+
+from gpu_helpers import announce, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def fv(B, n):
+    B.fv_rusanov_step(cfl=0.4, n_steps=n)
+
+
+def fd(B, n):
+    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n)
+
+
+CASES = {
+    "fv-euler3d": (lambda: I.config1(grid=(4, 4, 2)), fv, 1),
+    "fv-srhd": (lambda: I.config3(grid=(2, 2, 2)), fv, 1),
+    "fd-linsym": (lambda: I.config2(n_patches=64, N=20), fd, 4),
+    "fd-euler3d": (lambda: I.config1(grid=(4, 4, 2), halo=3), fd, 4),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_profile_times_each_main_kernel(case):
+    announce(f"profile {case}")
+    torch = need_gpu()
+    make, step, per_step = CASES[case]
+    b = make()
+    R = pb.PatchBatch(b)
+    step(R, 6)
+    ref = R.download()
+    R.close()
+    B = pb.PatchBatch(b)
+    step(B, 1)
+    torch.cuda.synchronize()
+    B.profile(True)
+    t0 = time.perf_counter()
+    step(B, 5)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms, launches = B.profile_read()
+    B.profile(False)
+    again_ms, again_n = B.profile_read()
+    g = B.download()
+    B.close()
+    assert launches == 5 * per_step
+    assert 0.0 < ms < wall_ms, (ms, wall_ms)
+    assert again_n == 0 and again_ms == 0.0
+    np.testing.assert_array_equal(g, ref)
+
+
+def test_profile_refused_in_graph_mode():
+    announce("profile + graph refused")
+    need_gpu()
+    b = I.config1(grid=(2, 2, 1))
+    B = pb.PatchBatch(b)
+    B.profile(True)
+    with pytest.raises(pb.PbError, match="eager"):
+        B.fv_rusanov_step(cfl=0.4, n_steps=2, use_graph=True)
+    B.profile(False)
+    B.fv_rusanov_step(cfl=0.4, n_steps=2, use_graph=True)
+    B.close()
