@@ -3,6 +3,7 @@ closed forms, invariants, exact solutions and brute force on tiny inputs.
 
 Each test names the part of the oracle a plausible mistake would break."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -271,6 +272,31 @@ def _sod(nx_patch, p=8, T=0.2):
     sel = x < 1.0
     ex = exact_riemann.sample((x[sel] - 0.5) / T, 1.0, 0.0, 1.0, 0.125, 0.0, 0.1)[0]
     return np.mean(np.abs(g[sel] - ex))
+
+
+def _printed_tol(tok):
+    """half a unit in the last printed digit of a tabulated value"""
+    dec = len(tok.split(".")[1]) if "." in tok else 0
+    return 0.5 * 10.0 ** (-dec)
+
+
+def test_exact_riemann_matches_published_star_states():
+    """The exact Riemann solver that the Sod pin below compares the oracle
+    with reproduces the star states of Toro's five tests (tests/golden), each
+    value to half a unit of its printed last digit or 1e-5 relative (test 5
+    starts from rounded inputs): p*, u* from the pressure iteration, and the
+    densities on both sides of the contact from the sampled solution."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "toro_riemann_star_states.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 5
+    for r in rows:
+        left_right = [float(x) for x in r[1:7]]
+        ps, us = exact_riemann.star_state(*left_right)
+        o = np.asarray(exact_riemann.sample(np.array([us - 1e-9, us + 1e-9]), *left_right))
+        got = (ps, us, o[0][0], o[0][1])
+        for g, tok in zip(got, r[7:11]):
+            want = float(tok)
+            assert abs(g - want) <= max(_printed_tol(tok), 1e-5 * abs(want)), (r[0], tok, g)
 
 
 @pytest.mark.slow
