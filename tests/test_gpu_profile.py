@@ -24,11 +24,20 @@ def fd(B, n):
     B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n)
 
 
+def fd_rk1(B, n):
+    B.fd_ko_step(dt_fixed=1e-3, sigma_ko=0.1, rk_stages=1, n_steps=n)
+
+
+# the plane-march kernels (16^3 patches), the whole-patch kernels of small
+# patches (4^3), both FD kernels, and forward Euler (one launch per step)
 CASES = {
     "fv-euler3d": (lambda: I.config1(grid=(4, 4, 2)), fv, 1),
+    "fv-euler3d-p4": (lambda: I.config1(grid=(4, 4, 2), p=4), fv, 1),
     "fv-srhd": (lambda: I.config3(grid=(2, 2, 2)), fv, 1),
     "fd-linsym": (lambda: I.config2(n_patches=64, N=20), fd, 4),
+    "fd-linsym-rk1": (lambda: I.config2(n_patches=64, N=20), fd_rk1, 1),
     "fd-euler3d": (lambda: I.config1(grid=(4, 4, 2), halo=3), fd, 4),
+    "fd-euler3d-p4": (lambda: I.config1(grid=(4, 4, 2), p=4, halo=3), fd, 4),
 }
 
 
