@@ -180,7 +180,7 @@ static pb_status enqueue_fv(pb_batch *b, double cfl, double dt_fixed, int n, hip
         if (b->pde == PB_PDE_SRHD)
             if ((st = launch_srhd_c2p(b, b->state[cur], slot, cfl_mode, cfl, s)) != PB_OK) return st;
         arm_events(b);
-        st = disarm_events(b, launch_fv_step(b, b->state[cur], b->state[cur ^ 1], slot, dt_fixed, cfl, s));
+        st = disarm_events(b, launch_fv_step(b, b->state[cur], b->state[cur ^ 1], slot, i, dt_fixed, cfl, s));
         if (st != PB_OK) return st;
         cur ^= 1;
     }

@@ -42,7 +42,8 @@ struct Ctrl {
     unsigned int c2p_maxit;
     unsigned int pad0;
     double last_dt;
-    unsigned long long pad[19];
+    unsigned long long lmax[3][3];      // FV steps of a call: largest speeds (IEEE bits) by step % 3
+    unsigned long long pad[10];
 };
 static_assert(sizeof(Ctrl) == 256, "Ctrl layout");
 
@@ -129,6 +130,74 @@ __device__ __forceinline__ void store_partial(double *__restrict__ part, const d
         for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[t][i]);
         part[(long long)t * n_units + unit] = m;
     }
+}
+
+// Hand-over of the CFL maxima between the FV steps of one call, with no
+// reduction kernel between them.  Step i of a call (step >= 0) folds the
+// largest speeds of its new state into lmax[i % 3] by atomicMax on the
+// IEEE-754 bit patterns: exact and independent of the order, since the
+// maxima are >= 0 and never NaN (fmax from 0 drops NaN speeds) and such
+// doubles order as their bit patterns.  Step i > 0 takes dt from
+// lmax[(i - 1) % 3] with the reduction kernel's arithmetic
+// (dt = cfl / sum_d Lambda_d / dx_min); its work-group 0 records that dt in
+// ctrl->dt[slot] for the host and clears lmax[(i + 1) % 3] for step i + 1
+// (last written two steps before and last read one step before, by kernels
+// that have finished).  Step 0 reads ctrl->dt[slot], which the reduction at
+// the start of the call writes; that reduction also clears lmax[0].
+// step < 0: the step stores its partials for a reduction kernel instead.
+struct FvChain {
+    int step;
+    double cfl, dxmin;
+};
+
+template <int DIM>
+__device__ __forceinline__ double chain_dt(const Ctrl *ctrl, const FvChain &c)
+{
+    const int r = (c.step + 2) % 3;
+    double den = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) den += __longlong_as_double((long long)ctrl->lmax[r][d]) / c.dxmin;
+    return c.cfl / den;
+}
+
+// the step's dt: fixed, handed over from the previous step of the call, or
+// from the reduction kernel (see FvChain)
+template <int DIM, bool kLam>
+__device__ __forceinline__ double step_dt(Ctrl *ctrl, int slot_in, double dt_fixed, const FvChain &c)
+{
+    if (dt_fixed > 0.0) return dt_fixed;
+    if (kLam && c.step > 0) {
+        const double dt = chain_dt<DIM>(ctrl, c);
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->dt[slot_in] = dt;
+        return dt;
+    }
+    return ctrl->dt[slot_in];
+}
+
+// the largest speeds of a work-group's cells: to the partials (c.step < 0)
+// or folded into the control block (see FvChain)
+template <int DIM>
+__device__ __forceinline__ void fold_speeds(Ctrl *ctrl, double *__restrict__ part, const double *lm, int unit,
+                                            int n_units, const FvChain &c)
+{
+    if (c.step < 0) {
+        store_partial<DIM>(part, lm, unit, n_units);
+        return;
+    }
+    __shared__ double red[3][kFvThreads / kWave];
+    const int t = threadIdx.x, lane = t & (kWave - 1), w = t / kWave;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+        const double m = wave_max(lm[d]);
+        if (lane == 0) red[d][w] = m;
+    }
+    __syncthreads();
+    if (t < DIM) {
+        double m = red[t][0];
+        for (int i = 1; i < (int)(blockDim.x / kWave); ++i) m = fmax(m, red[t][i]);
+        atomicMax(&ctrl->lmax[c.step % 3][t], (unsigned long long)__double_as_longlong(m));
+    }
+    if (blockIdx.x == 0 && t >= kWave && t < kWave + 3) ctrl->lmax[(c.step + 1) % 3][t - kWave] = 0ull;
 }
 
 // Work-group barrier for the LDS exchange only: wait for this wave's LDS
@@ -251,7 +320,7 @@ inline void launch_main(const pb_batch *b, void (*kern)(P...), dim3 grid, dim3 b
 
 // launchers (implemented in the kernel translation units)
 pb_status launch_fv_lambda(pb_batch *b, const void *q, double cfl, hipStream_t s);
-pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, double dt_fixed,
+pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, int step, double dt_fixed,
                          double cfl, hipStream_t s);
 pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt, double cfl,
                           hipStream_t s);

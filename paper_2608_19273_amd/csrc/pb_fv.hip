@@ -140,7 +140,7 @@ template <class Ph, int DIM, typename T, bool kLam>
 __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
     const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
-    Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in, double dt_fixed, Ph ph)
+    Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in, double dt_fixed, FvChain chain, Ph ph)
 {
     constexpr int N = Ph::N, A = Ph::A, AP = PlaneAux<Ph>::n, W = N + AP, AA = A > 0 ? A : 1;
     constexpr int PH = kFvPmax + 2;
@@ -164,7 +164,7 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
     const bool work = z0 < p;
     const bool active = work && t < p * p;
     const int x = active ? t % p : 0, y = active ? t / p : 0;
-    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot_in];
+    const double dt = step_dt<DIM, kLam>(ctrl, slot_in, dt_fixed, chain);
     const double hr_ = 0.5 * dt * P.inv_dx;   // the face sums below are doubled
     const int li = (y + 1) * PH + (x + 1);
 
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
 
     for (int z = z0; z < z1; ++z) plane(z, rnA, hrA);
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
-    if (kLam) store_partial<DIM>(part, lm, unit, n_units);
+    if (kLam) fold_speeds<DIM>(ctrl, part, lm, unit, n_units, chain);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,7 +439,7 @@ template <class Ph, typename T, bool kLam>
 __global__ __launch_bounds__(kFvThreads, 2) void fv_step_dma_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const PatchDev *__restrict__ patches, int n_units,
     int n_slabs, int slab, int remap, Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in,
-    double dt_fixed, Ph ph)
+    double dt_fixed, FvChain chain, Ph ph)
 {
     constexpr int N = Ph::N, A = Ph::A, AA = A > 0 ? A : 1;
     static_assert(Ph::E == 0, "the DMA variant has no extra per-cell input");
@@ -459,7 +459,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fv_step_dma_kernel(
     const bool work = z0 < p;
     const bool active = work && t < pp;
     const int x = active ? t % p : 0, y = active ? t / p : 0;
-    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot_in];
+    const double dt = step_dt<3, kLam>(ctrl, slot_in, dt_fixed, chain);
     const double hr_ = 0.5 * dt * P.inv_dx;
     // LDS slots of the cell and its four in-plane neighbours (halo strips
     // follow the p x p interior: -x, +x, -y, +y, p cells each)
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fv_step_dma_kernel(
         wait_vm(0);
     }
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
-    if (kLam) store_partial<3>(part, lm, unit, n_units);
+    if (kLam) fold_speeds<3>(ctrl, part, lm, unit, n_units, chain);
 }
 
 // ---------------------------------------------------------------------------
@@ -634,7 +634,7 @@ template <class Ph, typename T, bool kLam>
 __global__ __launch_bounds__(kFvThreads) void fv_small_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
     const PatchDev *__restrict__ patches, int K, int p, int G, Ctrl *__restrict__ ctrl,
-    double *__restrict__ part, int slot_in, double dt_fixed, Ph ph)
+    double *__restrict__ part, int slot_in, double dt_fixed, FvChain chain, Ph ph)
 {
     constexpr int N = Ph::N, A = Ph::A, AA = A > 0 ? A : 1;
     extern __shared__ double box[];   // [N + A][G * B]
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(kFvThreads) void fv_small_kernel(
     const int g = t / P3, l = t - g * P3;
     const bool active = g < G && k0 + g < K;
     const int x = l % p, y = (l / p) % p, z = l / (p * p);
-    const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot_in];
+    const double dt = step_dt<3, kLam>(ctrl, slot_in, dt_fixed, chain);
     auto slot = [&](int gg, int xx, int yy, int zz) { return gg * B + ((zz + 1) * pb + (yy + 1)) * pb + (xx + 1); };
 
     double qc[N], ac[AA], e[1] = {0.0};
@@ -721,7 +721,7 @@ __global__ __launch_bounds__(kFvThreads) void fv_small_kernel(
         if (kLam) cell_speeds_fast<Ph, 3>(ph, qw, lm);
     }
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
-    if (kLam) store_partial<3>(part, lm, blockIdx.x, gridDim.x);
+    if (kLam) fold_speeds<3>(ctrl, part, lm, blockIdx.x, gridDim.x, chain);
 }
 
 // Largest speeds of the current state (first step of a call in CFL mode):
@@ -798,6 +798,8 @@ __global__ __launch_bounds__(1024) void dt_reduce_kernel(const double *__restric
             const double dt = cfl / den;
             ctrl->dt[slot] = dt;
             ctrl->last_dt = dt;
+            // the first FV step of a call folds its speeds into lmax[0]
+            for (int d = 0; d < 3; ++d) ctrl->lmax[0][d] = 0ull;
         }
         if (want_stats) {
             ctrl->c2p_iters += (unsigned long long)tot[3];
@@ -854,9 +856,13 @@ __global__ void ctrl_init_kernel(Ctrl *ctrl)
 namespace {
 
 template <class Ph, int DIM, typename T>
-pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, int slot_in,
+pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, int slot_in, int step,
                        double dt_fixed, double cfl, hipStream_t s)
 {
+    // in CFL mode the steps of a call hand the speed maxima to each other
+    // through the control block (FvChain); step < 0 stores partials and
+    // runs the reduction kernel after the step
+    const FvChain chain{step, cfl, b->dxmin};
     const int slab = (DIM == 3) ? (b->fv_slab > 0 ? std::min(b->fv_slab, b->pmax) : b->pmax) : 1;
     const int n_slabs = (DIM == 3) ? (b->pmax + slab - 1) / slab : 1;
     const int n_units = b->K * n_slabs;
@@ -877,40 +883,40 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
         const bool lam = !(dt_fixed > 0.0) && Ph::E == 0;
         if (lam)
             launch_main(b, fv_small_kernel<Ph, T, true>, dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
-                               b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, ph);
+                               b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, chain, ph);
         else
             launch_main(b, fv_small_kernel<Ph, T, false>, dim3(nwg), dim3(kFvThreads), lds, s, qi, qo, ex,
-                               b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, ph);
+                               b->d_patches, b->K, p, G, ctrl, part, slot_in, dt_fixed, chain, ph);
         PB_HIP(hipGetLastError());
-        if (lam) return launch_dt_reduce(b, part, nwg, DIM, slot_in ^ 1, cfl, true, false, s);
+        if (lam && step < 0) return launch_dt_reduce(b, part, nwg, DIM, slot_in ^ 1, cfl, true, false, s);
         return PB_OK;
       }
     }
     if constexpr (Ph::E > 0) {  // SRHD: dt comes from the con2prim pass
         launch_main(b, fv_step_kernel<Ph, DIM, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                            ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
-                           slot_in, dt_fixed, ph);
+                           slot_in, dt_fixed, chain, ph);
     } else if (DIM == 3 && b->fv_dma && fv_dma_eligible(b)) {
         if (dt_fixed > 0.0)
             launch_main(b, fv_step_dma_kernel<Ph, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                                b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part, slot_in, dt_fixed,
-                               ph);
+                               chain, ph);
         else
             launch_main(b, fv_step_dma_kernel<Ph, T, true>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
                                b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part, slot_in, dt_fixed,
-                               ph);
+                               chain, ph);
     } else {
         if (dt_fixed > 0.0)
             launch_main(b, fv_step_kernel<Ph, DIM, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi,
                                qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
-                               slot_in, dt_fixed, ph);
+                               slot_in, dt_fixed, chain, ph);
         else
             launch_main(b, fv_step_kernel<Ph, DIM, T, true>, dim3(n_units), dim3(kFvThreads), 0, s, qi,
                                qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
-                               slot_in, dt_fixed, ph);
+                               slot_in, dt_fixed, chain, ph);
     }
     PB_HIP(hipGetLastError());
-    if (!(dt_fixed > 0.0) && Ph::E == 0) {
+    if (!(dt_fixed > 0.0) && Ph::E == 0 && step < 0) {
         pb_status st = launch_dt_reduce(b, part, n_units, DIM, slot_in ^ 1, cfl, true, false, s);
         if (st != PB_OK) return st;
     }
@@ -991,14 +997,14 @@ bool fv_dma_eligible(const pb_batch *b)
     return true;
 }
 
-pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, double dt_fixed,
+pb_status launch_fv_step(pb_batch *b, const void *qin, void *qout, int slot_in, int step, double dt_fixed,
                          double cfl, hipStream_t s)
 {
     return dispatch(b, [&](const auto &ph, auto dimc, auto tt) -> pb_status {
         using Ph = std::decay_t<decltype(ph)>;
         using T = decltype(tt);
         constexpr int DIM = decltype(dimc)::value;
-        return launch_typed<Ph, DIM, T>(b, ph, qin, qout, slot_in, dt_fixed, cfl, s);
+        return launch_typed<Ph, DIM, T>(b, ph, qin, qout, slot_in, step, dt_fixed, cfl, s);
     });
 }
 

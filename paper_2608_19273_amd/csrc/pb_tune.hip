@@ -108,7 +108,7 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
 pb_status trial(pb_batch *b, int kind, double cfl, double dt_fixed, double sigma, hipStream_t s)
 {
     void *qin = b->state[b->cur], *qout = b->state[b->cur ^ 1];
-    if (kind == 0) return launch_fv_step(b, qin, qout, 0, dt_fixed, cfl, s);
+    if (kind == 0) return launch_fv_step(b, qin, qout, 0, 0, dt_fixed, cfl, s);
     const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     return launch_fd_stage(b, 0, 4, qin, qin, b->ws + L.yA, qout, fd_dt(b, cfl, dt_fixed), sigma, s);
 }
