@@ -1,7 +1,7 @@
 """Edge cases of the GPU path against the oracle: single patches, zero steps,
 fixed time steps, ragged and tiny con2prim sizes (every guess), the limits
-of the FD unknown count, and SRHD batches whose patches are smaller than one
-work-group's chunk."""
+of the FD unknown count, SRHD batches whose patches are smaller than one
+work-group's chunk, and the dt hand-over between FV steps across calls."""
 import numpy as np
 import pytest
 
@@ -161,3 +161,29 @@ def test_srhd_small_patches_every_guess(p, small_net):
         B.close()
         assert np.all(rel_err(b, g, o) <= 1e-12), (guess, rel_err(b, g, o))
         assert st["c2p_cells"] == 2 * b.total_cells and st["c2p_failures"] == 0
+
+
+@pytest.mark.parametrize("small", [False, True])
+def test_fv_dt_handover_across_calls(small):
+    """CFL steps of one call hand the speed maxima to the next step through
+    the control block (three rotating slots): calls of 1, 2 and 4 CFL steps
+    with a fixed-dt call in between match the oracle run call by call, in the
+    plane kernel (16^3 patches) and the whole-patch kernel (4^3), and every
+    call's last dt is the oracle's."""
+    announce(f"fv dt hand-over across calls small={small}")
+    need_gpu()
+    import dataclasses
+    b = I.config1(grid=(2, 2, 2), p=4 if small else 16)
+    B = pb.PatchBatch(b)
+    ref = b
+    for n, fixed in ((1, 0.0), (2, 0.0), (1, 1e-4), (4, 0.0)):
+        dt = B.fv_rusanov_step(cfl=0.4, dt_fixed=fixed, n_steps=n, want_dt=True)
+        if fixed > 0.0:
+            o, dts, _ = oracle.fv_step(ref, dt_fixed=fixed, n_steps=n)
+        else:
+            o, dts, _ = oracle.fv_step(ref, cfl=0.4, n_steps=n)
+        ref = dataclasses.replace(ref, state=o)
+        g = B.download()
+        assert np.all(rel_err(b, g, o) <= 1e-12), (n, fixed, rel_err(b, g, o))
+        assert abs(dt - dts[-1]) <= 1e-14 * dts[-1], (n, fixed, dt, dts[-1])
+    B.close()
