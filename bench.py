@@ -21,7 +21,10 @@ the K sweep (runtime per cell against the number of independent patches
 for p = 3, 6, 16, FV and FD4), and offload mode (host chunks in and out
 through pinned staging and PCIe: total runtime against kernel time).
 
-Prints one JSON line on stdout; progress goes to stderr.
+Prints one compact JSON line on stdout (headline, roofline, CPU baseline and
+a one-line summary per further workload); the full result with every table
+goes to --detail-out (default gpurun_out/bench_detail.json); progress goes to
+stderr.
 """
 from __future__ import annotations
 
@@ -85,6 +88,69 @@ def timed(torch, fn):
     return max(wall, e0.elapsed_time(e1) / 1e3)
 
 
+def cpu_info():
+    """CPU model, the logical CPUs of the host and the CPUs this process may
+    run on"""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": os.cpu_count() or 1, "usable_cpus": usable}
+
+
+def _oracle_fd_worker(args):
+    """one worker of the multi-process oracle leg: repeated one-step RK4
+    updates of its own patches of the uneven linear-system batch for about
+    `seconds`; returns (cell-steps, seconds)"""
+    subset, seconds = args
+    import oracle
+    from paper_2608_19273_amd import inputs as I
+    b = I.config2(subset=subset)
+    q = b.state
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        q = oracle.fd_step(b, q, cfl=0.5, sigma=0.1, n_steps=1)[0]
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            return b.total_cells * steps, el
+
+
+def cpu_oracle_multiprocess(workers: int, seconds: float):
+    """The same single-threaded oracle run as `workers` independent processes
+    (spawned, so none of them inherits the GPU context), each advancing its
+    own patches of the uneven 58-unknown batch (one 4^3, two 8^3 and one 16^3
+    patch per worker, the batch's 1:2:1 mix): an embarrassingly parallel
+    oracle throughput over independent patches, labelled as such."""
+    import multiprocessing as mp
+    from paper_2608_19273_amd import inputs as I
+    sizes = I.config2_sizes()
+    pools = {p: list(map(int, (sizes == p).nonzero()[0])) for p in (4, 8, 16)}
+    jobs = []
+    for w in range(workers):
+        sub = [pools[4][w], pools[8][2 * w], pools[8][2 * w + 1], pools[16][w]]
+        jobs.append((sorted(sub), seconds))
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:
+        res = pool.map(_oracle_fd_worker, jobs)
+    wall = time.perf_counter() - t0
+    rate = sum(c / s for c, s in res)
+    return {"value": rate, "unit": "cell-steps/s", "cores": workers, "kind": "oracle, multi-process",
+            "sample": f"{workers} spawned processes, each one-step RK4 FD4 + KO6 updates of its own 4 patches "
+                      f"(4^3, 2x 8^3, 16^3) of the 58-unknown batch for {seconds:.0f} s; rate = sum of the "
+                      f"per-process rates; wall {wall:.1f} s"}
+
+
 def cpu_baseline(target_s: float):
     """The oracle (single-threaded FP64 C) on a bounded sample of the
     headline workload: the same IC recipe on 4x4x4 patches of 16^3."""
@@ -102,7 +168,7 @@ def cpu_baseline(target_s: float):
             break
     return {"value": b.total_cells * steps / el, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"3D Euler Rusanov FV, same IC recipe on 4x4x4 patches of 16^3 ({b.total_cells} cells), "
-                      f"{steps} steps, {el:.1f} s, single thread"}
+                      f"{steps} steps, {el:.1f} s, single thread", **cpu_info()}
 
 
 def cpu_oracle_sample(kind: str, target_s: float):
@@ -145,6 +211,7 @@ def attainable_copy(torch, pb):
 
 
 RETUNE = False
+MIN_WARMUP_S = 0.5
 
 
 def tune(B, kind, **kw):
@@ -166,7 +233,7 @@ def tune(B, kind, **kw):
 def bench_euler3d(torch, pb, b, storage, steps, warmup):
     B = pb.PatchBatch(b, storage=storage)
     tuned = tune(B, "fv", cfl=0.4)
-    B.fv_rusanov_step(cfl=0.4, n_steps=warmup)
+    extra = warm_up(torch, B, lambda n: B.fv_rusanov_step(cfl=0.4, n_steps=n), warmup, MIN_WARMUP_S)
     B.profile(True)
     el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.4, n_steps=steps))
     kern_ms, launches = B.profile_read()
@@ -181,7 +248,7 @@ def bench_euler3d(torch, pb, b, storage, steps, warmup):
     return {"cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
             "kernel_avg_us": avg_s * 1e6, "launches": launches, "bytes_per_cell": bpc,
             "kernel_GBs": cells * bpc / avg_s / 1e9, "nonfinite_units": st["nonfinite_units"],
-            "autotune": tuned, "tuning": tuning}
+            "warmup_extra_steps": extra, "autotune": tuned, "tuning": tuning}
 
 
 def bench_config0(torch, pb, I, calls):
@@ -205,10 +272,16 @@ def bench_fd(torch, pb, I, steps, warmup):
     B = pb.PatchBatch(b)
     tuned = tune(B, "fd", cfl=0.5, sigma_ko=0.1)
     B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=warmup)
+    # eager, with every stage launch timed by its own dispatch events
     B.profile(True)
-    el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
+    el_eager = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
     kern_ms, launches = B.profile_read()
     B.profile(False)
+    # the same steps captured once into a HIP graph (outside the timed
+    # region), then replayed: the configuration's execution mode
+    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps, use_graph=True)
+    el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps, use_graph=True))
+    st = B.stats()
     B.close()
     N = b.n_unknowns
     # per RK4 step: 4 x (3 dense N x N products + 3 D4 (4 flop) + 3 KO6 (9 flop) + update) per unknown
@@ -217,8 +290,9 @@ def bench_fd(torch, pb, I, steps, warmup):
     step_kernel_s = kern_ms / 1e3 / max(launches, 1) * 4
     return {"workload": "linear symmetric system N=58, 4096 patches {4^3,8^3,16^3} 1:2:1 shuffled "
                         f"({cells} cells), FD4 + KO6 (sigma 0.1) + RK4, CFL 0.5, FP64",
-            "cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps,
-            "stage_kernel_avg_us": kern_ms * 1e3 / max(launches, 1),
+            "cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps, "use_graph": True,
+            "ms_per_step_eager": el_eager * 1e3 / steps,
+            "stage_kernel_avg_us": kern_ms * 1e3 / max(launches, 1), "nonfinite_units": st["nonfinite_units"],
             "hbm_frac": cells * bytes_cell / step_kernel_s / 1e9 / HBM_PEAK_GBS,
             "fp64_frac": cells * flop_cell / step_kernel_s / 1e12 / FP64_PEAK_TFLOPS,
             "algorithmic_bytes_per_cell_step": bytes_cell, "algorithmic_flop_per_cell_step": flop_cell,
@@ -260,7 +334,7 @@ KSWEEP_K = (1, 4, 16, 64, 256, 1024, 4096, 8694, 16384)
 def bench_ksweep(torch, pb, I, k_max_16=8694):
     """Runtime per cell against the batch size K (the shape of the paper's
     main experiment): K independent 3D Euler patches of p^3 cells for
-    p in {3, 6, 16}, the FV step (CFL 0.4) and the FD4 + KO6 + RK4 step (CFL
+    p in {3, 6, 16} (smooth seeded state per patch), the FV step (CFL 0.4) and the FD4 + KO6 + RK4 step (CFL
     0.5, sigma 0.1), eager launches and the same steps replayed from a HIP
     graph, each timed by wall clock and events; per cell means per
     cell-update (FV) and per cell-step of all four RK stages (FD).  Also the
@@ -273,23 +347,27 @@ def bench_ksweep(torch, pb, I, k_max_16=8694):
             for K in KSWEEP_K:
                 if p == 16 and K > k_max_16:
                     continue
-                b = I.independent_euler_patches(7, K, p, halo=3 if scheme == "fd" else 1)
+                b = I.independent_euler_patches_smooth(7, K, p, halo=3 if scheme == "fd" else 1)
                 cells = b.total_cells
                 B = pb.PatchBatch(b)
                 if scheme == "fv":
                     step = lambda n, g: B.fv_rusanov_step(cfl=0.4, n_steps=n, use_graph=g)
                 else:
                     step = lambda n, g: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n, use_graph=g)
-                n = int(min(200, max(3, round(5e7 / (cells * (4 if scheme == "fd" else 1))))))
+                n = int(min(200 if scheme == "fv" else 100,
+                            max(3, round(5e7 / (cells * (4 if scheme == "fd" else 1))))))
                 step(1, False)
                 el = timed(torch, lambda: step(n, False))
                 step(n, True)   # capture (and one replay) outside the timed region
                 elg = timed(torch, lambda: step(n, True))
                 st = B.stats()
                 B.close()
+                # a row that computed a non-finite value timed something else
+                # than the update of a valid state: kept in the table, flagged
                 rows.append({"K": K, "cells": cells, "steps": n, "ns_per_cell": el / (n * cells) * 1e9,
                              "us_per_step": el / n * 1e6, "ns_per_cell_graph": elg / (n * cells) * 1e9,
-                             "us_per_step_graph": elg / n * 1e6, "nonfinite_units": st["nonfinite_units"]})
+                             "us_per_step_graph": elg / n * 1e6, "nonfinite_units": st["nonfinite_units"],
+                             "valid": st["nonfinite_units"] == 0})
                 del b
             out[f"{scheme}_p{p}"] = rows
             log(f"k-sweep {scheme} p={p}: " + ", ".join(f"K={r['K']}: {r['ns_per_cell']:.3f}/{r['ns_per_cell_graph']:.3f} ns"
@@ -312,9 +390,11 @@ def bench_ksweep(torch, pb, I, k_max_16=8694):
             n = int(min(50, max(2, round(2e6 / cells))))
             B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=1)
             el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n))
+            st = B.stats()
             B.close()
             rows.append({"K": K, "cells": cells, "steps": n, "ns_per_cell": el / (n * cells) * 1e9,
-                         "us_per_step": el / n * 1e6})
+                         "us_per_step": el / n * 1e6, "nonfinite_units": st["nonfinite_units"],
+                         "valid": st["nonfinite_units"] == 0})
             del b
         out[f"fd_linsym58_p{p}"] = rows
         log(f"k-sweep linsym58 p={p}: " + ", ".join(f"K={r['K']}: {r['ns_per_cell']:.2f} ns" for r in rows))
@@ -431,12 +511,92 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     return res
 
 
+def warm_up(torch, B, step_fn, warmup, min_seconds):
+    """W untimed steps, then further untimed steps until at least
+    `min_seconds` of warm-up have passed: the first ~200 launches after an
+    idle spell run about 15 % slower than the sustained rate (clock and power
+    state ramp), which a short W does not cover.  Returns the extra steps."""
+    t0 = time.perf_counter()
+    if warmup > 0:
+        step_fn(warmup)
+    torch.cuda.synchronize()
+    extra = 0
+    while time.perf_counter() - t0 < min_seconds:
+        step_fn(50)
+        torch.cuda.synchronize()
+        extra += 50
+    return extra
+
+
+def compact(result):
+    """The one-line summary the driver parses (a few hundred bytes per
+    workload): headline, roofline, CPU baseline and one line per further
+    workload; the full tables go to the detail file."""
+    keep = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "nonfinite_units")
+    out = {k: result[k] for k in keep if k in result}
+    r = result["roofline"]
+    out["roofline"] = {k: r[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                         "avg_launch_us", "attainable_copy_GBs", "frac_of_attainable")}
+    out["warmup_extra_steps"] = result.get("warmup_extra_steps")
+    if "cpu_baseline" in result:
+        out["cpu_baseline"] = result["cpu_baseline"]
+    wl = result.get("workloads", {})
+    s = {}
+    r3 = lambda v: None if v is None else float(f"{v:.4g}")
+    if "euler3d_fp32_storage" in wl:
+        w = wl["euler3d_fp32_storage"]
+        s["euler3d_fp32"] = {"cell_updates_per_s": r3(w["cell_updates_per_s"]), "kernel_us": r3(w["kernel_avg_us"]),
+                             "hbm_frac": r3(w["hbm_frac"])}
+    if "euler2d_64x64_config0" in wl:
+        w = wl["euler2d_64x64_config0"]
+        s["euler2d_config0_us_per_step"] = {k: r3(v["us_per_step"]) for k, v in w.items()}
+    if "advection_material_field" in wl:
+        w = wl["advection_material_field"]
+        s["adv_material_field"] = {"kernel_us": r3(w["kernel_avg_us"]), "hbm_frac": r3(w["hbm_frac"])}
+    if "linsym58_fd4_rk4" in wl:
+        w = wl["linsym58_fd4_rk4"]
+        s["linsym58_fd4_rk4"] = {"ms_per_step": r3(w["ms_per_step"]), "stage_us": r3(w["stage_kernel_avg_us"]),
+                                 "hbm_frac": r3(w["hbm_frac"]), "fp64_frac": r3(w["fp64_frac"]),
+                                 "graph": w.get("use_graph")}
+        if "cpu_oracle" in w:
+            s["linsym58_fd4_rk4"]["cpu_oracle_cell_steps_per_s"] = r3(w["cpu_oracle"]["value"])
+    if "euler3d_fd4_rk4" in wl:
+        w = wl["euler3d_fd4_rk4"]
+        s["euler3d_fd4_rk4"] = {"ms_per_step": r3(w["ms_per_step"]), "hbm_frac": r3(w["hbm_frac"]),
+                                "nonfinite_units": w["nonfinite_units"]}
+    if "srhd" in wl:
+        w = wl["srhd"]
+        s["srhd"] = {g: {"ms_per_step": r3(w[g]["ms_per_step"]), "newton_mean": r3(w[g]["newton_iterations_mean"]),
+                         "newton_max": w[g]["newton_iterations_max"], "failures": w[g]["c2p_failures"],
+                         "fallbacks": w[g]["fallbacks"]} for g in ("plain", "warm", "learned")}
+        s["srhd"]["learned_over_plain_speedup"] = r3(w["learned_over_plain_speedup"])
+        s["srhd"]["mlp_training_s"] = r3(w["mlp_training"]["seconds"])
+    if "k_sweep" in wl:
+        rows = [row for v in wl["k_sweep"].values() for row in v]
+        s["k_sweep"] = {"rows": len(rows), "invalid_rows": sum(1 for row in rows if not row.get("valid", True))}
+    if "offload" in wl:
+        s["offload_p16_K2048"] = {k: r3(v) for k, v in wl["offload"]["p16"][-1].items()
+                                  if k in ("total_ns_per_cell", "compute_ns_per_cell")}
+    if "cpu_oracle_multiprocess" in result:
+        m = result["cpu_oracle_multiprocess"]
+        s["cpu_oracle_multiprocess"] = {"value": r3(m["value"]), "unit": m["unit"], "cores": m["cores"]}
+    if s:
+        out["workloads"] = s
+    out["detail_file"] = result.get("detail_file")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--min-warmup-seconds", type=float, default=0.5,
+                    help="untimed warm-up steps continue until this much time has passed")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="processes of the multi-process oracle leg (0 = usable CPUs, at most 16)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-headline", action="store_true", help="skip the further workloads")
     ap.add_argument("--workloads", default="fp32,config0,advvar,linsym,fdeuler,srhd,ksweep,offload",
@@ -447,6 +607,8 @@ def main():
                     help="autotuner cache to start from (measured launch shapes per workload)")
     ap.add_argument("--retune", action="store_true", help="measure every workload's candidates again")
     ap.add_argument("--save-tuning", default=None, help="write the autotuner cache here at the end")
+    ap.add_argument("--detail-out", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+                    help="file for the full result (every table); stdout gets the one-line summary")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py runs on one GPU; there is no multi-GPU path (--gpus must be 1)"}))
@@ -457,8 +619,9 @@ def main():
     import paper_2608_19273_amd as pb
     from paper_2608_19273_amd import inputs as I
 
-    global RETUNE
+    global RETUNE, MIN_WARMUP_S
     RETUNE = args.retune
+    MIN_WARMUP_S = args.min_warmup_seconds
     if not args.retune and os.path.exists(args.tuning_file):
         log(f"tuning cache: {pb.pb_autotune_cache_load(args.tuning_file)} entries from {args.tuning_file}")
 
@@ -496,8 +659,11 @@ def main():
                      "attainable_copy_GBs": copy_gbs, "frac_of_attainable": achieved / copy_gbs,
                      "kernel_source_sha": sha},
         "nonfinite_units": h["nonfinite_units"],
+        "warmup_extra_steps": h["warmup_extra_steps"],
         "autotune": h["autotune"],
     }
+    log(f"headline {h['cell_updates_per_s'] / 1e9:.2f} G cell-updates/s, kernel {h['kernel_avg_us']:.1f} us, "
+        f"frac {achieved / HBM_PEAK_GBS:.3f}")
     if not args.only_headline:
         wl = {}
         want = set(args.workloads.split(","))
@@ -542,7 +708,18 @@ def main():
             if key in wl:
                 log(f"timing the CPU oracle on a {kind} sample")
                 wl[key]["cpu_oracle"] = cpu_oracle_sample(kind, 6.0)
-    print(json.dumps(result), flush=True)
+        if "linsym58_fd4_rk4" in wl:
+            workers = args.cpu_workers or min(16, cpu_info()["usable_cpus"])
+            log(f"timing the multi-process oracle ({workers} processes)")
+            result["cpu_oracle_multiprocess"] = cpu_oracle_multiprocess(workers, 5.0)
+    try:
+        os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+        with open(args.detail_out, "w") as fh:
+            json.dump(result, fh, indent=1)
+        result["detail_file"] = os.path.relpath(args.detail_out, ROOT)
+    except OSError as e:
+        log(f"could not write {args.detail_out}: {e}")
+    print(json.dumps(compact(result)), flush=True)
 
 
 if __name__ == "__main__":

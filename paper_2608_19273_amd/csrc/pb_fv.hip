@@ -67,10 +67,6 @@ __device__ __forceinline__ void cell_speeds_fast(const Ph &ph, const double *q, 
 
 }  // namespace
 
-#ifndef PB_FV_NTLOAD
-#define PB_FV_NTLOAD 0
-#endif
-
 // raw (storage-type) values of one cell: N unknowns plus the extra input
 template <class Ph, typename T>
 struct RawCell {
@@ -84,11 +80,7 @@ __device__ __forceinline__ void issue_load(const T *__restrict__ q, const double
 {
     const T *base = q + off * Ph::N + c;
 #pragma unroll
-#if PB_FV_NTLOAD
-    for (int v = 0; v < Ph::N; ++v) r.q[v] = __builtin_nontemporal_load(base + (long long)v * C);
-#else
     for (int v = 0; v < Ph::N; ++v) r.q[v] = base[(long long)v * C];
-#endif
     if (Ph::E) r.e = ex[off + c];
 }
 
@@ -99,18 +91,6 @@ __device__ __forceinline__ void unpack(const RawCell<Ph, T> &r, double *q, doubl
     for (int v = 0; v < Ph::N; ++v) q[v] = (double)r.q[v];
     e[0] = Ph::E ? r.e : 0.0;
 }
-
-#ifndef PB_FV_NTLOAD
-#define PB_FV_NTLOAD 0
-#endif
-#ifndef PB_FV_WPE
-#define PB_FV_WPE 0
-#endif
-#if PB_FV_WPE
-#define PB_FV_ATTR __attribute__((amdgpu_waves_per_eu(PB_FV_WPE)))
-#else
-#define PB_FV_ATTR
-#endif
 
 template <class Ph, int D>
 __device__ __forceinline__ void phys_flux_or_zero(const Ph &ph, const double *q, const double *a, double *F)
@@ -137,7 +117,7 @@ template <> struct PlaneAux<Srhd> {
 };
 
 template <class Ph, int DIM, typename T, bool kLam>
-__global__ __launch_bounds__(kFvThreads) PB_FV_ATTR void fv_step_kernel(
+__global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
     const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
     Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in, double dt_fixed, FvChain chain, Ph ph)

@@ -24,10 +24,6 @@
 
 #include <hip/hip_runtime.h>
 
-#ifndef PB_FASTDIV
-#define PB_FASTDIV 0
-#endif
-
 namespace pb {
 
 // 1/x from the hardware reciprocal estimate refined by two Newton steps
@@ -148,21 +144,13 @@ struct Euler {
     double gamma;
     __device__ __forceinline__ void aux(const double *q, const double *, double *a) const
     {
-#if PB_FASTDIV
-        const double ir = recip(q[0]);
-#else
         const double ir = 1.0 / q[0];
-#endif
         double m2 = q[1] * q[1] + q[2] * q[2];
         if (DIM == 3) m2 += q[3] * q[3];
         const double p = (gamma - 1.0) * (q[DIM + 1] - 0.5 * m2 * ir);
         a[0] = ir;
         a[1] = p;
-#if PB_FASTDIV
-        a[2] = root(gamma * p * ir);
-#else
         a[2] = sqrt(gamma * p * ir);
-#endif
     }
     __device__ __forceinline__ void aux_fast(const double *q, const double *, double *a) const
     {

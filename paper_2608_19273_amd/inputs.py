@@ -313,6 +313,45 @@ def independent_euler_patches(seed: int, K: int, p: int, halo: int = 1, gamma: f
                  pde="euler", params=np.array([gamma]), n_unknowns=5, state=state)
 
 
+def _unit_cube_modes(seed: int, K: int, p: int, n_modes: int) -> np.ndarray:
+    """[K, p^3] per patch: sum_m a_m sin(2 pi k_m . x + phi_m) / sum_m a_m
+    at the cell centres of the unit cube (x fastest), k_m in {-1,0,1}^3
+    minus 0, a_m ~ U(0,1), phi_m ~ U(0, 2 pi); values in [-1, 1]."""
+    x = (np.arange(p) + 0.5) / p
+    e = np.exp(2j * np.pi * np.outer(np.arange(-1, 2), x))            # e[k+1, i]
+    r = uniform(seed, K * n_modes * 2).reshape(K, n_modes, 2)
+    kk = (splitmix64(substream(seed, 5), K * n_modes) % np.uint64(26)).astype(np.int64).reshape(K, n_modes)
+    kk = np.where(kk >= 13, kk + 1, kk)  # skip (0,0,0), index 13 of 27
+    kx, ky, kz = kk % 3, (kk // 3) % 3, kk // 9
+    amp = r[:, :, 0] * np.exp(1j * 2 * np.pi * r[:, :, 1])            # [K, m]
+    out = np.zeros((K, p, p, p))
+    for m in range(n_modes):
+        t = amp[:, m, None, None, None] * e[kz[:, m]][:, :, None, None] * e[ky[:, m]][:, None, :, None] \
+            * e[kx[:, m]][:, None, None, :]
+        out += np.imag(t)
+    return out.reshape(K, p ** 3) / r[:, :, 0].sum(axis=1)[:, None]
+
+
+def independent_euler_patches_smooth(seed: int, K: int, p: int, halo: int = 1, gamma: float = 1.4) -> Batch:
+    """K independent 3D Euler patches of p^3 cells (each a periodic unit cube
+    on itself, dx = 1/p) with a smooth seeded state: per patch a uniform
+    velocity v_k (components ~ U[-0.3, 0.3]) carrying an entropy wave
+    rho = 1 + 0.2 s_rho, plus small acoustic perturbations v = v_k + 0.02 s_v,
+    p = 1 + 0.02 s_p, each s a normalised sum of 4 modes with wave vectors in
+    {-1,0,1}^3.  Stays smooth (far from shock formation) for the several
+    hundred FD4 + KO6 + RK4 steps of the K sweep, unlike i.i.d. cell values,
+    which the unlimited central scheme cannot carry."""
+    fields = [_unit_cube_modes(substream(seed, 20 + f), K, p, 4) for f in range(5)]
+    vk = uniform(substream(seed, 30), 3 * K, -0.3, 0.3).reshape(3, K)
+    rho = 1.0 + 0.2 * fields[0]
+    vel = [vk[d][:, None] + 0.02 * fields[1 + d] for d in range(3)]
+    pr = 1.0 + 0.02 * fields[4]
+    cons = np.stack(euler_prim_to_state(rho, vel, pr, gamma))            # [5, K, p^3]
+    state = np.ascontiguousarray(cons.transpose(1, 0, 2)).reshape(-1)
+    return Batch(dim=3, p=np.full(K, p, np.int32), dx=np.full(K, 1.0 / p), nbr=self_periodic(K, 3), halo=halo,
+                 pde="euler", params=np.array([gamma]), n_unknowns=5, state=state)
+
+
 def independent_halo_chunks(seed: int, K: int, p: int, halo: int = 1, gamma: float = 1.4) -> list:
     """K offload-mode input chunks of 3D Euler: each the (p+2h)^3 halo box in
     per-point order [z][y][x][5], i.i.d. primitives at every point (halo
