@@ -51,12 +51,14 @@ def test_plane_wave_closed_form(axis):
 
 def test_config2_subset_parity():
     """48 seeded patches of the full uneven batch (16 each of 4^3, 8^3,
-    16^3), N = 58, sigma 0.1, CFL 0.5, two RK4 steps."""
-    announce("fd config2 subset")
+    16^3), N = 58, sigma 0.1, CFL 0.5, ten RK4 steps (the step count read
+    for the configuration), through the graph-captured launches the benchmark
+    replays."""
+    announce("fd config2 subset, 10 steps")
     sel = I.config2_subset()
     b = I.config2(subset=sel)
-    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
-    g, dt = run_fd(b, n_steps=2)
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=10)
+    g, dt = run_fd(b, n_steps=10, use_graph=True)
     assert abs(dt - dts[-1]) <= 1e-15 * dts[-1]
     err = rel_err(b, g, o)
     assert np.all(err <= 1e-12), err.max()

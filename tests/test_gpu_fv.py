@@ -216,18 +216,19 @@ def test_graph_replay_matches_eager():
 @pytest.mark.slow
 def test_config1_full_size_parity():
     """The full 2048 x 16^3 Euler batch in the benchmark's launch
-    configuration, two steps, against the full oracle (FP64, then FP32
-    storage)."""
-    announce("config1 full size")
+    configuration, for the configuration's 20 steps, against the full oracle
+    (FP64, then FP32 storage)."""
+    announce("config1 full size, 20 steps")
     b = I.config1()
-    g, dt, st = run_gpu(b, n_steps=2)
-    o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=2)
+    g, dt, st = run_gpu(b, n_steps=20)
+    o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=20)
     assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
     assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
     # the FP32-storage run of the same workload
     b.state = b.state.astype(np.float32).astype(np.float64)
-    g32, _, _ = run_gpu(b, storage="fp32", n_steps=2)
-    o32, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=2, round_fp32=True)
+    announce("config1 full size, 20 steps, fp32 storage")
+    g32, _, _ = run_gpu(b, storage="fp32", n_steps=20)
+    o32, _, _ = oracle.fv_step(b, cfl=0.4, n_steps=20, round_fp32=True)
     assert np.all(rel_err(b, g32, o32) <= 1e-5), rel_err(b, g32, o32)
 
 

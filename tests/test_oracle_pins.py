@@ -846,3 +846,86 @@ def test_fd_patch_permutation_invariance():
     qp, _ = oracle.fd_step(bp, n_steps=1)
     for j, k in enumerate(perm):
         np.testing.assert_array_equal(bp.patch_view(qp, j), b.patch_view(q, k))
+
+
+def test_con2prim_fallback_composition():
+    """A guessed start that does not converge within max_iter is redone from
+    the plain guess (R14): the cell then carries the plain start's pressure
+    and status, the iterations of both attempts add up, and the fallback is
+    counted once.  The guessed start's own count comes from the same guess
+    with a large max_iter (the iterates do not depend on max_iter), the plain
+    start's from a run without guess, so every branch of the composition is
+    checked cell by cell: guessed start converged, fell back and converged,
+    fell back and failed."""
+    n = 20000
+    m = 3
+    rho, vx, vy, vz, eps = I.srhd_primitives(61, n)
+    cons, p = I.srhd_prim_to_cons(rho, vx, vy, vz, eps, 5 / 3)
+    # a poor but admissible guess: 1e-3 .. 10 times the true pressure, kept
+    # inside the bracket (p_lo, p_hi] so that it is used
+    E = cons[4] + cons[0]
+    s = np.sqrt(cons[1] ** 2 + cons[2] ** 2 + cons[3] ** 2)
+    lo, hi = np.maximum(s - E, 0.0), (5 / 3 - 1) * cons[4]
+    g = p * np.exp(I.uniform(62, n, math.log(1e-3), math.log(10.0)))
+    g = np.where((g > lo) & (g <= hi), g, 0.5 * (lo + hi))
+    _, gi, gst, _, _ = oracle.con2prim(cons, maxit=1000, p_guess=g)
+    gp = oracle.con2prim(cons, maxit=1000, p_guess=g)[0][4]
+    assert np.all(gst == 0)
+    pp_, pi, pst, _, _ = oracle.con2prim(cons, maxit=m)
+    pp = pp_[4]
+    prim, it, st, nfail, nfb = oracle.con2prim(cons, maxit=m, p_guess=g)
+    fb = gi > m
+    assert 1000 < fb.sum() < n - 1000                       # both branches are exercised
+    assert np.any(fb & (pst != 0)) and np.any(fb & (pst == 0))
+    assert nfb == fb.sum()
+    np.testing.assert_array_equal(prim[4][~fb], gp[~fb])
+    np.testing.assert_array_equal(it[~fb], gi[~fb])
+    assert np.all(st[~fb] == 0)
+    np.testing.assert_array_equal(prim[4][fb], pp[fb])
+    np.testing.assert_array_equal(st[fb], pst[fb])
+    np.testing.assert_array_equal(it[fb], m + pi[fb])
+    assert nfail == np.count_nonzero(st)
+    # without a guess nothing is ever redone
+    assert oracle.con2prim(cons, maxit=m)[4] == 0
+
+
+def test_adam_constant_gradient_closed_form():
+    """Bias-corrected Adam with a constant gradient g: m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the corrected moments are g and g^2 at every t
+    and each step moves a parameter by exactly lr g / (|g| + eps).  A wrong
+    bias-correction exponent (t - 1, or the moment decays swapped) breaks it
+    from the second step on."""
+    g = np.linspace(-2.0, 1.5, 12) + 0.01
+    lr, eps = 3e-3, 1e-8
+    p0 = np.linspace(0.3, -0.4, 12)
+    p, m, v = p0.copy(), np.zeros(12), np.zeros(12)
+    for t in range(1, 41):
+        p, m, v = M_oracle().adam_step(p, m, v, g, t, lr=lr, eps=eps)
+        np.testing.assert_allclose(p, p0 - t * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-13 * t)
+    np.testing.assert_allclose(m, (1 - 0.9 ** 40) * g, rtol=1e-13)
+    np.testing.assert_allclose(v, (1 - 0.999 ** 40) * g * g, rtol=1e-12)
+
+
+def test_adam_decay_after_gradient_stops():
+    """Constant g for T steps, then zero: m_t = b1^(t-T) (1 - b1^T) g and
+    v_t = b2^(t-T) (1 - b2^T) g^2, so step t moves a parameter by
+    lr mh / (sqrt(vh) + eps) with mh = m_t / (1 - b1^t), vh = v_t / (1 - b2^t),
+    written out from those closed forms."""
+    g = np.array([0.7, -1.3, 2.5e-3, -4.0])
+    lr, b1, b2, eps = 1e-3, 0.9, 0.999, 1e-8
+    T = 5
+    p, m, v = np.zeros(4), np.zeros(4), np.zeros(4)
+    expect = np.zeros(4)
+    for t in range(1, 26):
+        gt = g if t <= T else np.zeros(4)
+        p, m, v = M_oracle().adam_step(p, m, v, gt, t, lr=lr)
+        k = min(t, T)
+        mt = b1 ** (t - k) * (1 - b1 ** k) * g
+        vt = b2 ** (t - k) * (1 - b2 ** k) * g * g
+        expect = expect - lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        np.testing.assert_allclose(p, expect, rtol=1e-12, atol=1e-15)
+
+
+def M_oracle():
+    from oracle import mlp
+    return mlp
