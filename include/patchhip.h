@@ -314,6 +314,14 @@ typedef struct {
                                  0 = the kernel in which every wave does every
                                  phase (fd_wg_per_cu applies to it); both give
                                  bitwise equal results */
+    int32_t fv_persist;       /* FV 3D, batches of one p (register kernel): 1 =
+                                 one work-group per resident slot, each marching
+                                 an equal run of the batch's K*p planes (patch
+                                 after patch), so no partly filled last round
+                                 of work-groups; fv_slab is then unused.  0 =
+                                 one work-group per slab (fv_slab).  Results
+                                 differ from slab mode only where a slab seam
+                                 would change the order of additions. */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
@@ -328,8 +336,10 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  * kind 0 = the finite-volume step (fv_rusanov_step with the given cfl /
  * dt_fixed), kind 1 = one FD4+KO6 stage (fd_ko_step with sigma_ko; cfl /
  * dt_fixed as there).  Candidates:
- *   FV 3D: fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0}
- *          x fv_dma {1, 0} (only 0 where the DMA-fed kernel does not apply);
+ *   FV 3D: fv_persist 1 x fv_xcd_remap {1, 0} (batches of one p), then
+ *          fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0},
+ *          then the DMA-fed kernel with fv_slab in {p_max, p_max/2} x
+ *          fv_xcd_remap {1, 0} where it applies;
  *          a batch of one p with p^3 <= 256 runs the small-patch kernel,
  *          which has no launch-shape choice: one candidate, the current one;
  *   FV 2D: fv_xcd_remap {1, 0};
@@ -362,7 +372,8 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
                       int32_t use_cache, pb_autotune_result *out);
 
 /* The process-wide tuning cache as a text file, one entry per line:
- * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws>".
+ * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws> <fv_persist>"
+ * (a line without the last field loads with fv_persist = 0).
  * save writes every entry (replacing the file); load adds the file's entries
  * (a later entry of the same key wins) and stores their number in *n_loaded
  * (nullable).  Host-only; PB_EINVAL on a file that cannot be opened or a

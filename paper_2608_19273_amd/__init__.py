@@ -56,7 +56,8 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_xcd_remap", C.c_int32),
-                ("fd_wg_per_cu", C.c_int32), ("fv_dma", C.c_int32), ("fd_ws", C.c_int32)]
+                ("fd_wg_per_cu", C.c_int32), ("fv_dma", C.c_int32), ("fd_ws", C.c_int32),
+                ("fv_persist", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -373,8 +374,9 @@ class PatchBatch:
             self.bufs[0].copy_(torch.from_numpy(np.ascontiguousarray(state)).to(self.dtype))
         _check(lib().pb_batch_reset(self.handle, 0), "pb_batch_reset")
 
-    def set_tuning(self, fv_slab=0, fv_xcd_remap=1, fd_xcd_remap=1, fd_wg_per_cu=2, fv_dma=0, fd_ws=1):
-        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap, fd_wg_per_cu, fv_dma, fd_ws)
+    def set_tuning(self, fv_slab=0, fv_xcd_remap=1, fd_xcd_remap=1, fd_wg_per_cu=2, fv_dma=0, fd_ws=1,
+                   fv_persist=0):
+        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap, fd_wg_per_cu, fv_dma, fd_ws, fv_persist)
         _check(lib().pb_batch_set_tuning(self.handle, C.byref(t)), "pb_batch_set_tuning")
 
     def get_tuning(self):

@@ -371,6 +371,7 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     b->fd_wg_per_cu = t->fd_wg_per_cu == 0 ? 2 : t->fd_wg_per_cu;
     b->fv_dma = t->fv_dma ? 1 : 0;
     b->fd_ws = t->fd_ws ? 1 : 0;
+    b->fv_persist = t->fv_persist ? 1 : 0;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     return PB_OK;
@@ -387,6 +388,7 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
     out->fd_wg_per_cu = b->fd_wg_per_cu;
     out->fv_dma = b->fv_dma;
     out->fd_ws = b->fd_ws;
+    out->fv_persist = b->fv_persist;
     return PB_OK;
     PB_API_END
 }

@@ -20,7 +20,9 @@
 // order-independent for non-negative doubles); the last work-group to finish
 // turns the maxima into the next step's dt, so dt never leaves the device.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
+#include <vector>
 
 #include "pb_common.h"
 #include "pb_physics.h"
@@ -116,11 +118,25 @@ template <> struct PlaneAux<Srhd> {
     static __device__ __forceinline__ constexpr int idx(int j) { return j < 3 ? j : j + 1; }   // p, v_x, v_y, l_x, l_y
 };
 
+// Work schedule of the plane-march kernel.  Slab mode (plan.planes == 0):
+// work-group (unit) u marches slab u % n_slabs of patch u / n_slabs (a slab
+// can start beyond the last plane of a patch smaller than the batch maximum:
+// such a unit only takes part in the reductions).  Balanced mode (uniform
+// patch size p, plan.planes = K p planes in patch order): the grid is the
+// number of resident work-groups and work-group r marches the planes
+// [r T / G, (r + 1) T / G) of that sequence, one segment per patch it
+// crosses, so every work-group moves the same number of planes and the last
+// round of a grid of whole patches, partly filled, disappears.
+struct FvPlan {
+    int n_units, n_slabs, slab, remap;
+    long long planes;   // balanced mode: total planes (0: slab mode)
+};
+
 template <class Ph, int DIM, typename T, bool kLam>
 __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
-    const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
-    Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot_in, double dt_fixed, FvChain chain, Ph ph)
+    const PatchDev *__restrict__ patches, FvPlan plan, Ctrl *__restrict__ ctrl, double *__restrict__ part,
+    int slot_in, double dt_fixed, FvChain chain, Ph ph)
 {
     constexpr int N = Ph::N, A = Ph::A, AP = PlaneAux<Ph>::n, W = N + AP, AA = A > 0 ? A : 1;
     constexpr int PH = kFvPmax + 2;
@@ -128,8 +144,14 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     __shared__ double lds[2][W][PH * PH];
 
     const int t = threadIdx.x;
-    const int unit = remap ? xcd_remap(blockIdx.x, n_units) : (int)blockIdx.x;
-    const int k = unit / n_slabs, sl = unit - k * n_slabs;
+    const int unit = plan.remap ? xcd_remap(blockIdx.x, plan.n_units) : (int)blockIdx.x;
+    const double dt = step_dt<DIM, kLam>(ctrl, slot_in, dt_fixed, chain);
+    double lm[3] = {0.0, 0.0, 0.0};
+    bool bad = false;
+    int parity = 0;   // LDS buffer of the next plane (alternates over every plane the work-group marches)
+
+    // one segment: planes [z0, z1) of patch k
+    auto segment = [&](int k, int z0, int z1) {
     const PatchDev P = patches[k];
     const int p = P.p;
     const long long C = (DIM == 3) ? (long long)p * p * p : (long long)p * p;
@@ -137,14 +159,9 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
 #pragma unroll
     for (int f = 0; f < 6; ++f) onb[f] = (f < 2 * DIM) ? patches[P.nbr[f]].off : P.off;
 
-    const int z0 = (DIM == 3) ? sl * slab : 0;
-    const int z1 = (DIM == 3) ? min(p, z0 + slab) : 1;
-    // a slab can start beyond the last plane of a patch smaller than the
-    // batch maximum: such a unit only takes part in the reductions
-    const bool work = z0 < p;
+    const bool work = z0 < z1;
     const bool active = work && t < p * p;
     const int x = active ? t % p : 0, y = active ? t / p : 0;
-    const double dt = step_dt<DIM, kLam>(ctrl, slot_in, dt_fixed, chain);
     const double hr_ = 0.5 * dt * P.inv_dx;   // the face sums below are doubled
     const int li = (y + 1) * PH + (x + 1);
 
@@ -170,8 +187,6 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     // doubled flux and fluctuation of the lower z face (fs2l, dn2l)
     double qc[N], ac[AA], fzc[N], fs2l[N], dn2l[N], e[1];
     double lzc = 0.0;
-    double lm[3] = {0.0, 0.0, 0.0};
-    bool bad = false;
     // one-plane prefetch (raw storage-type values): the own column for plane
     // z+1 and the halo cell for plane z.  One plane ahead is as fast as two or
     // three, and with the next plane's flux evaluated after the x and y
@@ -216,7 +231,8 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     // one plane: consumes rn (own plane z+1) and hr (halo of plane z), then
     // refills them with planes z+2 and z+1
     auto plane = [&](int z, RawCell<Ph, T> &rn, RawCell<Ph, T> &hr) {
-        double(*buf)[PH * PH] = lds[z & 1];
+        double(*buf)[PH * PH] = lds[parity];
+        parity ^= 1;
         double hq[N], he[1];
         unpack<Ph>(hr, hq, he);
         issue_load<Ph>(qin, ex, hoff, C, min(z + 1, z1 - 1) * pp + hsrc, hr);
@@ -317,8 +333,30 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     };
 
     for (int z = z0; z < z1; ++z) plane(z, rnA, hrA);
+    };
+
+    if (DIM == 3 && plan.planes > 0) {
+        // balanced mode: a contiguous run of planes (every patch has p planes)
+        const int p = patches[0].p;
+        const long long G = plan.n_units;
+        long long s = plan.planes * unit / G;
+        const long long s1 = plan.planes * (unit + 1) / G;
+        while (s < s1) {
+            const int k = (int)(s / p);
+            const int za = (int)(s - (long long)k * p);
+            const int zb = (int)min((long long)p, za + (s1 - s));
+            segment(k, za, zb);
+            s += zb - za;
+        }
+    } else {
+        const int k = unit / plan.n_slabs, sl = unit - k * plan.n_slabs;
+        const int p = patches[k].p;
+        const int z0 = (DIM == 3) ? sl * plan.slab : 0;
+        const int z1 = (DIM == 3) ? min(p, z0 + plan.slab) : 1;
+        segment(k, min(z0, z1), z1);
+    }
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
-    if (kLam) fold_speeds<DIM>(ctrl, part, lm, unit, n_units, chain);
+    if (kLam) fold_speeds<DIM>(ctrl, part, lm, unit, plan.n_units, chain);
 }
 
 // ---------------------------------------------------------------------------
@@ -835,6 +873,31 @@ __global__ void ctrl_init_kernel(Ctrl *ctrl)
 
 namespace {
 
+// work-groups of `kern` (block threads, no dynamic LDS) resident at once on
+// the current device: occupancy per CU times the CU count, cached per kernel
+// and device
+pb_status resident_slots(const void *kern, int threads, int *out)
+{
+    struct Entry { const void *k; int dev, slots; };
+    static std::mutex mu;
+    static std::vector<Entry> cache;
+    int dev = 0;
+    PB_HIP(hipGetDevice(&dev));
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (const Entry &e : cache)
+            if (e.k == kern && e.dev == dev) { *out = e.slots; return PB_OK; }
+    }
+    int per_cu = 0, cus = 0;
+    PB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0));
+    PB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int slots = std::max(1, per_cu) * std::max(1, cus);
+    std::lock_guard<std::mutex> g(mu);
+    cache.push_back({kern, dev, slots});
+    *out = slots;
+    return PB_OK;
+}
+
 template <class Ph, int DIM, typename T>
 pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, int slot_in, int step,
                        double dt_fixed, double cfl, hipStream_t s)
@@ -845,7 +908,7 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     const FvChain chain{step, cfl, b->dxmin};
     const int slab = (DIM == 3) ? (b->fv_slab > 0 ? std::min(b->fv_slab, b->pmax) : b->pmax) : 1;
     const int n_slabs = (DIM == 3) ? (b->pmax + slab - 1) / slab : 1;
-    const int n_units = b->K * n_slabs;
+    int n_units = b->K * n_slabs;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
     const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     double *part = reinterpret_cast<double *>(b->ws + L.part);
@@ -872,10 +935,26 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
         return PB_OK;
       }
     }
+    // the plane-march kernel: slab units, or the balanced plane schedule
+    // over the work-groups that are resident at once (uniform p)
+    FvPlan plan{n_units, n_slabs, slab, b->fv_xcd_remap, 0};
+    auto plane_kernel = [&](auto kern) -> pb_status {
+        if (DIM == 3 && b->fv_persist && b->uniform_p) {
+            int slots = 0;
+            pb_status st = resident_slots(reinterpret_cast<const void *>(kern), kFvThreads, &slots);
+            if (st != PB_OK) return st;
+            const long long planes = (long long)b->K * b->p[0];
+            plan.planes = planes;
+            plan.n_units = (int)std::min<long long>(slots, planes);
+        }
+        n_units = plan.n_units;
+        launch_main(b, kern, dim3(plan.n_units), dim3(kFvThreads), 0, s, qi, qo, ex, b->d_patches, plan, ctrl, part,
+                    slot_in, dt_fixed, chain, ph);
+        return PB_OK;
+    };
+    pb_status lst = PB_OK;
     if constexpr (Ph::E > 0) {  // SRHD: dt comes from the con2prim pass
-        launch_main(b, fv_step_kernel<Ph, DIM, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
-                           ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
-                           slot_in, dt_fixed, chain, ph);
+        lst = plane_kernel(fv_step_kernel<Ph, DIM, T, false>);
     } else if (DIM == 3 && b->fv_dma && fv_dma_eligible(b)) {
         if (dt_fixed > 0.0)
             launch_main(b, fv_step_dma_kernel<Ph, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi, qo,
@@ -887,14 +966,11 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
                                chain, ph);
     } else {
         if (dt_fixed > 0.0)
-            launch_main(b, fv_step_kernel<Ph, DIM, T, false>, dim3(n_units), dim3(kFvThreads), 0, s, qi,
-                               qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
-                               slot_in, dt_fixed, chain, ph);
+            lst = plane_kernel(fv_step_kernel<Ph, DIM, T, false>);
         else
-            launch_main(b, fv_step_kernel<Ph, DIM, T, true>, dim3(n_units), dim3(kFvThreads), 0, s, qi,
-                               qo, ex, b->d_patches, n_units, n_slabs, slab, b->fv_xcd_remap, ctrl, part,
-                               slot_in, dt_fixed, chain, ph);
+            lst = plane_kernel(fv_step_kernel<Ph, DIM, T, true>);
     }
+    if (lst != PB_OK) return lst;
     PB_HIP(hipGetLastError());
     if (!(dt_fixed > 0.0) && Ph::E == 0 && step < 0) {
         pb_status st = launch_dt_reduce(b, part, n_units, DIM, slot_in ^ 1, cfl, true, false, s);

@@ -47,6 +47,7 @@ pb_tuning current(const pb_batch *b)
     t.fd_wg_per_cu = b->fd_wg_per_cu;
     t.fv_dma = b->fv_dma;
     t.fd_ws = b->fd_ws;
+    t.fv_persist = b->fv_persist;
     return t;
 }
 
@@ -58,6 +59,7 @@ void apply(pb_batch *b, const pb_tuning &t)
     b->fd_wg_per_cu = t.fd_wg_per_cu == 0 ? 2 : t.fd_wg_per_cu;
     b->fv_dma = t.fv_dma;
     b->fd_ws = t.fd_ws;
+    b->fv_persist = t.fv_persist;
 }
 
 std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
@@ -74,14 +76,32 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
         } else {
             slabs.push_back(0);
         }
-        const int dma_hi = fv_dma_eligible(b) ? 1 : 0;
-        for (int dma = dma_hi; dma >= 0; --dma)
+        if (b->dim == 3 && b->uniform_p)
+            for (int remap = 1; remap >= 0; --remap) {
+                pb_tuning t = base;
+                t.fv_persist = 1;
+                t.fv_dma = 0;
+                t.fv_slab = 0;
+                t.fv_xcd_remap = remap;
+                c.push_back(t);
+            }
+        for (int remap = 1; remap >= 0; --remap)
+            for (int s : slabs) {
+                pb_tuning t = base;
+                t.fv_persist = 0;
+                t.fv_slab = s;
+                t.fv_xcd_remap = remap;
+                t.fv_dma = 0;
+                c.push_back(t);
+            }
+        if (fv_dma_eligible(b))
             for (int remap = 1; remap >= 0; --remap)
-                for (int s : slabs) {
+                for (int i = 0; i < 2 && i < (int)slabs.size(); ++i) {
                     pb_tuning t = base;
-                    t.fv_slab = s;
+                    t.fv_persist = 0;
+                    t.fv_slab = slabs[i];
                     t.fv_xcd_remap = remap;
-                    t.fv_dma = dma;
+                    t.fv_dma = 1;
                     c.push_back(t);
                 }
     } else {
@@ -229,7 +249,8 @@ pb_status pb_autotune_cache_save(const char *path)
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &e : g_cache)
         f << e.first << ' ' << e.second.fv_slab << ' ' << e.second.fv_xcd_remap << ' ' << e.second.fd_xcd_remap << ' '
-          << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << ' ' << e.second.fd_ws << '\n';
+          << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << ' ' << e.second.fd_ws << ' ' << e.second.fv_persist
+          << '\n';
     if (!f) { set_error(std::string("write failed: ") + path); return PB_EINVAL; }
     return PB_OK;
     PB_API_END
@@ -250,8 +271,13 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
         std::istringstream in(line);
         std::string key, extra;
         pb_tuning t{};
-        if (!(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu >> t.fv_dma >> t.fd_ws) ||
-            (in >> extra) ||
+        bool ok = (bool)(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu >> t.fv_dma >>
+                         t.fd_ws);
+        if (ok && !(in >> t.fv_persist)) {   // six-field line: slab mode
+            t.fv_persist = 0;
+            in.clear();
+        }
+        if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 1 ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
             t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
             t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 1) {
