@@ -127,19 +127,25 @@ def test_autotune_rejects_bad_arguments_without_gpu():
 
 
 def test_autotune_cache_file_round_trip(tmp_path):
-    """the tuning cache is host-side: entries load, save and reload unchanged;
-    a malformed line is rejected with the entries before it kept"""
+    """the tuning cache is host-side: entries load, save and reload unchanged
+    (a six-field line, written before the balanced FV schedule existed, loads
+    as slab mode); a malformed line is rejected with the entries before it
+    kept"""
     pb.pb_autotune_cache_clear()
     src = tmp_path / "in.txt"
-    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0\n")
+    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0\n")
     assert pb.pb_autotune_cache_load(str(src)) == 2
     out = tmp_path / "out.txt"
     pb.pb_autotune_cache_save(str(out))
     lines = sorted(out.read_text().splitlines())
-    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1",
-                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0"])
+    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1",
+                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0 0"])
     bad = tmp_path / "bad.txt"
     bad.write_text("fv/x 4 1 1 2 1 1\nfv/y 99 1 1 2 1 1\nfv/z 4 1 1 2 1 1\n")
+    with pytest.raises(pb.PbError, match="bad2.txt:1"):
+        bad2 = tmp_path / "bad2.txt"
+        bad2.write_text("fv/w 4 1 1 2 1 1 7\n")
+        pb.pb_autotune_cache_load(str(bad2))
     with pytest.raises(pb.PbError, match="bad.txt:2"):
         pb.pb_autotune_cache_load(str(bad))
     pb.pb_autotune_cache_save(str(out))
