@@ -223,7 +223,7 @@ def tune(B, kind, **kw):
     def name(t):
         if kind == "fv":
             if t.get("fv_persist"):
-                return f"balanced/remap{t['fv_xcd_remap']}"
+                return f"balanced{t['fv_persist']}/remap{t['fv_xcd_remap']}"
             return f"slab{t['fv_slab']}/remap{t['fv_xcd_remap']}/dma{t['fv_dma']}"
         if t["fd_ws"]:
             return f"ws/remap{t['fd_xcd_remap']}"

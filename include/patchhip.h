@@ -269,10 +269,51 @@ pb_status pb_mlp_forward(const pb_mlp *m, const void *x, void *y, int64_t n, voi
 pb_status pb_mlp_grad(const pb_mlp *m, const void *x, const void *t, int64_t n, void *grad,
                       void *loss, void *stream);
 /* one Adam step on a batch: grad + update of the FP32 master weights and their
- * bfloat16 copies.  step is the 1-based Adam step counter. */
+ * bfloat16 copies.  step is the 1-based Adam step counter.
+ * Forward and backward run on the matrix cores (bf16 operands, FP32
+ * accumulation; dh1 and dh2 are rounded to bf16 for the products), the
+ * reduction over rows in a fixed order (bitwise reproducible).  Uses the
+ * MLP's own partial-gradient buffer (allocated by pb_mlp_create), so calls on
+ * one MLP must not overlap. */
 pb_status pb_mlp_train_step(pb_mlp *m, const void *x, const void *t, int64_t n, float lr,
                             float beta1, float beta2, float eps, int32_t step, void *loss,
                             void *stream);
+
+/* Training-set preparation on the device (the trainer then only allocates).
+ * pb_mlp_prepare: cons device SoA [5][n] doubles and their pressures p device
+ *   [n] doubles -> raw features x device [n][5] FP32 (as pb_mlp_features) and
+ *   targets y device [n] FP32 = binary32(log(p / E)) with E = tau + D, formed
+ *   in FP64.  n = 0 does nothing. */
+pb_status pb_mlp_prepare(const void *cons, const void *p, void *x, void *y, int64_t n, void *stream);
+/* pb_mlp_fit_norm: means and standard deviations (divisor n - 1) of the five
+ * feature columns of x [n][5] and of y [n], accumulated in FP64 in a fixed
+ * order, stored (rounded to binary32) as the MLP's normalisation block
+ * x_mean, x_std (floored at 1e-6), y_mean, y_std; the inference operands are
+ * refreshed.  n >= 2.  Asynchronous on stream. */
+pb_status pb_mlp_fit_norm(pb_mlp *m, const void *x, const void *y, int64_t n, void *stream);
+/* pb_mlp_standardise_target: t[i] = binary32((y[i] - y_mean) / y_std) in FP64
+ * with the MLP's binary32 y_mean, y_std (device [n] FP32 in and out). */
+pb_status pb_mlp_standardise_target(const pb_mlp *m, const void *y, void *t, int64_t n, void *stream);
+/* pb_mlp_permutation: idx device [n] int64 = the seeded permutation of
+ * [0, n) that pb_mlp_train_epoch walks for (seed, epoch): a balanced
+ * four-round Feistel network on 2h bits with cycle walking into [0, n)
+ * (Black & Rogaway, "Ciphers with arbitrary finite domains", 2002), h the
+ * smallest value with 2^(2h) >= n (and 2h >= 2), key = mix(seed + (epoch + 1)
+ * 0x9E3779B97F4A7C15), round function mix(key ^ (r + 1) 0x9E3779B97F4A7C15 ^ R)
+ * masked to h bits (r = 0..3, L, R <- R, L ^ F), mix = the SplitMix64
+ * finaliser (Steele, Lea & Flood, OOPSLA 2014); the value is L 2^h + R. */
+pb_status pb_mlp_permutation(uint64_t seed, int64_t epoch, int64_t n, void *idx, void *stream);
+/* pb_mlp_train_epoch: floor(n / batch) Adam steps (as pb_mlp_train_step) on
+ * the rows x[idx[b batch + j]], t[idx[b batch + j]] (j < batch) of the
+ * permutation idx of (seed, epoch), gathered inside the training kernel.
+ * Step s = step0 + b + 1 uses lr = binary32(lr_max (1 + cos(pi (s - 1) /
+ * total_steps)) / 2).  loss_sum (device double [1], nullable) accumulates
+ * the batch losses.  Errors: batch < 1 or > n, total_steps < step0 + the
+ * epoch's steps, bad Adam hyper-parameters. */
+pb_status pb_mlp_train_epoch(pb_mlp *m, const void *x, const void *t, int64_t n, int32_t batch,
+                             uint64_t seed, int32_t epoch, float lr_max, int64_t step0,
+                             int64_t total_steps, float beta1, float beta2, float eps,
+                             void *loss_sum, void *stream);
 
 /* ---------------------------------------------------------- measurement -- */
 
@@ -314,14 +355,16 @@ typedef struct {
                                  0 = the kernel in which every wave does every
                                  phase (fd_wg_per_cu applies to it); both give
                                  bitwise equal results */
-    int32_t fv_persist;       /* FV 3D, batches of one p (register kernel): 1 =
-                                 one work-group per resident slot, each marching
-                                 an equal run of the batch's K*p planes (patch
-                                 after patch), so no partly filled last round
-                                 of work-groups; fv_slab is then unused.  0 =
-                                 one work-group per slab (fv_slab).  Results
-                                 differ from slab mode only where a slab seam
-                                 would change the order of additions. */
+    int32_t fv_persist;       /* FV 3D, batches of one p (register kernel):
+                                 w in 1..8 = a grid of w work-groups per CU,
+                                 each marching an equal run of the batch's K*p
+                                 planes (patch after patch): with w no larger
+                                 than the work-groups a CU holds at once there
+                                 is no partly filled last round; fv_slab is
+                                 then unused.  0 = one work-group per slab
+                                 (fv_slab), the default.  Results differ from
+                                 slab mode only where a slab seam changes the
+                                 order of additions. */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
@@ -336,7 +379,7 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  * kind 0 = the finite-volume step (fv_rusanov_step with the given cfl /
  * dt_fixed), kind 1 = one FD4+KO6 stage (fd_ko_step with sigma_ko; cfl /
  * dt_fixed as there).  Candidates:
- *   FV 3D: fv_persist 1 x fv_xcd_remap {1, 0} (batches of one p), then
+ *   FV 3D: fv_persist {3, 2} x fv_xcd_remap {1, 0} (batches of one p), then
  *          fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0},
  *          then the DMA-fed kernel with fv_slab in {p_max, p_max/2} x
  *          fv_xcd_remap {1, 0} where it applies;

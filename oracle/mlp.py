@@ -132,3 +132,29 @@ def guess(params, norm, cons, bf16=True):
         y = y.astype(np.float32).astype(np.float64)  # the GPU output is binary32
     E = cons[4] + cons[0]
     return E * np.exp(float(np.float32(norm[10])) + float(np.float32(norm[11])) * y)
+
+
+def target(cons, p) -> np.ndarray:
+    """training target log(p / E), E = tau + D, in float64, rounded to float32"""
+    cons = np.asarray(cons, dtype=np.float64)
+    E = cons[4] + cons[0]
+    return np.log(np.asarray(p, dtype=np.float64) / E).astype(np.float32)
+
+
+def fit_norm(x, y) -> np.ndarray:
+    """normalisation block of a training set: per feature column and for the
+    target, the mean and the standard deviation with divisor n - 1 (feature
+    deviations floored at 1e-6), in float64, rounded to float32:
+    [x_mean(5), x_std(5), y_mean, y_std]"""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    xm = x.mean(axis=0)
+    xs = np.maximum(x.std(axis=0, ddof=1), 1e-6)
+    return np.concatenate([xm, xs, [y.mean(), y.std(ddof=1)]]).astype(np.float32)
+
+
+def standardise_target(y, norm) -> np.ndarray:
+    """(y - y_mean) / y_std in float64 with the float32 statistics, rounded to
+    float32"""
+    n = np.asarray(norm, dtype=np.float32).astype(np.float64)
+    return ((np.asarray(y, dtype=np.float32).astype(np.float64) - n[10]) / n[11]).astype(np.float32)

@@ -129,6 +129,12 @@ def lib():
         L.pb_mlp_grad.argtypes = [vp, vp, vp, C.c_int64, vp, vp, vp]
         L.pb_mlp_train_step.argtypes = [vp, vp, vp, C.c_int64, C.c_float, C.c_float, C.c_float, C.c_float,
                                         C.c_int32, vp, vp]
+        L.pb_mlp_prepare.argtypes = [vp, vp, vp, vp, C.c_int64, vp]
+        L.pb_mlp_fit_norm.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.pb_mlp_standardise_target.argtypes = [vp, vp, vp, C.c_int64, vp]
+        L.pb_mlp_permutation.argtypes = [C.c_uint64, C.c_int64, C.c_int64, vp, vp]
+        L.pb_mlp_train_epoch.argtypes = [vp, vp, vp, C.c_int64, C.c_int32, C.c_uint64, C.c_int32, C.c_float,
+                                         C.c_int64, C.c_int64, C.c_float, C.c_float, C.c_float, vp, vp]
         L.pb_offload_create.argtypes = [C.POINTER(OffloadDesc), C.POINTER(vp)]
         L.pb_offload_destroy.argtypes = [vp]
         L.pb_offload_fv_step.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), dp, C.c_double,
@@ -140,7 +146,9 @@ def lib():
                      "pb_autotune_cache_save", "pb_autotune_cache_load", "pb_autotune_cache_clear", "pb_batch_set_c2p_guess", "pb_batch_profile",
                      "pb_batch_profile_read", "pb_stream_copy", "fv_rusanov_step",
                      "fd_ko_step", "con2prim", "pb_mlp_create", "pb_mlp_destroy", "pb_mlp_set_params",
-                     "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_features", "pb_mlp_grad", "pb_mlp_train_step"):
+                     "pb_mlp_get_params", "pb_mlp_forward", "pb_mlp_features", "pb_mlp_grad", "pb_mlp_train_step",
+                     "pb_mlp_prepare", "pb_mlp_fit_norm", "pb_mlp_standardise_target", "pb_mlp_permutation",
+                     "pb_mlp_train_epoch"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -296,6 +304,48 @@ class Mlp:
     def train_step(self, x, t, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
         _check(lib().pb_mlp_train_step(self.handle, _ptr(x), _ptr(t), x.shape[0], lr, beta1, beta2, eps, step,
                                        _ptr(loss), _stream()), "pb_mlp_train_step")
+
+    def fit_norm(self, x, y):
+        """normalisation statistics of the training set (device) -> this
+        network's normalisation block"""
+        _check(lib().pb_mlp_fit_norm(self.handle, _ptr(x), _ptr(y), x.shape[0], _stream()), "pb_mlp_fit_norm")
+
+    def standardise_target(self, y):
+        """t = (y - y_mean) / y_std with this network's statistics (device)"""
+        import torch
+        t = torch.empty_like(y)
+        _check(lib().pb_mlp_standardise_target(self.handle, _ptr(y), _ptr(t), y.shape[0], _stream()),
+               "pb_mlp_standardise_target")
+        return t
+
+    def train_epoch(self, x, t, batch, seed, epoch, lr_max, step0, total_steps, loss_sum=None, beta1=0.9,
+                    beta2=0.999, eps=1e-8):
+        """one epoch of Adam steps over batches of the seeded permutation of
+        the rows (cosine learning rate over total_steps); loss_sum (device
+        float64 [1], nullable) accumulates the batch losses"""
+        _check(lib().pb_mlp_train_epoch(self.handle, _ptr(x), _ptr(t), x.shape[0], batch, seed, epoch, lr_max, step0,
+                                        total_steps, beta1, beta2, eps, _ptr(loss_sum), _stream()),
+               "pb_mlp_train_epoch")
+
+
+def pb_mlp_prepare(cons, p):
+    """training inputs of conserved states cons [5, n] (float64 device) and
+    their pressures p [n]: raw features [n, 5] and targets log(p/E) [n]
+    (float32 device)"""
+    import torch
+    n = cons.shape[-1]
+    x = torch.empty((n, MLP_IN), dtype=torch.float32, device=cons.device)
+    y = torch.empty(n, dtype=torch.float32, device=cons.device)
+    _check(lib().pb_mlp_prepare(_ptr(cons), _ptr(p), _ptr(x), _ptr(y), n, _stream()), "pb_mlp_prepare")
+    return x, y
+
+
+def pb_mlp_permutation(seed, epoch, n, device="cuda"):
+    """the library's seeded permutation of [0, n) for (seed, epoch) (int64 device)"""
+    import torch
+    idx = torch.empty(n, dtype=torch.int64, device=device)
+    _check(lib().pb_mlp_permutation(seed, epoch, n, _ptr(idx), _stream()), "pb_mlp_permutation")
+    return idx
 
 
 def pb_mlp_features(cons):

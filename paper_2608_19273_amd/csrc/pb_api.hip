@@ -365,13 +365,14 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     if (!b || !t) { set_error("NULL argument"); return PB_EINVAL; }
     if (t->fv_slab < 0 || t->fv_slab > kFvPmax) { set_error("fv_slab must be in [0, 16]"); return PB_EINVAL; }
     if (t->fd_wg_per_cu < 0 || t->fd_wg_per_cu > 2) { set_error("fd_wg_per_cu must be 0, 1 or 2"); return PB_EINVAL; }
+    if (t->fv_persist < 0 || t->fv_persist > 8) { set_error("fv_persist must be in [0, 8]"); return PB_EINVAL; }
     b->fv_slab = t->fv_slab;
     b->fv_xcd_remap = t->fv_xcd_remap ? 1 : 0;
     b->fd_xcd_remap = t->fd_xcd_remap ? 1 : 0;
     b->fd_wg_per_cu = t->fd_wg_per_cu == 0 ? 2 : t->fd_wg_per_cu;
     b->fv_dma = t->fv_dma ? 1 : 0;
     b->fd_ws = t->fd_ws ? 1 : 0;
-    b->fv_persist = t->fv_persist ? 1 : 0;
+    b->fv_persist = t->fv_persist;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     return PB_OK;

@@ -250,7 +250,7 @@ struct pb_batch {
     int fd_wg_per_cu = 2;
     int fd_ws = 1;   // linear-system FD: wave-specialised kernel
     int fv_dma = 0;
-    int fv_persist = 1;   // FV 3D, one p: balanced plane schedule over resident work-groups
+    int fv_persist = 0;   // FV 3D, one p: > 0 = balanced plane schedule over this many work-groups per CU
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;

@@ -122,8 +122,9 @@ template <> struct PlaneAux<Srhd> {
 // work-group (unit) u marches slab u % n_slabs of patch u / n_slabs (a slab
 // can start beyond the last plane of a patch smaller than the batch maximum:
 // such a unit only takes part in the reductions).  Balanced mode (uniform
-// patch size p, plan.planes = K p planes in patch order): the grid is the
-// number of resident work-groups and work-group r marches the planes
+// patch size p, plan.planes = K p planes in patch order): the grid is a
+// chosen number of work-groups per CU (those that fit at once: no second
+// round) and work-group r marches the planes
 // [r T / G, (r + 1) T / G) of that sequence, one segment per patch it
 // crosses, so every work-group moves the same number of planes and the last
 // round of a grid of whole patches, partly filled, disappears.
@@ -873,28 +874,20 @@ __global__ void ctrl_init_kernel(Ctrl *ctrl)
 
 namespace {
 
-// work-groups of `kern` (block threads, no dynamic LDS) resident at once on
-// the current device: occupancy per CU times the CU count, cached per kernel
-// and device
-pb_status resident_slots(const void *kern, int threads, int *out)
+// compute units of the current device (cached per device)
+pb_status device_cus(int *out)
 {
-    struct Entry { const void *k; int dev, slots; };
     static std::mutex mu;
-    static std::vector<Entry> cache;
+    static std::vector<std::pair<int, int>> cache;
     int dev = 0;
     PB_HIP(hipGetDevice(&dev));
-    {
-        std::lock_guard<std::mutex> g(mu);
-        for (const Entry &e : cache)
-            if (e.k == kern && e.dev == dev) { *out = e.slots; return PB_OK; }
-    }
-    int per_cu = 0, cus = 0;
-    PB_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, 0));
-    PB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int slots = std::max(1, per_cu) * std::max(1, cus);
     std::lock_guard<std::mutex> g(mu);
-    cache.push_back({kern, dev, slots});
-    *out = slots;
+    for (const auto &e : cache)
+        if (e.first == dev) { *out = e.second; return PB_OK; }
+    int cus = 0;
+    PB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    cache.push_back({dev, std::max(1, cus)});
+    *out = std::max(1, cus);
     return PB_OK;
 }
 
@@ -939,10 +932,11 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     // over the work-groups that are resident at once (uniform p)
     FvPlan plan{n_units, n_slabs, slab, b->fv_xcd_remap, 0};
     auto plane_kernel = [&](auto kern) -> pb_status {
-        if (DIM == 3 && b->fv_persist && b->uniform_p) {
-            int slots = 0;
-            pb_status st = resident_slots(reinterpret_cast<const void *>(kern), kFvThreads, &slots);
+        if (DIM == 3 && b->fv_persist > 0 && b->uniform_p) {
+            int cus = 0;
+            pb_status st = device_cus(&cus);
             if (st != PB_OK) return st;
+            const long long slots = (long long)b->fv_persist * cus;
             const long long planes = (long long)b->K * b->p[0];
             plan.planes = planes;
             plan.n_units = (int)std::min<long long>(slots, planes);

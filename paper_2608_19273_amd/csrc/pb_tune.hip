@@ -77,9 +77,10 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
             slabs.push_back(0);
         }
         if (b->dim == 3 && b->uniform_p)
+            for (int wgs = 3; wgs >= 2; --wgs)
             for (int remap = 1; remap >= 0; --remap) {
                 pb_tuning t = base;
-                t.fv_persist = 1;
+                t.fv_persist = wgs;
                 t.fv_dma = 0;
                 t.fv_slab = 0;
                 t.fv_xcd_remap = remap;
@@ -277,7 +278,7 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
             t.fv_persist = 0;
             in.clear();
         }
-        if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 1 ||
+        if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 8 ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
             t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
             t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 1) {

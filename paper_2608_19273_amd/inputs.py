@@ -529,3 +529,41 @@ def config2_subset(seed: int = 2, n_per_size=(16, 16, 16)):
             chosen.append(int(where[j]))
         sel += chosen
     return sorted(sel)
+
+
+# ------------------------------------------------------ training batches --
+
+
+def feistel_permutation(seed: int, epoch: int, n: int) -> np.ndarray:
+    """The seeded permutation of [0, n) that orders the training rows of one
+    epoch: a balanced four-round Feistel network on 2h bits (h the smallest
+    value with 2^(2h) >= n, 2h >= 2) with cycle walking into [0, n) (Black &
+    Rogaway, "Ciphers with arbitrary finite domains", CT-RSA 2002).  Key =
+    mix(seed + (epoch + 1) G), round r (0..3): L, R <- R, L ^ (mix(key ^
+    (r + 1) G ^ R) & (2^h - 1)), value L 2^h + R; mix is the SplitMix64
+    finaliser, G = 0x9E3779B97F4A7C15.  Returns int64 [n]."""
+    if n == 0:
+        return np.zeros(0, np.int64)
+    m = 2
+    while m < 62 and (1 << m) < n:
+        m += 1
+    h = (m + 1) // 2
+    mask = np.uint64((1 << h) - 1)
+    with np.errstate(over="ignore"):
+        key = _mix(np.array([np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + np.uint64(epoch + 1) * _GOLDEN],
+                            dtype=np.uint64))[0]
+        rk = [key ^ (np.uint64(r + 1) * _GOLDEN) for r in range(4)]
+
+        def perm(v):
+            L, R = v >> np.uint64(h), v & mask
+            for r in range(4):
+                f = _mix(rk[r] ^ R) & mask
+                L, R = R, L ^ f
+            return (L << np.uint64(h)) | R
+
+        v = perm(np.arange(n, dtype=np.uint64))
+        todo = v >= np.uint64(n)
+        while todo.any():
+            v[todo] = perm(v[todo])
+            todo = v >= np.uint64(n)
+    return v.astype(np.int64)

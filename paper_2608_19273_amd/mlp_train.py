@@ -3,10 +3,14 @@
 Pairs (conserved state, pressure) come from the seeded SRHD primitive
 distribution of the SRHD workload (rho, eps log-uniform in [1e-3, 10],
 Lorentz factor uniform in [1, 10], isotropic velocity) mapped to conserved
-variables by the input generator.  Features are computed on the GPU by
-pb_mlp_features; the target is log(p/E), standardised.  Each optimisation
-step is one pb_mlp_train_step call (forward, backward, weight gradients and an
-Adam update on the device).
+variables by the input generator.  Everything after that runs in the library
+(torch only allocates the device buffers):
+  pb_mlp_prepare             raw features and the target log(p/E),
+  pb_mlp_fit_norm            their means and standard deviations,
+  pb_mlp_standardise_target  the standardised target,
+  pb_mlp_train_epoch         per epoch, Adam steps on batches of a seeded
+                             permutation of the rows (forward, backward and
+                             update on the matrix cores), cosine learning rate.
 """
 from __future__ import annotations
 
@@ -14,7 +18,7 @@ import math
 
 import numpy as np
 
-from . import MLP_HID, MLP_IN, MLP_NPARAM, Mlp, pb_mlp_features
+from . import MLP_HID, MLP_IN, MLP_NPARAM, Mlp, pb_mlp_prepare
 from . import inputs as I
 
 
@@ -30,48 +34,36 @@ def he_init(seed: int) -> np.ndarray:
 
 
 def dataset(seed: int, n: int, device="cuda"):
-    """raw features x [n, 5] (float32, device), log(p/E) [n] (float64, device),
-    conserved states [5, n] (float64, device)"""
+    """raw features x [n, 5] and targets log(p/E) [n] (float32, device, made by
+    the library), conserved states [5, n] (float64, device)"""
     import torch
     cons, p = I.srhd_training_pairs(seed, n)
     c = torch.from_numpy(np.ascontiguousarray(cons)).to(device)
-    x = pb_mlp_features(c)
-    E = c[4] + c[0]
-    y = torch.log(torch.from_numpy(p).to(device) / E)
+    pt = torch.from_numpy(np.ascontiguousarray(p)).to(device)
+    x, y = pb_mlp_prepare(c, pt)
     return x, y, c
 
 
+# placeholder statistics until pb_mlp_fit_norm replaces them on the device
+_UNIT_NORM = np.array([0.0] * 5 + [1.0] * 5 + [0.0, 1.0], np.float32)
+
+
 def train(n_pairs=1 << 22, epochs=20, batch=8192, lr=3e-3, seed=2024, data_seed=77, device="cuda", log=None):
-    """Returns (Mlp, history dict).  Cosine learning-rate decay over all steps."""
+    """Returns (Mlp, history dict): per-epoch mean batch loss, step count and
+    the fitted normalisation.  Cosine learning-rate decay over all steps."""
     import torch
     x, y, _ = dataset(data_seed, n_pairs, device)
-    xm = x.double().mean(0)
-    xs = x.double().std(0).clamp_min(1e-6)
-    ym, ys = y.mean(), y.std()
-    norm = np.concatenate([xm.cpu().numpy(), xs.cpu().numpy(), [ym.item(), ys.item()]]).astype(np.float32)
-    t = ((y - float(norm[10])) / float(norm[11])).float()
-    net = Mlp(he_init(seed), norm)
-    g = torch.Generator(device=device)
-    g.manual_seed(seed)
+    net = Mlp(he_init(seed), _UNIT_NORM)
+    net.fit_norm(x, y)
+    t = net.standardise_target(y)
     steps_per_epoch = n_pairs // batch
     total = epochs * steps_per_epoch
-    loss = torch.zeros(1, dtype=torch.float32, device=device)
-    hist = {"epoch_loss": []}
-    step = 0
+    loss_sum = torch.zeros(epochs, dtype=torch.float64, device=device)
     for ep in range(epochs):
-        perm = torch.randperm(n_pairs, generator=g, device=device)
-        acc = torch.zeros((), dtype=torch.float64, device=device)
-        for b in range(steps_per_epoch):
-            idx = perm[b * batch:(b + 1) * batch]
-            xb = x.index_select(0, idx).contiguous()
-            tb = t.index_select(0, idx).contiguous()
-            step += 1
-            lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * (step - 1) / total))
-            net.train_step(xb, tb, lr_t, step, loss=loss)
-            acc += loss[0].double()
-        hist["epoch_loss"].append(acc.item() / steps_per_epoch)
+        net.train_epoch(x, t, batch, seed, ep, lr, ep * steps_per_epoch, total, loss_sum=loss_sum[ep:])
         if log:
-            log(f"epoch {ep + 1}/{epochs}: mean batch loss {hist['epoch_loss'][-1]:.3e}")
-    hist["steps"] = step
-    hist["norm"] = norm
+            log(f"epoch {ep + 1}/{epochs} queued")
+    sums = loss_sum.cpu().numpy()
+    hist = {"epoch_loss": [float(v) / steps_per_epoch for v in sums], "steps": total,
+            "norm": net.get_params()[1]}
     return net, hist

@@ -144,7 +144,7 @@ def test_autotune_cache_file_round_trip(tmp_path):
     bad.write_text("fv/x 4 1 1 2 1 1\nfv/y 99 1 1 2 1 1\nfv/z 4 1 1 2 1 1\n")
     with pytest.raises(pb.PbError, match="bad2.txt:1"):
         bad2 = tmp_path / "bad2.txt"
-        bad2.write_text("fv/w 4 1 1 2 1 1 7\n")
+        bad2.write_text("fv/w 4 1 1 2 1 1 9\n")
         pb.pb_autotune_cache_load(str(bad2))
     with pytest.raises(pb.PbError, match="bad.txt:2"):
         pb.pb_autotune_cache_load(str(bad))

@@ -62,7 +62,8 @@ def test_euler3d_balanced_schedule(grid, storage):
     32 patches (fewer planes than slots: one plane per work-group), 256
     patches (runs of 5-6 planes crossing patches) and 768 patches (16 planes
     per slot, runs starting mid-patch); against the oracle, against slab mode
-    to roundoff, bitwise repeatable, both XCD orders."""
+    to roundoff, bitwise repeatable, both XCD orders, 2, 3 and 5
+    work-groups per CU (5: more than fit at once, so a second round)."""
     announce(f"euler3d balanced schedule {grid} {storage}")
     b = I.config1(grid=grid)
     tol = 1e-12
@@ -71,13 +72,13 @@ def test_euler3d_balanced_schedule(grid, storage):
         tol = 1e-5
     o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=3, round_fp32=storage == "fp32")
     gs, _, _ = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_slab": 0, "fv_xcd_remap": 1})
-    for remap in (1, 0):
-        g, dt, st = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_persist": 1, "fv_xcd_remap": remap})
+    for wgs, remap in ((3, 1), (3, 0), (2, 1), (5, 1)):
+        g, dt, st = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_persist": wgs, "fv_xcd_remap": remap})
         assert np.all(rel_err(b, g, o) <= tol), rel_err(b, g, o)
         assert np.all(rel_err(b, g, gs) <= (1e-14 if storage == "fp64" else 1e-6))
         assert abs(dt - dts[-1]) <= 1e-13 * dts[-1]
         assert st["nonfinite_units"] == 0
-        g2, _, _ = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_persist": 1, "fv_xcd_remap": remap})
+        g2, _, _ = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_persist": wgs, "fv_xcd_remap": remap})
         np.testing.assert_array_equal(g, g2)
 
 

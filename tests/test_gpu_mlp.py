@@ -29,25 +29,15 @@ def test_features_match_oracle():
     np.testing.assert_allclose(x, M.features(cons).astype(np.float32), rtol=2e-6, atol=2e-6)
 
 
-def _bf16_clear(v, err):
-    """True where a binary32 value v lies farther than `err` from the nearest
-    bf16 rounding midpoint (so any value within err of v rounds to the same
-    bf16 number); zeros (ReLU-clipped) are clear"""
-    v32 = np.asarray(v, np.float32)
-    u = v32.view(np.uint32).astype(np.int64)
-    frac = np.abs((u & 0xFFFF) - 0x8000) / 65536.0          # in bf16 ulps
-    a = np.abs(v32.astype(np.float64))
-    ulp = np.exp2(np.floor(np.log2(np.where(a > 0, a, 1.0))) - 7)
-    return (a == 0) | (frac * ulp > err)
-
-
 def test_forward_matches_oracle():
-    """Per row: where every bf16 rounding of the hidden activations lies
-    farther from a rounding midpoint than twice the FP32 accumulation bound of
-    its dot product ((K+1) 2^-24 sum |terms|), both sides round identically and
-    the outputs must agree to the FP32 accumulation bound of the last layer;
-    rows with an activation near a midpoint may flip one bf16 ulp and are
-    bounded in number."""
+    """Both sides round the same values to bf16 at the same points; they
+    differ by the FP32 (matrix cores) against FP64 (oracle) accumulation.
+    Most rows agree to the FP32 accumulation bound of the last layer, (K+1)
+    2^-24 sum |terms|; a hidden activation that lies within that accumulation
+    error of a bf16 rounding midpoint may round one bf16 ulp apart, so every
+    row must lie within the bound of one-ulp flips of its activations
+    (propagated through the weights), and such rows must stay a small
+    minority."""
     announce("mlp forward")
     torch = need_gpu()
     p, norm = random_net()
@@ -55,20 +45,98 @@ def test_forward_matches_oracle():
     x = (I.normal(12, 20000 * 5).reshape(20000, 5) * np.array([1.0, 0.2, 0.8, 1.0, 0.2]) + norm[:5]).astype(np.float32)
     y = net.forward(torch.from_numpy(x).cuda()).cpu().numpy()
     yo, (xb, h1, h2, W1, W2, w3) = M.forward(p, norm, x, keep=True)
-    _, b1, _, b2, _, b3 = M.unpack(p)
+    _, _, _, _, _, b3 = M.unpack(p)
     u = 2.0 ** -24
-    a1 = xb @ W1.T + b1
-    e1 = 6 * u * (np.abs(xb) @ np.abs(W1).T + np.abs(b1))
-    a2 = h1 @ W2.T + b2
-    e2 = 65 * u * (np.abs(h1) @ np.abs(W2).T + np.abs(b2))
-    clear = (_bf16_clear(np.maximum(a1, 0), 2 * e1) | (a1 + e1 < 0)).all(axis=1) & \
-            (_bf16_clear(np.maximum(a2, 0), 2 * e2) | (a2 + e2 < 0)).all(axis=1)
-    d = np.abs(y - yo)
     e3 = 65 * u * (np.abs(h2) @ np.abs(w3) + abs(b3))
-    assert clear.mean() > 0.5, clear.mean()
-    assert np.all(d[clear] <= e3[clear]), (d[clear] / e3[clear]).max()
-    assert np.all(d <= 2e-2 * (1 + np.abs(yo).max()))
+    ulp = lambda h: np.exp2(np.floor(np.log2(np.where(h > 0, h, 1.0))) - 7) * (h > 0)
+    flip = ulp(h2) @ np.abs(w3) + (ulp(h1) @ np.abs(W2).T) @ np.abs(w3)
+    d = np.abs(y - yo)
+    tight = d <= e3
+    assert tight.mean() >= 0.8, tight.mean()
+    assert np.all(d <= e3 + flip), np.max(d / (e3 + flip))
     net.close()
+
+
+def test_prepare_matches_oracle():
+    """pb_mlp_prepare: raw features within a few binary32 ulp of the oracle's
+    FP64 features (FP32 ratios and logarithms on the GPU), targets
+    binary32(log(p/E)) within one ulp (FP64 logarithms of both sides)"""
+    announce("mlp prepare")
+    torch = need_gpu()
+    cons, p = I.srhd_training_pairs(31, 50000)
+    x, y = pb.pb_mlp_prepare(torch.from_numpy(cons).cuda(), torch.from_numpy(p).cuda())
+    np.testing.assert_allclose(x.cpu().numpy(), M.features(cons).astype(np.float32), rtol=2e-6, atol=2e-6)
+    yo = M.target(cons, p)
+    yg = y.cpu().numpy()
+    assert np.all(np.abs(yg - yo) <= np.spacing(np.abs(yo)))
+
+
+def test_fit_norm_and_standardise_match_oracle():
+    """pb_mlp_fit_norm: means and standard deviations (FP64 sums in the
+    library's fixed order against numpy's) within one binary32 ulp; the
+    standardised target then bitwise equal to the oracle's with the same
+    statistics"""
+    announce("mlp fit_norm / standardise")
+    torch = need_gpu()
+    cons, p = I.srhd_training_pairs(32, 300001)
+    x, y = pb.pb_mlp_prepare(torch.from_numpy(cons).cuda(), torch.from_numpy(p).cuda())
+    net = pb.Mlp(*random_net(3))
+    net.fit_norm(x, y)
+    _, ng = net.get_params()
+    no = M.fit_norm(x.cpu().numpy(), y.cpu().numpy())
+    assert np.all(np.abs(ng - no) <= np.spacing(np.abs(no))), (ng, no)
+    t = net.standardise_target(y).cpu().numpy()
+    np.testing.assert_array_equal(t, M.standardise_target(y.cpu().numpy(), ng))
+    net.close()
+
+
+@pytest.mark.parametrize("n", [1, 7, 4096, 100003, 1 << 22])
+def test_permutation_matches_generator(n):
+    """the library's epoch permutation is bit for bit the one the input
+    generator defines, for sizes with and without cycle walking"""
+    announce(f"mlp permutation n={n}")
+    need_gpu()
+    for seed, epoch in ((2024, 0), (2024, 3), (5, 11)):
+        g = pb.pb_mlp_permutation(seed, epoch, n).cpu().numpy()
+        np.testing.assert_array_equal(g, I.feistel_permutation(seed, epoch, n))
+
+
+def test_train_epoch_equals_gathered_steps():
+    """pb_mlp_train_epoch (rows gathered inside the kernel through the epoch
+    permutation, cosine learning rate) gives bit for bit the parameters and
+    losses of pb_mlp_train_step calls on batches gathered on the host with
+    the generator's permutation and the same schedule"""
+    announce("mlp train_epoch")
+    torch = need_gpu()
+    import math
+    n, batch, seed, lr = 5000, 1024, 99, np.float32(3e-3)
+    x = torch.from_numpy((I.normal(40, n * 5).reshape(n, 5) * 0.8 + random_net()[1][:5]).astype(np.float32)).cuda()
+    t = torch.from_numpy(I.normal(41, n).astype(np.float32)).cuda()
+    p0, norm = random_net(42)
+    A = pb.Mlp(p0, norm)
+    Bn = pb.Mlp(p0, norm)
+    spe = n // batch
+    total = 2 * spe
+    ls = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ref = np.zeros(2)
+    for ep in range(2):
+        A.train_epoch(x, t, batch, seed, ep, float(lr), ep * spe, total, loss_sum=ls[ep:])
+        perm = torch.from_numpy(I.feistel_permutation(seed, ep, n)).cuda()
+        for b in range(spe):
+            step = ep * spe + b + 1
+            lr_t = float(np.float32(0.5 * float(lr) * (1.0 + math.cos(math.pi * (step - 1) / total))))
+            idx = perm[b * batch:(b + 1) * batch]
+            xb = x.index_select(0, idx).contiguous()
+            tb = t.index_select(0, idx).contiguous()
+            loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+            Bn.train_step(xb, tb, lr_t, step, loss=loss)
+            ref[ep] += float(loss.item())
+    pa, _ = A.get_params()
+    pbp, _ = Bn.get_params()
+    np.testing.assert_array_equal(pa, pbp)
+    np.testing.assert_allclose(ls.cpu().numpy(), ref, rtol=1e-12)
+    A.close()
+    Bn.close()
 
 
 def test_gradient_matches_oracle():

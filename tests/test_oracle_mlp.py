@@ -1,6 +1,8 @@
 """Pins of the MLP reference: bfloat16 rounding against torch's own
 conversion, a network with a closed-form output, and the hand-written
 backward pass against central finite differences."""
+import math
+
 import numpy as np
 import pytest
 
@@ -86,3 +88,43 @@ def test_standardise_is_the_quotient_up_to_rounding():
     q2 = ((x32 - norm2[:5]) / norm2[5:10]).astype(np.float32)
     ulp = np.spacing(np.abs(q2)).astype(np.float64)
     assert np.all(np.abs(z2 - q2.astype(np.float64)) <= 1.5 * ulp)
+
+
+def test_training_target_closed_form():
+    """log(p/E) of a cell at rest: tau = rho eps, E = rho (1 + eps) and
+    p = (Gamma - 1) rho eps, so p/E = (Gamma - 1) eps / (1 + eps)."""
+    rho = np.array([0.3, 2.0, 7.0])
+    eps = np.array([0.01, 0.5, 9.0])
+    z = np.zeros(3)
+    cons, p = I.srhd_prim_to_cons(rho, z, z, z, eps, 5 / 3)
+    t = M.target(cons, p)
+    np.testing.assert_allclose(t, np.log((2 / 3) * eps / (1 + eps)).astype(np.float32), rtol=1e-6)
+
+
+def test_fit_norm_closed_form():
+    """mean and sample standard deviation (divisor n - 1) of 1..n are
+    (n + 1)/2 and sqrt(n (n + 1) / 12); a constant column takes the 1e-6
+    floor (features only)."""
+    n = 1001
+    v = np.arange(1, n + 1, dtype=np.float64)
+    x = np.stack([v, 2 * v, -v, np.full(n, 3.0), v / 4], axis=1)
+    norm = M.fit_norm(x, v)
+    s = math.sqrt(n * (n + 1) / 12.0)
+    np.testing.assert_allclose(norm[:5], np.float32([(n + 1) / 2, n + 1, -(n + 1) / 2, 3.0, (n + 1) / 8]), rtol=1e-7)
+    np.testing.assert_allclose(norm[5:10], np.float32([s, 2 * s, s, 1e-6, s / 4]), rtol=1e-6)
+    np.testing.assert_allclose(norm[10:], np.float32([(n + 1) / 2, s]), rtol=1e-7)
+    t = M.standardise_target(v, norm)
+    np.testing.assert_allclose(t[[0, n // 2, n - 1]], [-(n - 1) / 2 / s, 0.0, (n - 1) / 2 / s], rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5, 1000, 4096, 12345])
+def test_training_permutation_is_a_seeded_bijection(n):
+    """the epoch permutation of the training rows covers [0, n) exactly once,
+    depends on seed and epoch, and is reproducible"""
+    a = I.feistel_permutation(2024, 0, n)
+    np.testing.assert_array_equal(np.sort(a), np.arange(n))
+    np.testing.assert_array_equal(a, I.feistel_permutation(2024, 0, n))
+    if n >= 1000:
+        assert np.mean(a != I.feistel_permutation(2024, 1, n)) > 0.99
+        assert np.mean(a != I.feistel_permutation(7, 0, n)) > 0.99
+        assert abs(np.corrcoef(np.arange(n), a)[0, 1]) < 0.1
