@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "pb_common.h"
@@ -579,8 +580,9 @@ int perm_half_bits(long long n)
 // forward + backward over n rows (mapped by rmap) into the partial buffer
 // `part`, then the fixed-order reduction (and Adam); shared by the entry
 // points that take the library's scratch and the one that takes a caller's
-pb_status run_grad_into(pb_mlp *m, float *part, const float *x, const float *t, long long n, const RowMap &rmap,
-                        hipStream_t s, int adam, float lr, float b1, float b2, float eps, int step, double *loss_acc)
+pb_status run_grad_into(pb_mlp *m, float *part, float *grad, float *loss, const float *x, const float *t, long long n,
+                        const RowMap &rmap, hipStream_t s, int adam, float lr, float b1, float b2, float eps, int step,
+                        double *loss_acc)
 {
     const long long nchunks = (n + 63) / 64;
     const int waves = (int)std::min<long long>(kTrainWavesMax, nchunks);
@@ -591,7 +593,7 @@ pb_status run_grad_into(pb_mlp *m, float *part, const float *x, const float *t, 
     const float bc1 = adam ? 1.f - std::pow(b1, (float)step) : 1.f;
     const float bc2 = adam ? 1.f - std::pow(b2, (float)step) : 1.f;
     hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kMlpNParam + 1 + kT - 1) / kT), dim3(kT), 0, s, part, waves, n,
-                       m->grad, m->loss, loss_acc, m->par, m->madam, m->vadam, adam, lr, b1, b2, eps, bc1, bc2);
+                       grad, loss, loss_acc, m->par, m->madam, m->vadam, adam, lr, b1, b2, eps, bc1, bc2);
     PB_HIP(hipGetLastError());
     if (adam) return refresh(m, s);
     return PB_OK;
@@ -600,7 +602,34 @@ pb_status run_grad_into(pb_mlp *m, float *part, const float *x, const float *t, 
 pb_status run_grad(pb_mlp *m, const float *x, const float *t, long long n, const RowMap &rmap, hipStream_t s, int adam,
                    float lr, float b1, float b2, float eps, int step, double *loss_acc)
 {
-    return run_grad_into(m, m->part, x, t, n, rmap, s, adam, lr, b1, b2, eps, step, loss_acc);
+    return run_grad_into(m, m->part, m->grad, m->loss, x, t, n, rmap, s, adam, lr, b1, b2, eps, step, loss_acc);
+}
+
+// The partial-gradient scratch of pb_mlp_grad_noalloc: one file-scope
+// device array (each GPU the library runs on holds its own copy until the
+// process ends).  Host code never passes the array's name to a kernel (on
+// the host it is a stand-in, not a device address): it takes the address
+// hipGetSymbolAddress reports for the current device, once per device.
+constexpr long long kNoAllocMaxRows = 1ll << 30;
+__device__ __align__(256) float scratch[kTrainWavesMax * kPartStride];
+
+pb_status scratch_address(float **out)
+{
+    constexpr int kMaxDev = 64;
+    static std::mutex mu;
+    static float *addr[kMaxDev] = {};
+    int dev = 0;
+    PB_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDev) { set_error("device index out of range"); return PB_EUNSUPPORTED; }
+    std::lock_guard<std::mutex> g(mu);
+    if (!addr[dev]) {
+        void *ptr = nullptr;
+        PB_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) { set_error("hipGetSymbolAddress(scratch) returned NULL"); return PB_EHIP; }
+        addr[dev] = static_cast<float *>(ptr);
+    }
+    *out = addr[dev];
+    return PB_OK;
 }
 
 bool adam_ok(float lr, float beta1, float beta2, float eps)
@@ -812,6 +841,26 @@ pb_status pb_mlp_grad(const pb_mlp *m, const void *x, const void *t, int64_t n, 
     PB_HIP(hipMemcpyAsync(grad, mm->grad, kMlpNParam * sizeof(float), hipMemcpyDeviceToDevice, s));
     PB_HIP(hipMemcpyAsync(loss, mm->loss, sizeof(float), hipMemcpyDeviceToDevice, s));
     return PB_OK;
+    PB_API_END
+}
+
+pb_status pb_mlp_grad_noalloc(const pb_mlp *m, const void *x, const void *t, int64_t n, void *grad, void *loss,
+                              void *stream)
+{
+    PB_API_BEGIN
+    if (!m || !x || !t || !grad || !loss) { set_error("NULL argument"); return PB_EINVAL; }
+    if (n < 1) { set_error("n must be >= 1"); return PB_EINVAL; }
+    if (n > kNoAllocMaxRows) {
+        set_error("pb_mlp_grad_noalloc: n exceeds the maximum of 2^30 rows");
+        return PB_EINVAL;
+    }
+    float *part = nullptr;
+    pb_status st = scratch_address(&part);
+    if (st != PB_OK) return st;
+    const RowMap ident{0, 0, 0ull, 0};
+    return run_grad_into(const_cast<pb_mlp *>(m), part, static_cast<float *>(grad), static_cast<float *>(loss),
+                         static_cast<const float *>(x), static_cast<const float *>(t), n, ident,
+                         static_cast<hipStream_t>(stream), 0, 0.f, 0.f, 0.f, 0.f, 1, nullptr);
     PB_API_END
 }
 
