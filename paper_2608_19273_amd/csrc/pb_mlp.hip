@@ -417,18 +417,34 @@ __global__ __launch_bounds__(64) void mlp_train_kernel(const MlpPack *__restrict
 
 // grad = fixed-order sum of the partial rows; loss = their loss sum / n
 // (added to *loss_acc when given); optionally one bias-corrected Adam step
-// on the masters
-__global__ __launch_bounds__(kT) void mlp_reduce_adam_kernel(const float *__restrict__ part, int rows, long long n,
-                                                             float *__restrict__ grad, float *__restrict__ loss,
-                                                             double *__restrict__ loss_acc, float *__restrict__ par,
-                                                             float *__restrict__ mo, float *__restrict__ vo, int adam,
-                                                             float lr, float b1, float b2, float eps, float bc1,
-                                                             float bc2)
+// on the masters.  A work-group takes 64 parameters; its four waves sum the
+// rows r = q (mod 4) (q the wave) in four interleaved accumulators each, and
+// wave 0 adds the four wave sums in order: the same order for every call
+// with the same row count.
+constexpr int kRedParams = 64;
+__global__ __launch_bounds__(256) void mlp_reduce_adam_kernel(const float *__restrict__ part, int rows, long long n,
+                                                              float *__restrict__ grad, float *__restrict__ loss,
+                                                              double *__restrict__ loss_acc, float *__restrict__ par,
+                                                              float *__restrict__ mo, float *__restrict__ vo, int adam,
+                                                              float lr, float b1, float b2, float eps, float bc1,
+                                                              float bc2)
 {
-    const int pi = blockIdx.x * kT + threadIdx.x;
-    if (pi > kMlpNParam) return;
-    float gsum = 0.f;
-    for (int r = 0; r < rows; ++r) gsum += part[(long long)r * kPartStride + pi];
+    __shared__ float red[4][kRedParams];
+    const int q = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int pi = blockIdx.x * kRedParams + j;
+    float a[4] = {0.f, 0.f, 0.f, 0.f};
+    if (pi <= kMlpNParam) {
+        int r = q;
+        for (; r + 12 < rows; r += 16) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += part[(long long)(r + 4 * u) * kPartStride + pi];
+        }
+        for (int u = 0; r < rows; r += 4, ++u) a[u & 3] += part[(long long)r * kPartStride + pi];
+    }
+    red[q][j] = (a[0] + a[1]) + (a[2] + a[3]);
+    __syncthreads();
+    if (q != 0 || pi > kMlpNParam) return;
+    const float gsum = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
     if (pi == kMlpNParam) {
         const float L = gsum / (float)n;
         loss[0] = L;
@@ -592,7 +608,8 @@ pb_status run_grad_into(pb_mlp *m, float *part, float *grad, float *loss, const 
     PB_HIP(hipGetLastError());
     const float bc1 = adam ? 1.f - std::pow(b1, (float)step) : 1.f;
     const float bc2 = adam ? 1.f - std::pow(b2, (float)step) : 1.f;
-    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kMlpNParam + 1 + kT - 1) / kT), dim3(kT), 0, s, part, waves, n,
+    hipLaunchKernelGGL(mlp_reduce_adam_kernel, dim3((kMlpNParam + 1 + kRedParams - 1) / kRedParams), dim3(256), 0, s,
+                       part, waves, n,
                        grad, loss, loss_acc, m->par, m->madam, m->vadam, adam, lr, b1, b2, eps, bc1, bc2);
     PB_HIP(hipGetLastError());
     if (adam) return refresh(m, s);
