@@ -33,8 +33,9 @@
  *
  * State layout in HBM ("patch-blocked structure of arrays")
  *   patch k with p_k cells per direction owns cells [off_k, off_k + p_k^d),
- *   off_k = sum_{j<k} p_j^d; unknown v of local cell c sits at element
- *       off_k * N + v * p_k^d + c,        c = (z * p_k + y) * p_k + x,
+ *   off_k = sum_{j<k} p_j^d; value v (0 <= v < N + M: the N unknowns, then
+ *   the M material parameters) of local cell c sits at element
+ *       off_k * (N + M) + v * p_k^d + c,  c = (z * p_k + y) * p_k + x,
  *   x fastest.  Elements are double (PB_STORE_FP64) or float (PB_STORE_FP32:
  *   arithmetic stays double, every stored value is rounded to nearest even).
  */
@@ -72,7 +73,8 @@ typedef enum {
     PB_PDE_ADVECTION_VAR = 5, /* linear advection by a velocity field held as
                                material parameters (paper Sec. II: N evolving
                                plus M fixed values per point): n_unknowns =
-                               1 + dim, Q = (q, a_x, a_y(, a_z)); F_d = a_d(x) q,
+                               1, n_aux = dim, per point (q, a_x, a_y(, a_z));
+                               F_d = a_d(x) q,
                                S = -kappa q.  The dim field values of every
                                cell are read by the fluxes and speeds and
                                carried through every step unchanged (bitwise).
@@ -94,7 +96,14 @@ typedef struct {
     int32_t pde;              /* pb_pde */
     const double *pde_params; /* host, copied at create */
     int64_t n_pde_params;
-    int32_t n_unknowns;       /* N */
+    int32_t n_unknowns;       /* N: evolving values per point */
+    int32_t n_aux;            /* M: material parameters per point (paper Sec.
+                                 II: the state holds N + M values per point,
+                                 the last M read by the physics and copied
+                                 unchanged through every update).  M = dim for
+                                 ADVECTION_VAR (the velocity field); every
+                                 other PDE takes M = 0 (M > 0 there:
+                                 PB_EUNSUPPORTED, checked on the host) */
     int32_t storage;          /* pb_storage */
     void *state;              /* device: the state, in the layout above */
     void *state_alt;          /* device: second buffer of the same size (the
@@ -348,7 +357,12 @@ typedef struct {
                                  allows it (no SRHD, every p a multiple of 4,
                                  16-byte aligned state), 0 = the register-prefetch
                                  kernel (the default) */
-    int32_t fd_ws;            /* FD: 1 = the wave-specialised stage kernel (one
+    int32_t fd_ws;            /* FD: 2 = one wave per 4x4x4 tile, no
+                                 work-group barrier (footprints and matrix
+                                 operands DMA'd into the wave's own LDS one
+                                 chunk of four unknowns ahead; results equal
+                                 the other two to roundoff);
+                                 1 = the wave-specialised stage kernel (one
                                  work-group of 12 waves per CU: 8 waves stage
                                  data and compute gradients while 4 run the
                                  matrix product and the update; the default),
@@ -386,7 +400,7 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  *          a batch of one p with p^3 <= 256 runs the small-patch kernel,
  *          which has no launch-shape choice: one candidate, the current one;
  *   FV 2D: fv_xcd_remap {1, 0};
- *   FD:    fd_ws 1 x fd_xcd_remap {1, 0}, then fd_ws 0 x fd_xcd_remap {1, 0}
+ *   FD:    fd_ws {2, 1} x fd_xcd_remap {1, 0}, then fd_ws 0 x fd_xcd_remap {1, 0}
  *          x fd_wg_per_cu {2, 1}.
  * Each candidate runs one untimed launch and then `trials` timed launches
  * (HIP events on the batch's stream), over two interleaved passes; its time

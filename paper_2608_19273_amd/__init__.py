@@ -40,7 +40,7 @@ class BatchDesc(C.Structure):
     _fields_ = [("dim", C.c_int32), ("n_patches", C.c_int32), ("p", C.POINTER(C.c_int32)),
                 ("dx", C.POINTER(C.c_double)), ("neighbor", C.POINTER(C.c_int32)), ("halo", C.c_int32),
                 ("pde", C.c_int32), ("pde_params", C.POINTER(C.c_double)), ("n_pde_params", C.c_int64),
-                ("n_unknowns", C.c_int32), ("storage", C.c_int32), ("state", C.c_void_p),
+                ("n_unknowns", C.c_int32), ("n_aux", C.c_int32), ("storage", C.c_int32), ("state", C.c_void_p),
                 ("state_alt", C.c_void_p), ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p)]
 
@@ -379,7 +379,7 @@ class PatchBatch:
                               self._dx.ctypes.data_as(C.POINTER(C.c_double)),
                               self._nbr.ctypes.data_as(C.POINTER(C.c_int32)), batch.halo, PDE[batch.pde],
                               self._prm.ctypes.data_as(C.POINTER(C.c_double)), self._prm.size,
-                              batch.n_unknowns, STORAGE[storage], self.bufs[0].data_ptr(),
+                              batch.n_unknowns - batch.n_aux, batch.n_aux, STORAGE[storage], self.bufs[0].data_ptr(),
                               self.bufs[1].data_ptr(), None, 0, _stream())
         ws = pb_workspace_size(self.desc)
         self.workspace = torch.empty(ws + 256, dtype=torch.uint8, device=self.device)

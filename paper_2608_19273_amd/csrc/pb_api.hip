@@ -82,7 +82,17 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
     if (d->halo < 1) { set_error("halo must be >= 1"); return PB_EINVAL; }
     if (d->pde < PB_PDE_ADVECTION_F || d->pde > PB_PDE_ADVECTION_VAR) { set_error("unknown pde"); return PB_EINVAL; }
     if (d->storage != PB_STORE_FP64 && d->storage != PB_STORE_FP32) { set_error("unknown storage"); return PB_EINVAL; }
-    const int N = d->n_unknowns;
+    if (d->n_unknowns < 1 || d->n_aux < 0 || d->n_aux > 64) { set_error("need n_unknowns >= 1 and 0 <= n_aux <= 64"); return PB_EINVAL; }
+    if (d->pde == PB_PDE_ADVECTION_VAR) {
+        if (d->n_unknowns != 1 || d->n_aux != d->dim) {
+            set_error("variable advection needs n_unknowns = 1 and n_aux = dim");
+            return PB_EINVAL;
+        }
+    } else if (d->n_aux != 0) {
+        set_error("n_aux > 0 (material parameters) is implemented for ADVECTION_VAR only");
+        return PB_EUNSUPPORTED;
+    }
+    const int N = d->n_unknowns + d->n_aux;   // values per point
     switch (d->pde) {
     case PB_PDE_ADVECTION_F:
     case PB_PDE_ADVECTION_B:
@@ -98,7 +108,6 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
         if (N != 5 || d->dim != 3) { set_error("SRHD needs dim = 3 and n_unknowns = 5"); return PB_EINVAL; }
         break;
     case PB_PDE_ADVECTION_VAR:
-        if (N != 1 + d->dim) { set_error("variable advection needs n_unknowns = 1 + dim"); return PB_EINVAL; }
         break;
     }
     const int np = n_params_needed(d->pde, N);
@@ -264,7 +273,8 @@ pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes)
     long long cells = 0;
     pb_status st = validate(desc, false, &cells, nullptr, nullptr);
     if (st != PB_OK) return st;
-    *bytes = ws_layout(desc->pde, desc->dim, desc->halo, cells, desc->n_unknowns, desc->storage, desc->n_patches).total;
+    *bytes = ws_layout(desc->pde, desc->dim, desc->halo, cells, desc->n_unknowns + desc->n_aux, desc->storage,
+                       desc->n_patches).total;
     return PB_OK;
     PB_API_END
 }
@@ -283,14 +293,14 @@ pb_status patch_batch_create(const pb_batch_desc *d, pb_batch **out)
     if (!b) { set_error("out of host memory"); return PB_ENOMEM; }
     b->dim = d->dim;
     b->K = d->n_patches;
-    b->N = d->n_unknowns;
+    b->N = d->n_unknowns + d->n_aux;   // values per point: the kernels carry the last n_aux unchanged
     b->h = d->halo;
     b->pde = d->pde;
     b->storage = d->storage;
     b->p.assign(d->p, d->p + d->n_patches);
     b->dx.assign(d->dx, d->dx + d->n_patches);
     b->nbr.assign(d->neighbor, d->neighbor + (size_t)d->n_patches * 2 * d->dim);
-    b->params.assign(d->pde_params, d->pde_params + n_params_needed(d->pde, d->n_unknowns));
+    b->params.assign(d->pde_params, d->pde_params + n_params_needed(d->pde, b->N));
     b->state[0] = d->state;
     b->state[1] = d->state_alt;
     b->ws = static_cast<char *>(d->workspace);
@@ -342,6 +352,7 @@ pb_status patch_batch_destroy(pb_batch *b)
     if (b->d_fd_items) (void)hipFree(b->d_fd_items);
     if (b->d_fd_ws_items) (void)hipFree(b->d_fd_ws_items);
     if (b->d_fd_B) (void)hipFree(b->d_fd_B);
+    if (b->d_fd_A) (void)hipFree(b->d_fd_A);
     delete b;
     return PB_OK;
     PB_API_END
@@ -366,12 +377,13 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     if (t->fv_slab < 0 || t->fv_slab > kFvPmax) { set_error("fv_slab must be in [0, 16]"); return PB_EINVAL; }
     if (t->fd_wg_per_cu < 0 || t->fd_wg_per_cu > 2) { set_error("fd_wg_per_cu must be 0, 1 or 2"); return PB_EINVAL; }
     if (t->fv_persist < 0 || t->fv_persist > 8) { set_error("fv_persist must be in [0, 8]"); return PB_EINVAL; }
+    if (t->fd_ws < 0 || t->fd_ws > 2) { set_error("fd_ws must be 0, 1 or 2"); return PB_EINVAL; }
     b->fv_slab = t->fv_slab;
     b->fv_xcd_remap = t->fv_xcd_remap ? 1 : 0;
     b->fd_xcd_remap = t->fd_xcd_remap ? 1 : 0;
     b->fd_wg_per_cu = t->fd_wg_per_cu == 0 ? 2 : t->fd_wg_per_cu;
     b->fv_dma = t->fv_dma ? 1 : 0;
-    b->fd_ws = t->fd_ws ? 1 : 0;
+    b->fd_ws = t->fd_ws;
     b->fv_persist = t->fv_persist;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();

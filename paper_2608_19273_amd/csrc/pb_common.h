@@ -261,6 +261,7 @@ struct pb_batch {
     void *d_fd_ws_items = nullptr;   // per-tile geometry of the wave-specialised kernel
     int fd_n_items = 0;
     double *d_fd_B = nullptr;
+    double *d_fd_A = nullptr;        // A operands of the one-wave-per-tile FD kernel
     // graph cache
     struct GraphEntry {
         int kind, n_steps, parity_cur;

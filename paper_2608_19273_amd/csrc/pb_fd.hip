@@ -726,6 +726,228 @@ __global__ __launch_bounds__(kWsThreads) void fd_stage_ws_kernel(
     }
 }
 
+// ------------------------------------------------ one wave per tile --
+//
+// fd_ws = 2: every wave advances whole 4x4x4 tiles on its own, with no
+// work-group barrier.  Per chunk of four unknowns (one K step of the matrix
+// product):
+//   1. the chunk's footprints (4 x 384 doubles) and its A operands (rows of
+//      -B_d for the four unknowns, 12 x 64 doubles of a packed table, L2-
+//      resident) go HBM/L2 -> the wave's own LDS by the global->LDS DMA, one
+//      chunk ahead, double buffered (no register holds data in flight, and
+//      every memory instruction of the chunk loop is one of these copies, so
+//      the wait for a chunk is an exact count);
+//   2. lane l differentiates unknown 4c + l/16 at the tile cells 16 nt + l%16
+//      (nt = 0..3, the tile's z planes): its D4_d values are exactly the B
+//      operands of v_mfma_f64_16x16x4f64 for column tile nt, and its KO6 value
+//      sits in the same lane and register as the accumulator of that row and
+//      cell, so nothing is transposed;
+//   3. 48 matrix instructions (3 directions x 4 row tiles x 4 column tiles)
+//      accumulate -sum_d B_d G_d for 64 rows x 64 cells in registers, then the
+//      chunk's KO6 is added to its rows.
+// After the last chunk the stage update runs in the matrix-core output layout
+// (lane l, register i of tile (rt, nt): row 16 rt + 4 i + l/16, cell
+// 16 nt + l%16).  The arithmetic is the other stage kernels' formula by
+// formula; only the order of the additions over the K steps differs (four
+// unknowns per step, directions in order), so results agree to roundoff.
+constexpr int kTileCh = 4;                   // unknowns per chunk (one K step)
+constexpr int kTileMaxCh = kMaxN / kTileCh;  // 15 chunks for N <= 60
+constexpr int kTileA = 3 * 4 * 64;           // A operands of one chunk (doubles)
+constexpr int kTileDma = kTileCh * 3 + kTileA / 128;   // copies per chunk: 12 + 6
+
+// this wave's LDS: two chunk buffers of footprints and A operands
+struct TileLds {
+    double foot[2][kTileCh][kFoot];
+    double a[2][kTileA];
+};
+
+// one chunk's copies (unknowns >= N are read from unknown N - 1: their
+// gradients are zeroed, and their A columns are zero)
+__device__ __forceinline__ void tile_dma(TileLds &L, int buf, const TileSrc &t, const double *apk, int c, int N)
+{
+    const int l = threadIdx.x & 63;
+#pragma unroll
+    for (int u = 0; u < kTileCh; ++u) {
+        const int v = min(c * kTileCh + u, N - 1);
+        const double *src = t.base + (long long)v * t.C;
+#pragma unroll
+        for (int i = 0; i < 3; ++i) dma_to_lds16(src + t.fo[i], &L.foot[buf][u][128 * i]);
+    }
+    const double *as = apk + (long long)c * kTileA + 2 * l;
+#pragma unroll
+    for (int i = 0; i < kTileA / 128; ++i) dma_to_lds16(as + 128 * i, &L.a[buf][128 * i]);
+}
+
+// wait until at most 18 (the next chunk's copies) / 0 of this wave's vector
+// memory operations are in flight, leaving the LDS counter unconstrained;
+// the empty asm keeps LDS reads of the chunk after the wait
+__device__ __forceinline__ void tile_wait_next()
+{
+    static_assert(kTileDma == 18, "vmcnt immediate below");
+    __builtin_amdgcn_s_waitcnt(0x4F72);   // vmcnt(18) = [3:0] 2, [15:14] 1; expcnt 7; lgkmcnt 15
+    __asm__ volatile("" ::: "memory");
+}
+__device__ __forceinline__ void tile_wait_all()
+{
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt 7, lgkmcnt 15
+    __asm__ volatile("" ::: "memory");
+}
+
+__global__ __launch_bounds__(64) void fd_stage_tile_kernel(
+    const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
+    double *__restrict__ acc, const WsItem *__restrict__ items, int n_items, const double *__restrict__ apk,
+    int N, int stage, int rk, double dt, double sigma, int remap)
+{
+    __shared__ TileLds L;
+    const int l = threadIdx.x, g = l >> 4, j = l & 15;
+    const int x = j & 3, yy = j >> 2;
+    const int G = (int)gridDim.x, slot = remap ? xcd_remap((int)blockIdx.x, G) : (int)blockIdx.x;
+    const int nch = (N + kTileCh - 1) / kTileCh;
+    // footprint slots of the lane's column (x, yy) (see foot_slot): plane z
+    // of the tile at 48 z + ib; a y neighbour at offset k at ysl[k] + z ystr[k];
+    // a z neighbour in halo layer h (0..5) at zb + 4 h
+    const int ib = yy * 12 + x + 4;
+    const int zb = kRegZ + yy * 24 + x;
+    int ysl[6], ystr[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int yo = k < 3 ? yy - 3 + k : yy + k - 2;   // yy-3..yy-1, yy+1..yy+3
+        if (yo >= 0 && yo < kT) {
+            ysl[k] = yo * 12 + x + 4;
+            ystr[k] = 48;
+        } else {
+            ysl[k] = kRegY + (yo < 0 ? yo + 3 : yo - 1) * kT + x;
+            ystr[k] = 24;
+        }
+    }
+    const bool need_q0 = rk == 1 || stage < 3, need_acc = rk == 4 && stage > 0;
+    int buf = 0;
+    for (int it = slot; it < n_items; it += G) {
+        const WsItem W = items[it];
+        const int p = W.p, ntl = p / kT;
+        const TileSrc src = tile_src(y, W.off, p, ((W.tz / kT) * ntl + W.ty / kT) * ntl + W.tx / kT, N);
+        const double c4 = W.inv_dx / 12.0, cko = sigma * W.inv_dx / 64.0;
+        f64x4_t am[4][4];
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt)
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) am[rt][nt] = (f64x4_t){0.0, 0.0, 0.0, 0.0};
+        tile_dma(L, buf, src, apk, 0, N);
+        // fully unrolled: the KO6 rows of chunk c are a fixed accumulator register
+#pragma clang loop unroll(full)
+        for (int c = 0; c < kTileMaxCh; ++c) {
+            if (c >= nch) continue;   // (not break: a constant trip count lets the loop unroll)
+            // keep each chunk's instructions together: scheduling across the
+            // unrolled chunks would hold several chunks' values at once
+            __builtin_amdgcn_sched_barrier(0);
+            const int cur = buf;
+            if (c + 1 < nch) {
+                buf ^= 1;
+                // the chunk index as a value the compiler cannot see through:
+                // otherwise it computes every chunk's copy addresses up front
+                int cn = c + 1, bn = buf;
+                __asm__ volatile("" : "+s"(cn), "+s"(bn));
+                tile_dma(L, bn, src, apk, cn, N);
+                tile_wait_next();
+            } else {
+                tile_wait_all();
+            }
+            // gradients and dissipation of unknown 4c + g at the lane's cells
+            const bool live = c * kTileCh + g < N;
+            const double *uf = L.foot[cur][g];
+            double gd[3][4], ko[4];
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const int sc = 48 * nt + ib;
+                const double u0 = uf[sc];
+                double g0, g1, g2, k;
+                {
+                    const double m3 = uf[sc - 3], m2 = uf[sc - 2], m1 = uf[sc - 1], p1 = uf[sc + 1], p2 = uf[sc + 2],
+                                 p3 = uf[sc + 3];
+                    g0 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                    k = ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                }
+                {
+                    const double m3 = uf[ysl[0] + nt * ystr[0]], m2 = uf[ysl[1] + nt * ystr[1]],
+                                 m1 = uf[ysl[2] + nt * ystr[2]], p1 = uf[ysl[3] + nt * ystr[3]],
+                                 p2 = uf[ysl[4] + nt * ystr[4]], p3 = uf[ysl[5] + nt * ystr[5]];
+                    g1 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                    k += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                }
+                {
+                    // z neighbours nt-3..nt+3: a plane of the tile or a halo layer
+                    auto zs = [&](int z) { return z >= 0 && z < kT ? 48 * z + ib : zb + 4 * (z < 0 ? z + 3 : z - 1); };
+                    const double m3 = uf[zs(nt - 3)], m2 = uf[zs(nt - 2)], m1 = uf[zs(nt - 1)], p1 = uf[zs(nt + 1)],
+                                 p2 = uf[zs(nt + 2)], p3 = uf[zs(nt + 3)];
+                    g2 = ((m2 - p2) + 8.0 * (p1 - m1)) * c4;
+                    k += ((m3 + p3) - 6.0 * (m2 + p2)) + 15.0 * (m1 + p1) - 20.0 * u0;
+                }
+                gd[0][nt] = live ? g0 : 0.0;
+                gd[1][nt] = live ? g1 : 0.0;
+                gd[2][nt] = live ? g2 : 0.0;
+                ko[nt] = live ? cko * k : 0.0;
+            }
+            // -sum_d B_d G_d over this K step (A operands from this chunk's LDS copy)
+            const double *ap = &L.a[cur][l];
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+#pragma unroll
+                for (int rt = 0; rt < 4; ++rt) {
+                    const double a = ap[(d * 4 + rt) * 64];
+#pragma unroll
+                    for (int nt = 0; nt < 4; ++nt)
+                        am[rt][nt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, gd[d][nt], am[rt][nt], 0, 0, 0);
+                }
+            // KO6 of unknown 4c + g: row 16 (c/4) + 4 (c%4) + g of the output layout
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) am[c / 4][nt][c % 4] += ko[nt];
+        }
+        buf ^= 1;   // the next tile's first chunk goes to the other buffer
+        // stage update, one row tile at a time (all loads of a round first)
+        const long long C = (long long)p * p * p, pp = (long long)p * p;
+        const long long cell = ((long long)W.tz * p + (W.ty + yy)) * p + (W.tx + x);
+#pragma unroll
+        for (int rt = 0; rt < 4; ++rt) {
+            double qv[4][4], av[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rt + 4 * i + g;
+                const long long gr = W.off * N + (long long)(r < N ? r : 0) * C + cell;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    qv[i][nt] = (r < N && need_q0) ? q0[gr + nt * pp] : 0.0;
+                    av[i][nt] = (r < N && need_acc) ? acc[gr + nt * pp] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * rt + 4 * i + g;
+                if (r >= N) continue;
+                const long long gr = W.off * N + (long long)r * C + cell;
+#pragma unroll
+                for (int nt = 0; nt < 4; ++nt) {
+                    const long long gi = gr + nt * pp;
+                    const double R = am[rt][nt][i];
+                    if (rk == 1) {
+                        acc[gi] = qv[i][nt] + dt * R;
+                    } else if (stage == 0) {
+                        ynext[gi] = qv[i][nt] + 0.5 * dt * R;
+                        acc[gi] = qv[i][nt] + (dt / 6.0) * R;
+                    } else if (stage == 1) {
+                        ynext[gi] = qv[i][nt] + 0.5 * dt * R;
+                        acc[gi] = av[i][nt] + (dt / 3.0) * R;
+                    } else if (stage == 2) {
+                        ynext[gi] = qv[i][nt] + dt * R;
+                        acc[gi] = av[i][nt] + (dt / 3.0) * R;
+                    } else {
+                        acc[gi] = av[i][nt] + (dt / 6.0) * R;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ host --
 
 pb_status fd_prepare(pb_batch *b)
@@ -752,6 +974,24 @@ pb_status fd_prepare(pb_batch *b)
     }
     PB_HIP(hipMalloc(&b->d_fd_ws_items, ws.size() * sizeof(WsItem)));
     PB_HIP(hipMemcpy(b->d_fd_ws_items, ws.data(), ws.size() * sizeof(WsItem), hipMemcpyHostToDevice));
+    // A operands of the one-wave-per-tile kernel: per chunk c of four
+    // unknowns, direction d, row tile rt and lane l, -B_d[16 rt + l%16][4 c + l/16]
+    // (zero outside N x N)
+    {
+        const int N = b->N;
+        std::vector<double> apk((size_t)kTileMaxCh * kTileA, 0.0);
+        for (int c = 0; c < kTileMaxCh; ++c)
+            for (int d = 0; d < 3; ++d)
+                for (int rt = 0; rt < 4; ++rt)
+                    for (int l = 0; l < 64; ++l) {
+                        const int r = 16 * rt + l % 16, k = 4 * c + l / 16;
+                        if (r < N && k < N)
+                            apk[(size_t)c * kTileA + (d * 4 + rt) * 64 + l] =
+                                -b->params[3 + (size_t)d * N * N + (size_t)r * N + k];
+                    }
+        PB_HIP(hipMalloc(&b->d_fd_A, apk.size() * sizeof(double)));
+        PB_HIP(hipMemcpy(b->d_fd_A, apk.data(), apk.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     PB_HIP(hipMalloc(&b->d_fd_items, items.size() * sizeof(FdItem)));
     PB_HIP(hipMalloc(&b->d_fd_B, nB * sizeof(double)));
     PB_HIP(hipMemcpy(b->d_fd_items, items.data(), items.size() * sizeof(FdItem), hipMemcpyHostToDevice));
@@ -771,6 +1011,16 @@ pb_status launch_fd_stage(pb_batch *b, int stage, int rk_stages, const void *q0,
     int dev = 0, cus = 0;
     PB_HIP(hipGetDevice(&dev));
     PB_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (b->fd_ws == 2) {
+        // one wave per work-group, as many as the LDS holds (4 per CU)
+        const int grid = std::max(1, std::min(b->fd_n_items, cus * 4));
+        launch_main(b, fd_stage_tile_kernel, dim3(grid), dim3(64), 0, s, static_cast<const double *>(y),
+                    static_cast<const double *>(q0), static_cast<double *>(ynext), static_cast<double *>(acc),
+                    reinterpret_cast<const WsItem *>(b->d_fd_ws_items), b->fd_n_items, b->d_fd_A, b->N, stage,
+                    rk_stages, dt, sigma, b->fd_xcd_remap);
+        PB_HIP(hipGetLastError());
+        return PB_OK;
+    }
     if (b->fd_ws) {
         // one wave-specialised work-group per CU
         const int grid = std::max(1, std::min(b->fd_n_items, cus));

@@ -106,12 +106,13 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
                     c.push_back(t);
                 }
     } else {
-        for (int remap = 1; remap >= 0; --remap) {
-            pb_tuning t = base;
-            t.fd_ws = 1;
-            t.fd_xcd_remap = remap;
-            c.push_back(t);
-        }
+        for (int ws = 2; ws >= 1; --ws)
+            for (int remap = 1; remap >= 0; --remap) {
+                pb_tuning t = base;
+                t.fd_ws = ws;
+                t.fd_xcd_remap = remap;
+                c.push_back(t);
+            }
         for (int wg = 2; wg >= 1; --wg)
             for (int remap = 1; remap >= 0; --remap) {
                 pb_tuning t = base;
@@ -281,7 +282,7 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
         if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 8 ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
             t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
-            t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 1) {
+            t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 2) {
             set_error(std::string(path) + ":" + std::to_string(lineno) + ": malformed tuning entry");
             if (n_loaded) *n_loaded = n;
             return PB_EINVAL;

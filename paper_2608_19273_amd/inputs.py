@@ -106,6 +106,12 @@ class Batch:
     def K(self) -> int:
         return int(self.p.shape[0])
 
+    @property
+    def n_aux(self) -> int:
+        """material parameters among the n_unknowns values per point (the
+        velocity field of variable advection)"""
+        return self.dim if self.pde == "adv_var" else 0
+
     def cells(self) -> np.ndarray:
         return self.p.astype(np.int64) ** self.dim
 

@@ -37,8 +37,8 @@ def desc_for(b, state=1, alt=2, ws=256, ws_bytes=1 << 40, storage=0, **over):
     keep = (p, dx, nbr, prm)
     d = pb.BatchDesc(b.dim, b.K, p.ctypes.data_as(C.POINTER(C.c_int32)), dx.ctypes.data_as(C.POINTER(C.c_double)),
                      nbr.ctypes.data_as(C.POINTER(C.c_int32)), b.halo, pb.PDE[b.pde],
-                     prm.ctypes.data_as(C.POINTER(C.c_double)), prm.size, b.n_unknowns, storage, state, alt, ws,
-                     ws_bytes, None)
+                     prm.ctypes.data_as(C.POINTER(C.c_double)), prm.size, b.n_unknowns - b.n_aux, b.n_aux, storage,
+                     state, alt, ws, ws_bytes, None)
     for k, v in over.items():
         setattr(d, k, v)
     return d, keep
@@ -61,6 +61,27 @@ def test_workspace_size_layout():
     d, keep = desc_for(b2)
     per = a256(b2.total_cells * 58 * 8)
     assert pb.pb_workspace_size(d) == 256 + part(b2.K) + 2 * per
+
+
+def test_material_parameter_counts():
+    """n_aux (M material parameters per point): the variable-advection
+    batch takes n_unknowns = 1 and n_aux = dim; M > 0 for another PDE is a
+    valid request the library does not implement; either is reported before
+    any HIP call"""
+    b = I.adv_var_batch((2, 2, 1), 4)
+    d, keep = desc_for(b)
+    assert (d.n_unknowns, d.n_aux) == (1, 3)
+    assert pb.pb_workspace_size(d) > 0
+    h = C.c_void_p()
+    for n, m, rc, msg in ((4, 0, pb.PB_EINVAL, "n_aux = dim"), (1, 2, pb.PB_EINVAL, "n_aux = dim"),
+                          (1, -1, pb.PB_EINVAL, "n_aux")):
+        d.n_unknowns, d.n_aux = n, m
+        assert pb.lib().patch_batch_create(C.byref(d), C.byref(h)) == rc
+        assert msg in pb.last_error() and not h.value
+    e, keep2 = desc_for(I.config0())
+    e.n_aux = 1
+    assert pb.lib().patch_batch_create(C.byref(e), C.byref(h)) == pb.PB_EUNSUPPORTED
+    assert "ADVECTION_VAR" in pb.last_error() and not h.value
 
 
 @pytest.mark.parametrize("field,value,msg", [

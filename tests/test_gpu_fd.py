@@ -152,6 +152,50 @@ def test_wave_specialised_kernel_matches(N):
     assert np.all(rel_err(b, out[1], o2) <= 1e-12)
 
 
+@pytest.mark.parametrize("N", [1, 3, 4, 5, 8, 13, 20, 29, 33, 47, 53, 57, 58, 60])
+def test_tile_kernel_matches(N):
+    """The one-wave-per-tile stage kernel (fd_ws = 2) against the oracle and,
+    to roundoff (it adds the K steps in another order), against the
+    wave-specialised kernel, for every count of 4-unknown chunks (N = 1..60,
+    ragged last chunks), both tile orders, RK4 with CFL dt and a fixed-dt
+    forward Euler step, on 5 uneven patches."""
+    announce(f"fd tile kernel N={N}")
+    need_gpu()
+    b = I.config2(n_patches=5, N=N, sizes=np.array([8, 4, 16, 4, 8], np.int32))
+    out = {}
+    for ws, remap in ((2, 1), (2, 0), (1, 1)):
+        B = pb.PatchBatch(b)
+        B.set_tuning(fd_ws=ws, fd_xcd_remap=remap)
+        assert B.get_tuning()["fd_ws"] == ws
+        B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
+        B.fd_ko_step(cfl=0.5, dt_fixed=1e-3, sigma_ko=0.05, rk_stages=1, n_steps=1)
+        out[(ws, remap)] = B.download()
+        B.close()
+    np.testing.assert_array_equal(out[(2, 1)], out[(2, 0)])
+    assert np.all(rel_err(b, out[(2, 1)], out[(1, 1)]) <= 1e-14)
+    o, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
+    b2 = b.copy()
+    b2.state = o
+    o2, _ = oracle.fd_step(b2, dt_fixed=1e-3, sigma=0.05, rk_stages=1, n_steps=1)
+    assert np.all(rel_err(b, out[(2, 1)], o2) <= 1e-12)
+
+
+def test_tile_kernel_config2_subset():
+    """The 48-patch subset of the uneven 58-unknown batch, 10 graph-replayed
+    RK4 steps with the one-wave-per-tile kernel, against the oracle."""
+    announce("fd tile kernel config2 subset, 10 steps")
+    need_gpu()
+    b = I.config2(subset=I.config2_subset())
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=10)
+    B = pb.PatchBatch(b)
+    B.set_tuning(fd_ws=2, fd_xcd_remap=1)
+    dt = B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=10, use_graph=True, want_dt=True)
+    g = B.download()
+    B.close()
+    assert abs(dt - dts[-1]) <= 1e-15 * dts[-1]
+    assert np.all(rel_err(b, g, o) <= 1e-12)
+
+
 def test_graph_replays_match_eager():
     """Three steps captured in a HIP graph and replayed three times, with the
     program's own eager work and synchronisations between the replays: every

@@ -30,7 +30,8 @@ def test_fv_autotune_euler3d():
     before, st0 = B.download(), B.stats()
     r = B.autotune("fv", cfl=0.4, trials=2)
     check_result(r, 16)
-    assert sorted({c["fv_slab"] for c, _ in r["candidates"]}) == [2, 4, 8, 16]
+    assert sorted({c["fv_slab"] for c, _ in r["candidates"] if not c["fv_persist"]}) == [2, 4, 8, 16]
+    assert {c["fv_persist"] for c, _ in r["candidates"]} == {0, 2, 3}
     assert {c["fv_dma"] for c, _ in r["candidates"]} == {0, 1}
     assert B.get_tuning() == r["best"]
     np.testing.assert_array_equal(B.download(), before)
@@ -46,9 +47,10 @@ def test_fv_autotune_euler3d():
 
 
 def test_fd_autotune_is_bitwise_neutral():
-    """FD tunings only move tiles between work-groups or split the phases of a
-    tile between waves differently: a step after tuning is bitwise equal to a
-    step at the default tuning."""
+    """FD tunings move tiles between work-groups or split the phases of a tile
+    between waves differently: a step after tuning is bitwise equal to a step
+    at the default tuning, except with the one-wave-per-tile kernel, which
+    adds the K steps of the product in another order (roundoff)."""
     announce("autotune fd")
     need_gpu()
     pb.pb_autotune_cache_clear()
@@ -56,8 +58,8 @@ def test_fd_autotune_is_bitwise_neutral():
     B = pb.PatchBatch(b)
     before, st0 = B.download(), B.stats()
     r = B.autotune("fd", cfl=0.5, sigma_ko=0.1, trials=2)
-    check_result(r, 6)
-    assert {c["fd_ws"] for c, _ in r["candidates"]} == {0, 1}
+    check_result(r, 8)
+    assert {c["fd_ws"] for c, _ in r["candidates"]} == {0, 1, 2}
     np.testing.assert_array_equal(B.download(), before)
     assert B.stats() == st0
     B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
@@ -67,7 +69,10 @@ def test_fd_autotune_is_bitwise_neutral():
     B0.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
     g0 = B0.download()
     B0.close()
-    np.testing.assert_array_equal(g, g0)
+    if r["best"]["fd_ws"] == 2:
+        assert np.all(rel_err(b, g, g0) <= 1e-14)
+    else:
+        np.testing.assert_array_equal(g, g0)
     o, _ = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
     assert np.all(rel_err(b, g, o) <= 1e-12)
     with pytest.raises(pb.PbError):
@@ -83,7 +88,7 @@ def test_srhd_autotune_then_step():
     B = pb.PatchBatch(b)
     before, st0 = B.download(), B.stats()
     r = B.autotune("fv", cfl=0.4, trials=2)
-    check_result(r, 8)   # SRHD has no DMA-fed kernel: slabs x remap only
+    check_result(r, 12)   # SRHD has no DMA-fed kernel: balanced (2, 3 per CU) and slabs, x remap
     assert {c["fv_dma"] for c, _ in r["candidates"]} == {0}
     np.testing.assert_array_equal(B.download(), before)
     assert B.stats() == st0
