@@ -277,6 +277,19 @@ pb_status pb_mlp_forward(const pb_mlp *m, const void *x, void *y, int64_t n, voi
  * grad device [PB_MLP_NPARAM] FP32 (overwritten), loss device [1] FP32 */
 pb_status pb_mlp_grad(const pb_mlp *m, const void *x, const void *t, int64_t n, void *grad,
                       void *loss, void *stream);
+/* pb_mlp_grad without any allocation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops): the same
+ * kernels and results as pb_mlp_grad, with the partial-gradient scratch in a
+ * fixed device array of the library (256 rows of 4672 floats, 4.8 MB, held
+ * by each GPU the library runs on until the process ends) instead of the
+ * MLP's own buffer, and grad / loss written directly by the reduction.
+ * n must be in [1, 2^30] (larger n: PB_EINVAL, nothing enqueued).  Calls no
+ * hipMalloc / hipFree.  Every call on one GPU shares that GPU's array (each
+ * call rewrites the rows it reads, so no clearing is needed): calls that
+ * overlap on one GPU (other streams, other threads) race. */
+pb_status pb_mlp_grad_noalloc(const pb_mlp *m, const void *x, const void *t, int64_t n, void *grad,
+                              void *loss, void *stream);
+
 /* one Adam step on a batch: grad + update of the FP32 master weights and their
  * bfloat16 copies.  step is the 1-based Adam step counter.
  * Forward and backward run on the matrix cores (bf16 operands, FP32
