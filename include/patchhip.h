@@ -392,10 +392,37 @@ typedef struct {
                                  (fv_slab), the default.  Results differ from
                                  slab mode only where a slab seam changes the
                                  order of additions. */
+    int32_t fv_column;        /* FV 3D (register kernel): w in 1..8 = column
+                                 runs: the patches are linked along +z (k to
+                                 its +z neighbour s where s's -z neighbour is
+                                 k and both have the same p >= 2) into chains
+                                 and cycles, each split into runs of nearly
+                                 equal plane counts, about w work-groups per
+                                 CU in total; a work-group marches its run
+                                 across patch tops without a restart, so the
+                                 plane below and above every patch top inside
+                                 a run is read once.  Takes precedence over
+                                 fv_persist and fv_slab; builds a small device
+                                 table here (host call, PB_EHIP if that
+                                 fails).  0 = off, the default.  Results
+                                 differ from slab mode only where a run
+                                 starts inside a patch, as at a slab seam. */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
 pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
+
+/* The column runs that fv_column = w sets up for the 3D batch `desc` (its
+ * host tables only; device pointers are not used) on a device of `cus`
+ * compute units, in unit order (the order the XCD remap groups).  Host-only.
+ * runs: host [max_runs][4] receiving (patch, first plane, planes, 0): the
+ * unit marches `planes` planes from `first plane` of `patch` on up its +z
+ * chain.  *n_runs receives the number of runs even when it exceeds max_runs
+ * (then PB_EINVAL and nothing is written; runs may be NULL with max_runs 0
+ * to ask for the count).  PB_EINVAL also for an invalid desc, a 2D batch,
+ * w outside [1, 8] or cus < 1. */
+pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, int32_t *runs, int32_t max_runs,
+                            int32_t *n_runs);
 
 /* ------------------------------------------------------------ autotuner -- */
 
@@ -406,10 +433,11 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
  * kind 0 = the finite-volume step (fv_rusanov_step with the given cfl /
  * dt_fixed), kind 1 = one FD4+KO6 stage (fd_ko_step with sigma_ko; cfl /
  * dt_fixed as there).  Candidates:
- *   FV 3D: fv_persist {3, 2} x fv_xcd_remap {1, 0} (batches of one p), then
- *          fv_slab in {p_max, p_max/2, p_max/4, ...} (>= 2) x fv_xcd_remap {1, 0},
- *          then the DMA-fed kernel with fv_slab in {p_max, p_max/2} x
- *          fv_xcd_remap {1, 0} where it applies;
+ *   FV 3D: fv_column {3, 2} x fv_xcd_remap {1, 0}, then fv_persist 3 x
+ *          fv_xcd_remap {1, 0} (batches of one p), then fv_slab in
+ *          {p_max, p_max/2, p_max/4} (>= 2) x fv_xcd_remap {1, 0}, then the
+ *          DMA-fed kernel with fv_slab in {p_max, p_max/2} x fv_xcd_remap
+ *          {1, 0} where it applies;
  *          a batch of one p with p^3 <= 256 runs the small-patch kernel,
  *          which has no launch-shape choice: one candidate, the current one;
  *   FV 2D: fv_xcd_remap {1, 0};
@@ -442,8 +470,9 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
                       int32_t use_cache, pb_autotune_result *out);
 
 /* The process-wide tuning cache as a text file, one entry per line:
- * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws> <fv_persist>"
- * (a line without the last field loads with fv_persist = 0).
+ * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws> <fv_persist> <fv_column>"
+ * (a line without the last field loads with fv_column = 0, one without the
+ * last two also with fv_persist = 0).
  * save writes every entry (replacing the file); load adds the file's entries
  * (a later entry of the same key wins) and stores their number in *n_loaded
  * (nullable).  Host-only; PB_EINVAL on a file that cannot be opened or a

@@ -279,6 +279,30 @@ pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes)
     PB_API_END
 }
 
+pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, int32_t *runs, int32_t max_runs,
+                            int32_t *n_runs)
+{
+    PB_API_BEGIN
+    if (!n_runs || (max_runs > 0 && !runs)) { set_error("NULL argument"); return PB_EINVAL; }
+    *n_runs = 0;
+    long long cells = 0;
+    pb_status st = validate(desc, false, &cells, nullptr, nullptr);
+    if (st != PB_OK) return st;
+    if (desc->dim != 3) { set_error("column runs apply to 3D batches"); return PB_EINVAL; }
+    if (w < 1 || w > 8 || cus < 1) { set_error("need w in [1, 8] and cus >= 1"); return PB_EINVAL; }
+    const std::vector<int4> r = fv_column_runs(desc->n_patches, desc->p, desc->neighbor, w, cus);
+    *n_runs = (int32_t)r.size();
+    if ((int32_t)r.size() > max_runs) { set_error("runs buffer too small"); return PB_EINVAL; }
+    for (size_t i = 0; i < r.size(); ++i) {
+        runs[4 * i + 0] = r[i].x;
+        runs[4 * i + 1] = r[i].y;
+        runs[4 * i + 2] = r[i].z;
+        runs[4 * i + 3] = r[i].w;
+    }
+    return PB_OK;
+    PB_API_END
+}
+
 pb_status patch_batch_create(const pb_batch_desc *d, pb_batch **out)
 {
     PB_API_BEGIN
@@ -353,6 +377,7 @@ pb_status patch_batch_destroy(pb_batch *b)
     if (b->d_fd_ws_items) (void)hipFree(b->d_fd_ws_items);
     if (b->d_fd_B) (void)hipFree(b->d_fd_B);
     if (b->d_fd_A) (void)hipFree(b->d_fd_A);
+    if (b->d_fv_runs) (void)hipFree(b->d_fv_runs);
     delete b;
     return PB_OK;
     PB_API_END
@@ -377,6 +402,7 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     if (t->fv_slab < 0 || t->fv_slab > kFvPmax) { set_error("fv_slab must be in [0, 16]"); return PB_EINVAL; }
     if (t->fd_wg_per_cu < 0 || t->fd_wg_per_cu > 2) { set_error("fd_wg_per_cu must be 0, 1 or 2"); return PB_EINVAL; }
     if (t->fv_persist < 0 || t->fv_persist > 8) { set_error("fv_persist must be in [0, 8]"); return PB_EINVAL; }
+    if (t->fv_column < 0 || t->fv_column > 8) { set_error("fv_column must be in [0, 8]"); return PB_EINVAL; }
     if (t->fd_ws < 0 || t->fd_ws > 2) { set_error("fd_ws must be 0, 1 or 2"); return PB_EINVAL; }
     b->fv_slab = t->fv_slab;
     b->fv_xcd_remap = t->fv_xcd_remap ? 1 : 0;
@@ -385,9 +411,10 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     b->fv_dma = t->fv_dma ? 1 : 0;
     b->fd_ws = t->fd_ws;
     b->fv_persist = t->fv_persist;
+    b->fv_column = t->fv_column;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
-    return PB_OK;
+    return fv_column_prepare(b);
     PB_API_END
 }
 
@@ -402,6 +429,7 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
     out->fv_dma = b->fv_dma;
     out->fd_ws = b->fd_ws;
     out->fv_persist = b->fv_persist;
+    out->fv_column = b->fv_column;
     return PB_OK;
     PB_API_END
 }

@@ -251,6 +251,10 @@ struct pb_batch {
     int fd_ws = 1;   // linear-system FD: wave-specialised kernel
     int fv_dma = 0;
     int fv_persist = 0;   // FV 3D, one p: > 0 = balanced plane schedule over this many work-groups per CU
+    int fv_column = 0;    // FV 3D: > 0 = column runs along +z chains, about this many work-groups per CU
+    void *d_fv_runs = nullptr;   // column runs (int4: patch, first plane, planes, 0), one per unit
+    int fv_n_runs = 0;
+    int fv_runs_w = 0;            // the fv_column the table was built for
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
@@ -340,6 +344,12 @@ bool fv_dma_eligible(const pb_batch *b);
 // (p+2)^3 slots of N + A doubles per patch within kFvSmallLds bytes
 constexpr size_t kFvSmallLds = 64 * 1024;
 bool fv_small_eligible(const pb_batch *b);
+// the column runs (patch, first plane, planes, 0) of a 3D batch with
+// neighbour table nbr [K][6], about w work-groups per CU on `cus` CUs
+std::vector<int4> fv_column_runs(int K, const int *p, const int *nbr, int w, int cus);
+// (re)builds the column-run table of the FV plane-march kernel for
+// b->fv_column (frees it when 0); host call, done when the tuning is set
+pb_status fv_column_prepare(pb_batch *b);
 // dt of an FD step: dt_fixed if > 0, else cfl / sum_d (rho(B_d) / dx_min)
 double fd_dt(const pb_batch *b, double cfl, double dt_fixed);
 // uploads the FD work list and B_d (library-owned; done once, before any capture)

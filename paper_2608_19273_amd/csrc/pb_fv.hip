@@ -127,14 +127,19 @@ template <> struct PlaneAux<Srhd> {
 // round) and work-group r marches the planes
 // [r T / G, (r + 1) T / G) of that sequence, one segment per patch it
 // crosses, so every work-group moves the same number of planes and the last
-// round of a grid of whole patches, partly filled, disappears.
+// round of a grid of whole patches, partly filled, disappears.  Column mode
+// (plan.runs): unit u marches runs[u].z planes starting at plane runs[u].y of
+// patch runs[u].x and continuing, without a restart, into the +z neighbour
+// (the z halo between consecutive patches of a run is the plane the march
+// has just processed: it is never read twice).
 struct FvPlan {
     int n_units, n_slabs, slab, remap;
     long long planes;   // balanced mode: total planes (0: slab mode)
+    const int4 *runs;   // column mode (non-null): unit u marches runs[u] = (patch, first plane, planes)
 };
 
 template <class Ph, int DIM, typename T, bool kLam>
-__global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
+__global__ __launch_bounds__(kFvThreads) __attribute__((amdgpu_waves_per_eu(3))) void fv_step_kernel(
     const T *__restrict__ qin, T *__restrict__ qout, const double *__restrict__ ex,
     const PatchDev *__restrict__ patches, FvPlan plan, Ctrl *__restrict__ ctrl, double *__restrict__ part,
     int slot_in, double dt_fixed, FvChain chain, Ph ph)
@@ -151,50 +156,63 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     bool bad = false;
     int parity = 0;   // LDS buffer of the next plane (alternates over every plane the work-group marches)
 
-    // one segment: planes [z0, z1) of patch k
-    auto segment = [&](int k, int z0, int z1) {
-    const PatchDev P = patches[k];
-    const int p = P.p;
+    // one segment: n planes starting at plane z0 of patch k, continuing into
+    // the +z neighbour at the patch's top (the patches of a run share p)
+    auto segment = [&](int k, int z0, int n) {
+    const int p = patches[k].p;
     const long long C = (DIM == 3) ? (long long)p * p * p : (long long)p * p;
-    long long onb[6];
-#pragma unroll
-    for (int f = 0; f < 6; ++f) onb[f] = (f < 2 * DIM) ? patches[P.nbr[f]].off : P.off;
 
-    const bool work = z0 < z1;
+    const bool work = n > 0;
     const bool active = work && t < p * p;
     const int x = active ? t % p : 0, y = active ? t / p : 0;
-    const double hr_ = 0.5 * dt * P.inv_dx;   // the face sums below are doubled
     const int li = (y + 1) * PH + (x + 1);
 
     // face-halo cell of each plane: wave w serves side w (-x, +x, -y, +y),
     // so the extra loads and aux evaluations spread over all four waves
-    const int side = t >> 6, j = t & 63;
+    const int side = __builtin_amdgcn_readfirstlane(t >> 6), j = t & 63;
     const bool halo = work && j < p;
     int hsrc = 0, hdst = 0;
-    long long hoff = 0;
     if (halo) {
         int hx, hy, sx, sy;
-        if (side == 0)      { hx = -1; hy = j;  sx = p - 1; sy = j;     hoff = onb[0]; }
-        else if (side == 1) { hx = p;  hy = j;  sx = 0;     sy = j;     hoff = onb[1]; }
-        else if (side == 2) { hx = j;  hy = -1; sx = j;     sy = p - 1; hoff = onb[2]; }
-        else                { hx = j;  hy = p;  sx = j;     sy = 0;     hoff = onb[3]; }
+        if (side == 0)      { hx = -1; hy = j;  sx = p - 1; sy = j;     }
+        else if (side == 1) { hx = p;  hy = j;  sx = 0;     sy = j;     }
+        else if (side == 2) { hx = j;  hy = -1; sx = j;     sy = p - 1; }
+        else                { hx = j;  hy = p;  sx = j;     sy = 0;     }
         hsrc = sy * p + sx;
         hdst = (hy + 1) * PH + (hx + 1);
     }
     const long long cxy = (long long)y * p + x;
     const long long pp = (long long)p * p;
+    // the current patch and its +z neighbour (the run's next patch): cell
+    // offsets of the patch and of the wave's halo-side neighbour (lanes
+    // without a halo cell load cell 0 of that neighbour and drop it)
+    long long offc = patches[k].off, hoffc = patches[patches[k].nbr[side]].off;
+    double hr_ = 0.5 * dt * patches[k].inv_dx;   // the face sums below are doubled
+    int kn = (DIM == 3) ? patches[k].nbr[5] : k;
+    long long offn = patches[kn].off, hoffn = patches[patches[kn].nbr[side]].off;
+    int zl = z0;   // the current plane's z inside the current patch
 
-    // per thread: this plane (qc, ac), its z flux and speed (fzc, lzc), the
-    // doubled flux and fluctuation of the lower z face (fs2l, dn2l)
-    double qc[N], ac[AA], fzc[N], fs2l[N], dn2l[N], e[1];
-    double lzc = 0.0;
+    // per thread, two sets that swap roles from plane to plane (the loop runs
+    // two planes per trip, so nothing is copied between them): a plane's
+    // values (q, a), its z flux and speed (fz, lz), and the doubled flux and
+    // fluctuation of its lower z face (fs, dn)
+    struct Carry {
+        double q[N], a[AA], fz[N], fs[N], dn[N];
+        double lz;
+    };
+    Carry cA, cB;
+    double e[1];
+    double *qc = cA.q, *ac = cA.a, *fzc = cA.fz, *fs2l = cA.fs, *dn2l = cA.dn;
+    double &lzc = cA.lz;
+    lzc = 0.0;
     // one-plane prefetch (raw storage-type values): the own column for plane
     // z+1 and the halo cell for plane z.  One plane ahead is as fast as two or
     // three, and with the next plane's flux evaluated after the x and y
     // directions the kernel fits in 3 waves per SIMD without spilling.
     RawCell<Ph, T> rnA, hrA;
 
-    auto own_plane_off = [&](int zz) -> long long { return zz >= p ? onb[5] : P.off; };
+    // plane zl + d (d = 0, 1, 2; p >= 2) of the run: the current patch or the next
+    auto own_plane_off = [&](int zz) -> long long { return zz >= p ? offn : offc; };
     auto own_plane_c = [&](int zz) -> long long { return (zz >= p ? zz - p : zz) * pp + cxy; };
 
     // Every lane issues every load (idle lanes at a valid address they do not
@@ -204,10 +222,10 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
     // for the load right there and empties the prefetch ring.
     if (work) {
         RawCell<Ph, T> rc;
-        issue_load<Ph>(qin, ex, P.off, C, z0 * pp + cxy, rc);
+        issue_load<Ph>(qin, ex, offc, C, z0 * pp + cxy, rc);
         if (DIM == 3) {
             RawCell<Ph, T> rm;
-            const long long om = (z0 == 0) ? onb[4] : P.off;
+            const long long om = (z0 == 0) ? patches[patches[k].nbr[4]].off : offc;
             const int zm = (z0 == 0) ? p - 1 : z0 - 1;
             issue_load<Ph>(qin, ex, om, C, zm * pp + cxy, rm);
             issue_load<Ph>(qin, ex, own_plane_off(z0 + 1), C, own_plane_c(z0 + 1), rnA);
@@ -226,17 +244,23 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
         }
     }
     if (work) {
-        issue_load<Ph>(qin, ex, hoff, C, z0 * pp + hsrc, hrA);
+        issue_load<Ph>(qin, ex, hoffc, C, z0 * pp + hsrc, hrA);
     }
 
-    // one plane: consumes rn (own plane z+1) and hr (halo of plane z), then
-    // refills them with planes z+2 and z+1
-    auto plane = [&](int z, RawCell<Ph, T> &rn, RawCell<Ph, T> &hr) {
+    // run plane i (at zl of the current patch): consumes rn (own plane i+1)
+    // and hr (halo of plane i), then refills them with planes i+2 and i+1,
+    // clamped to the plane after the run and to the run's last plane
+    auto plane = [&](int i, RawCell<Ph, T> &rn, RawCell<Ph, T> &hr, Carry &cur, Carry &nxt) {
+        const double *qc = cur.q, *ac = cur.a, *fzc = cur.fz, *fs2l = cur.fs, *dn2l = cur.dn;
+        const double lzc = cur.lz;
         double(*buf)[PH * PH] = lds[parity];
         parity ^= 1;
         double hq[N], he[1];
         unpack<Ph>(hr, hq, he);
-        issue_load<Ph>(qin, ex, hoff, C, min(z + 1, z1 - 1) * pp + hsrc, hr);
+        {
+            const int zh = zl + min(1, n - 1 - i);
+            issue_load<Ph>(qin, ex, zh >= p ? hoffn : hoffc, C, (zh >= p ? zh - p : zh) * pp + hsrc, hr);
+        }
         if (halo) {
             double ha[AA];
             ph.aux(hq, he, ha);
@@ -285,25 +309,23 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
         }
         // the next plane's primitives, flux and speed, after the x and y
         // directions: fewer values are live at once (3 waves per SIMD)
-        double qn[N], an[AA], fzn[N];
-        double lzn = 0.0;
+        double *qn = nxt.q, *an = nxt.a, *fzn = nxt.fz;
+        double &lzn = nxt.lz;
+        lzn = 0.0;
         if (DIM == 3) {
             unpack<Ph>(rn, qn, e);
-            issue_load<Ph>(qin, ex, own_plane_off(min(z + 2, z1)), C, own_plane_c(min(z + 2, z1)), rn);
+            const int z2 = zl + min(2, n - i);
+            issue_load<Ph>(qin, ex, own_plane_off(z2), C, own_plane_c(z2), rn);
             ph.aux(qn, e, an);
             phys_flux_or_zero<Ph, DZ>(ph, qn, an, fzn);
             lzn = ph.template eig<DZ>(qn, an);
         }
         if (active) {
             if (DIM == 3) {
-                double fs2u[N], dn2u[N];
+                double *fs2u = nxt.fs, *dn2u = nxt.dn;
                 rusanov_face2<Ph, DZ>(ph, qc, fzc, lzc, qn, fzn, lzn, fs2u, dn2u);
 #pragma unroll
-                for (int v = 0; v < N; ++v) {
-                    acc2[v] += (fs2u[v] - fs2l[v]) + (dn2u[v] + dn2l[v]);
-                    fs2l[v] = fs2u[v];
-                    dn2l[v] = dn2u[v];
-                }
+                for (int v = 0; v < N; ++v) acc2[v] += (fs2u[v] - fs2l[v]) + (dn2u[v] + dn2l[v]);
             }
             double S[N];
             if (Ph::kSrc) {
@@ -313,7 +335,7 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
                 for (int v = 0; v < N; ++v) S[v] = 0.0;
             }
             double qw[N];
-            T *dst = qout + P.off * N + z * pp + cxy;
+            T *dst = qout + offc * N + zl * pp + cxy;
 #pragma unroll
             for (int v = 0; v < N; ++v) {
                 const double nv = v < N - Ph::M ? qc[v] - hr_ * acc2[v] + dt * S[v] : qc[v];   // material: carried
@@ -324,19 +346,35 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
             }
             if (kLam) cell_speeds_fast<Ph, DIM>(ph, qw, lm);
         }
-        if (DIM == 3) {
-#pragma unroll
-            for (int v = 0; v < N; ++v) { qc[v] = qn[v]; fzc[v] = fzn[v]; }
-#pragma unroll
-            for (int a = 0; a < A; ++a) ac[a] = an[a];
-            lzc = lzn;
+    };
+    // after plane i: the run continues in the +z neighbour at the patch's top
+    // (already the source of the loads issued for its first planes)
+    auto advance = [&](int i) {
+        if (DIM == 3 && ++zl == p && i + 1 < n) {
+            zl = 0;
+            offc = offn;
+            hoffc = hoffn;
+            hr_ = 0.5 * dt * patches[kn].inv_dx;
+            kn = patches[kn].nbr[5];
+            offn = patches[kn].off;
+            hoffn = patches[patches[kn].nbr[side]].off;
         }
     };
 
-    for (int z = z0; z < z1; ++z) plane(z, rnA, hrA);
+    int i = 0;
+    for (; i + 1 < n; i += 2) {
+        plane(i, rnA, hrA, cA, cB);
+        advance(i);
+        plane(i + 1, rnA, hrA, cB, cA);
+        advance(i + 1);
+    }
+    if (i < n) plane(i, rnA, hrA, cA, cB);
     };
 
-    if (DIM == 3 && plan.planes > 0) {
+    if (DIM == 3 && plan.runs) {
+        const int4 r = plan.runs[unit];
+        segment(r.x, r.y, r.z);
+    } else if (DIM == 3 && plan.planes > 0) {
         // balanced mode: a contiguous run of planes (every patch has p planes)
         const int p = patches[0].p;
         const long long G = plan.n_units;
@@ -346,7 +384,7 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
             const int k = (int)(s / p);
             const int za = (int)(s - (long long)k * p);
             const int zb = (int)min((long long)p, za + (s1 - s));
-            segment(k, za, zb);
+            segment(k, za, zb - za);
             s += zb - za;
         }
     } else {
@@ -354,7 +392,7 @@ __global__ __launch_bounds__(kFvThreads) void fv_step_kernel(
         const int p = patches[k].p;
         const int z0 = (DIM == 3) ? sl * plan.slab : 0;
         const int z1 = (DIM == 3) ? min(p, z0 + plan.slab) : 1;
-        segment(k, min(z0, z1), z1);
+        segment(k, min(z0, z1), max(0, z1 - z0));
     }
     if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
     if (kLam) fold_speeds<DIM>(ctrl, part, lm, unit, plan.n_units, chain);
@@ -928,11 +966,15 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
         return PB_OK;
       }
     }
-    // the plane-march kernel: slab units, or the balanced plane schedule
-    // over the work-groups that are resident at once (uniform p)
-    FvPlan plan{n_units, n_slabs, slab, b->fv_xcd_remap, 0};
+    // the plane-march kernel: slab units, column runs along +z chains, or
+    // the balanced plane schedule over the work-groups that are resident at
+    // once (uniform p)
+    FvPlan plan{n_units, n_slabs, slab, b->fv_xcd_remap, 0, nullptr};
     auto plane_kernel = [&](auto kern) -> pb_status {
-        if (DIM == 3 && b->fv_persist > 0 && b->uniform_p) {
+        if (DIM == 3 && b->fv_column > 0 && b->d_fv_runs) {
+            plan.runs = static_cast<const int4 *>(b->d_fv_runs);
+            plan.n_units = b->fv_n_runs;
+        } else if (DIM == 3 && b->fv_persist > 0 && b->uniform_p) {
             int cus = 0;
             pb_status st = device_cus(&cus);
             if (st != PB_OK) return st;
@@ -1031,6 +1073,94 @@ pb_status dispatch(pb_batch *b, F &&f)
 }
 
 }  // namespace
+
+// Column runs: the +z link k -> s = nbr[k][+z] holds where s's -z neighbour
+// is k and both patches have the same p >= 2 (the march then reads s's first
+// planes as the continuation of k's column).  Links form chains and cycles;
+// each gets a number of runs proportional to its planes (at least one, at
+// most one per plane), about fv_column work-groups per CU in total, and runs
+// of one chain split its planes as evenly as integers allow.  Units are
+// ordered chain after chain, chains by their smallest patch index, so that
+// with the XCD remap the runs of neighbouring chains of a grid in patch order
+// share an XCD (and its L2) and reach equal heights at about the same time.
+std::vector<int4> fv_column_runs(int K, const int *p, const int *nbr, int w, int cus)
+{
+    std::vector<int> succ(K, -1), pred(K, -1);
+    for (int k = 0; k < K; ++k) {
+        const int s = nbr[6 * k + 5];
+        if (p[k] >= 2 && p[s] == p[k] && nbr[6 * s + 4] == k) {
+            succ[k] = s;
+            pred[s] = k;
+        }
+    }
+    std::vector<std::vector<int>> chains;
+    std::vector<char> seen(K, 0);
+    for (int k = 0; k < K; ++k) {   // open chains, from their first patch
+        if (pred[k] >= 0) continue;
+        chains.emplace_back();
+        for (int j = k; j >= 0; j = succ[j]) {
+            seen[j] = 1;
+            chains.back().push_back(j);
+        }
+    }
+    for (int k = 0; k < K; ++k) {   // cycles, from their smallest patch
+        if (seen[k]) continue;
+        chains.emplace_back();
+        int j = k;
+        do {
+            seen[j] = 1;
+            chains.back().push_back(j);
+            j = succ[j];
+        } while (j != k);
+    }
+    std::vector<std::pair<int, int>> order;   // (smallest patch, chain)
+    for (int c = 0; c < (int)chains.size(); ++c)
+        order.push_back({*std::min_element(chains[c].begin(), chains[c].end()), c});
+    std::sort(order.begin(), order.end());
+    long long total = 0;
+    for (const auto &c : chains) total += (long long)c.size() * p[c[0]];
+    const double slots = (double)w * cus;
+    std::vector<int4> runs;
+    for (const auto &o : order) {
+        const std::vector<int> &c = chains[o.second];
+        const int pc = p[c[0]];
+        const long long planes = (long long)c.size() * pc;
+        const long long r = std::max(1LL, std::min(planes, std::llround(slots * (double)planes / (double)total)));
+        for (long long j = 0; j < r; ++j) {
+            const long long s0 = j * planes / r, s1 = (j + 1) * planes / r;
+            runs.push_back(make_int4(c[s0 / pc], (int)(s0 % pc), (int)(s1 - s0), 0));
+        }
+    }
+    return runs;
+}
+
+pb_status fv_column_prepare(pb_batch *b)
+{
+    if (b->fv_column == b->fv_runs_w && (b->d_fv_runs || b->fv_column <= 0 || b->dim != 3)) return PB_OK;
+    b->fv_runs_w = 0;
+    if (b->d_fv_runs) {
+        PB_HIP(hipFree(b->d_fv_runs));
+        b->d_fv_runs = nullptr;
+        b->fv_n_runs = 0;
+    }
+    if (b->fv_column <= 0 || b->dim != 3) return PB_OK;
+    int cus = 0;
+    pb_status st = device_cus(&cus);
+    if (st != PB_OK) return st;
+    const std::vector<int4> runs = fv_column_runs(b->K, b->p.data(), b->nbr.data(), b->fv_column, cus);
+    if ((long long)runs.size() > max_units(b->K)) { set_error("column runs exceed the partial buffers"); return PB_EINVAL; }
+    void *d = nullptr;
+    PB_HIP(hipMalloc(&d, runs.size() * sizeof(int4)));
+    if (hipMemcpy(d, runs.data(), runs.size() * sizeof(int4), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        set_error("hipMemcpy of the column runs failed");
+        return PB_EHIP;
+    }
+    b->d_fv_runs = d;
+    b->fv_n_runs = (int)runs.size();
+    b->fv_runs_w = b->fv_column;
+    return PB_OK;
+}
 
 bool fv_small_eligible(const pb_batch *b)
 {

@@ -48,10 +48,11 @@ pb_tuning current(const pb_batch *b)
     t.fv_dma = b->fv_dma;
     t.fd_ws = b->fd_ws;
     t.fv_persist = b->fv_persist;
+    t.fv_column = b->fv_column;
     return t;
 }
 
-void apply(pb_batch *b, const pb_tuning &t)
+pb_status apply(pb_batch *b, const pb_tuning &t)
 {
     b->fv_slab = t.fv_slab;
     b->fv_xcd_remap = t.fv_xcd_remap;
@@ -60,6 +61,8 @@ void apply(pb_batch *b, const pb_tuning &t)
     b->fv_dma = t.fv_dma;
     b->fd_ws = t.fd_ws;
     b->fv_persist = t.fv_persist;
+    b->fv_column = t.fv_column;
+    return fv_column_prepare(b);
 }
 
 std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
@@ -71,37 +74,44 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
     } else if (kind == 0) {
         std::vector<int> slabs;
         if (b->dim == 3) {
-            for (int s = b->pmax; s >= 2; s /= 2) slabs.push_back(s);
+            for (int s = b->pmax; s >= 2 && slabs.size() < 3; s /= 2) slabs.push_back(s);
             if (slabs.empty()) slabs.push_back(b->pmax);
         } else {
             slabs.push_back(0);
         }
+        auto plain = [&](int remap) {
+            pb_tuning t = base;
+            t.fv_persist = 0;
+            t.fv_column = 0;
+            t.fv_dma = 0;
+            t.fv_slab = 0;
+            t.fv_xcd_remap = remap;
+            return t;
+        };
+        if (b->dim == 3)
+            for (int w = 3; w >= 2; --w)
+                for (int remap = 1; remap >= 0; --remap) {
+                    pb_tuning t = plain(remap);
+                    t.fv_column = w;
+                    c.push_back(t);
+                }
         if (b->dim == 3 && b->uniform_p)
-            for (int wgs = 3; wgs >= 2; --wgs)
             for (int remap = 1; remap >= 0; --remap) {
-                pb_tuning t = base;
-                t.fv_persist = wgs;
-                t.fv_dma = 0;
-                t.fv_slab = 0;
-                t.fv_xcd_remap = remap;
+                pb_tuning t = plain(remap);
+                t.fv_persist = 3;
                 c.push_back(t);
             }
         for (int remap = 1; remap >= 0; --remap)
             for (int s : slabs) {
-                pb_tuning t = base;
-                t.fv_persist = 0;
+                pb_tuning t = plain(remap);
                 t.fv_slab = s;
-                t.fv_xcd_remap = remap;
-                t.fv_dma = 0;
                 c.push_back(t);
             }
         if (fv_dma_eligible(b))
             for (int remap = 1; remap >= 0; --remap)
                 for (int i = 0; i < 2 && i < (int)slabs.size(); ++i) {
-                    pb_tuning t = base;
-                    t.fv_persist = 0;
+                    pb_tuning t = plain(remap);
                     t.fv_slab = slabs[i];
-                    t.fv_xcd_remap = remap;
                     t.fv_dma = 1;
                     c.push_back(t);
                 }
@@ -203,7 +213,7 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
         for (size_t ci = 0; ci < cand.size() && st == PB_OK; ++ci) {
             // second pass in reverse order, so drift does not favour one end
             const size_t i = pass == 0 ? ci : cand.size() - 1 - ci;
-            apply(b, cand[i]);
+            if ((st = apply(b, cand[i])) != PB_OK) break;
             if ((st = trial(b, kind, cfl, dt_fixed, sigma_ko, s)) != PB_OK) break;
             hipError_t e = hipEventRecord(e0, s);
             for (int r = 0; r < trials && e == hipSuccess && st == PB_OK; ++r)
@@ -223,7 +233,7 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
     hipError_t er = hipMemcpyAsync(b->ws, &saved, sizeof(Ctrl), hipMemcpyHostToDevice, s);
     if (er == hipSuccess) er = hipStreamSynchronize(s);
     if (st != PB_OK) {
-        apply(b, before);
+        (void)pb_batch_set_tuning(b, &before);   // (also drops graphs that hold an older run table)
         return st;
     }
     if (er != hipSuccess) return hip_fail(er, "pb_autotune: restoring the control block");
@@ -237,7 +247,6 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
         std::lock_guard<std::mutex> lk(g_mu);
         g_cache[key] = cand[bi];
     }
-    apply(b, before);
     return pb_batch_set_tuning(b, &cand[bi]);
     PB_API_END
 }
@@ -252,7 +261,7 @@ pb_status pb_autotune_cache_save(const char *path)
     for (auto &e : g_cache)
         f << e.first << ' ' << e.second.fv_slab << ' ' << e.second.fv_xcd_remap << ' ' << e.second.fd_xcd_remap << ' '
           << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << ' ' << e.second.fd_ws << ' ' << e.second.fv_persist
-          << '\n';
+          << ' ' << e.second.fv_column << '\n';
     if (!f) { set_error(std::string("write failed: ") + path); return PB_EINVAL; }
     return PB_OK;
     PB_API_END
@@ -278,8 +287,11 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
         if (ok && !(in >> t.fv_persist)) {   // six-field line: slab mode
             t.fv_persist = 0;
             in.clear();
+        } else if (ok && !(in >> t.fv_column)) {   // seven-field line: no column runs
+            t.fv_column = 0;
+            in.clear();
         }
-        if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 8 ||
+        if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 8 || t.fv_column < 0 || t.fv_column > 8 ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
             t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
             t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 2) {

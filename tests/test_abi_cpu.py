@@ -149,24 +149,34 @@ def test_autotune_rejects_bad_arguments_without_gpu():
 
 def test_autotune_cache_file_round_trip(tmp_path):
     """the tuning cache is host-side: entries load, save and reload unchanged
-    (a six-field line, written before the balanced FV schedule existed, loads
-    as slab mode); a malformed line is rejected with the entries before it
-    kept"""
+    (a six-field line loads with fv_persist = fv_column = 0, a seven-field
+    line with fv_column = 0); a malformed line is rejected with the entries
+    before it kept"""
     pb.pb_autotune_cache_clear()
     src = tmp_path / "in.txt"
-    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0\n")
-    assert pb.pb_autotune_cache_load(str(src)) == 2
+    src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0\n"
+                   "fv/pde2/d3/N5/s0/h1/16x768 0 1 1 2 0 1 0 3\n")
+    assert pb.pb_autotune_cache_load(str(src)) == 3
     out = tmp_path / "out.txt"
     pb.pb_autotune_cache_save(str(out))
     lines = sorted(out.read_text().splitlines())
-    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1",
-                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0 0"])
+    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1 0",
+                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0 0 0",
+                            "fv/pde2/d3/N5/s0/h1/16x768 0 1 1 2 0 1 0 3"])
     bad = tmp_path / "bad.txt"
     bad.write_text("fv/x 4 1 1 2 1 1\nfv/y 99 1 1 2 1 1\nfv/z 4 1 1 2 1 1\n")
     with pytest.raises(pb.PbError, match="bad2.txt:1"):
         bad2 = tmp_path / "bad2.txt"
         bad2.write_text("fv/w 4 1 1 2 1 1 9\n")
         pb.pb_autotune_cache_load(str(bad2))
+    with pytest.raises(pb.PbError, match="bad3.txt:1"):
+        bad3 = tmp_path / "bad3.txt"
+        bad3.write_text("fv/v 4 1 1 2 1 1 0 9\n")
+        pb.pb_autotune_cache_load(str(bad3))
+    with pytest.raises(pb.PbError, match="bad4.txt:1"):
+        bad4 = tmp_path / "bad4.txt"
+        bad4.write_text("fv/u 4 1 1 2 1 1 0 3 1\n")
+        pb.pb_autotune_cache_load(str(bad4))
     with pytest.raises(pb.PbError, match="bad.txt:2"):
         pb.pb_autotune_cache_load(str(bad))
     pb.pb_autotune_cache_save(str(out))
@@ -203,3 +213,87 @@ def test_offload_create_rejects_bad_descriptions():
     assert create(batch_patches=-1) == pb.PB_EINVAL
     assert L.pb_offload_fv_step(None, 1, None, None, None, 1e-3, None) == pb.PB_EINVAL
     assert L.pb_offload_destroy(None) == pb.PB_EINVAL
+
+
+def _check_runs(b, runs, w, cus):
+    """every plane of every patch in exactly one run; inside a run the plane
+    after a patch top is the +z neighbour's first plane, and only along a link
+    (the neighbour's -z neighbour is the patch, same p); about w * cus runs"""
+    count = [np.zeros(int(pk), np.int32) for pk in b.p]
+    for k, z0, n, pad in runs:
+        assert pad == 0 and n >= 1 and 0 <= z0 < b.p[k]
+        z = z0
+        for _ in range(n):
+            count[k][z] += 1
+            z += 1
+            if z == b.p[k]:
+                s = b.nbr[k, 5]
+                k_next, z = s, 0
+                if _ + 1 < n:   # the run continues: only along a link
+                    assert b.nbr[s, 4] == k and b.p[s] == b.p[k] >= 2
+                k = k_next
+    for c in count:
+        np.testing.assert_array_equal(c, 1)
+    planes = int(b.p.astype(np.int64).sum())
+    assert len(runs) <= planes
+
+
+@pytest.mark.parametrize("grid,w", [((16, 16, 8), 3), ((8, 8, 3), 1), ((8, 8, 3), 3), ((4, 4, 2), 2),
+                                    ((16, 16, 3), 2)])
+def test_column_runs_cover_every_plane(grid, w):
+    """The column-run schedule (pb_fv_column_runs, the table fv_column = w
+    uploads): z-periodic grids give one cycle per column; the runs of a
+    column split its planes evenly and, with enough planes, number about
+    w * 256 in total; chains come in order of their smallest patch."""
+    b = I.make_uniform_batch(grid, 16, 1, "euler", [1.4], 5, 1.0 / 16)
+    d, keep = desc_for(b)
+    runs = pb.pb_fv_column_runs(d, w, 256)
+    _check_runs(b, runs, w, 256)
+    nx, ny, nz = grid
+    columns = nx * ny
+    planes_per_col = nz * 16
+    per_col = max(1, min(planes_per_col, round(w * 256 * planes_per_col / (columns * planes_per_col))))
+    assert len(runs) == columns * per_col
+    # column c (patches c, c + nx ny, ...) owns units [c per_col, (c + 1) per_col), split evenly
+    for c in range(columns):
+        rc = runs[c * per_col:(c + 1) * per_col]
+        starts = [(k // columns) * 16 + z0 for k, z0, n, _ in rc]
+        assert all(k % columns == c for k, _, _, _ in rc)
+        assert starts == [j * planes_per_col // per_col for j in range(per_col)]
+
+
+def test_column_runs_open_chains_and_ragged():
+    """Open z chains (bottom and top patches are their own outer z
+    neighbours), a ragged batch whose patches are their own z neighbours, and
+    the query's error paths."""
+    b = I.make_uniform_batch((4, 4, 3), 8, 1, "euler", [1.4], 5, 1.0 / 8)
+    layer = 16
+    for k in range(b.K):
+        if k // layer == 0:
+            b.nbr[k, 4] = k
+        if k // layer == 2:
+            b.nbr[k, 5] = k
+    d, keep = desc_for(b)
+    for w in (1, 3, 8):
+        runs = pb.pb_fv_column_runs(d, w, 4)
+        _check_runs(b, runs, w, 4)
+        # 16 chains of 24 planes, 4 w slots: runs per chain round(w / 4), at least 1
+        assert len(runs) == 16 * max(1, round(w * 4 / 16))
+    # a chain of one patch per patch when the +z neighbour is itself
+    ps = np.array([5, 5, 11, 16, 11], np.int32)
+    nbr = np.array([[1, 1, 0, 0, 0, 0], [0, 0, 1, 1, 1, 1], [4, 4, 2, 2, 2, 2], [3] * 6, [2, 2, 4, 4, 4, 4]],
+                   np.int32)
+    rb = I.Batch(dim=3, p=ps, dx=1.0 / ps, nbr=nbr, halo=1, pde="euler", params=np.array([1.4]), n_unknowns=5,
+                 state=np.zeros(5 * int((ps.astype(np.int64) ** 3).sum())))
+    d2, keep2 = desc_for(rb)
+    runs = pb.pb_fv_column_runs(d2, 3, 256)
+    _check_runs(rb, runs, 3, 256)
+    assert len(runs) == int(ps.sum())   # more slots than planes: one run per plane
+    n = C.c_int32(-1)
+    assert pb.lib().pb_fv_column_runs(C.byref(d2), 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert n.value == len(runs)
+    assert pb.lib().pb_fv_column_runs(C.byref(d2), 0, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert pb.lib().pb_fv_column_runs(C.byref(d2), 9, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    b2 = I.config0()
+    d3, keep3 = desc_for(b2)
+    assert pb.lib().pb_fv_column_runs(C.byref(d3), 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL

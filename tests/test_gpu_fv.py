@@ -180,6 +180,58 @@ def test_advection_source_any_cfl(form):
     assert np.all(rel_err(b, g, o) <= 1e-12)
 
 
+@pytest.mark.parametrize("grid,storage", [((4, 4, 2), "fp64"), ((8, 8, 3), "fp64"), ((8, 8, 4), "fp32"),
+                                          ((16, 16, 3), "fp64")])
+def test_euler3d_column_runs(grid, storage):
+    """Column runs (each work-group marches a run of planes up a +z chain of
+    patches, crossing patch tops without a restart): 32 patches (more slots
+    than planes: runs of one plane), 192 patches in chains of 3 (one run of
+    48 planes per chain at w = 1, runs of 12 crossing patch tops at w = 3),
+    256 and 768 patches; against the oracle, against whole-patch slabs to
+    roundoff, bitwise repeatable, both XCD orders."""
+    announce(f"euler3d column runs {grid} {storage}")
+    b = I.config1(grid=grid)
+    tol = 1e-12
+    if storage == "fp32":
+        b.state = b.state.astype(np.float32).astype(np.float64)
+        tol = 1e-5
+    o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=3, round_fp32=storage == "fp32")
+    gs, _, _ = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_slab": 0, "fv_xcd_remap": 1})
+    for w, remap in ((3, 1), (3, 0), (2, 1), (1, 1), (8, 1)):
+        g, dt, st = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_column": w, "fv_xcd_remap": remap})
+        assert np.all(rel_err(b, g, o) <= tol), (w, remap, rel_err(b, g, o))
+        assert np.all(rel_err(b, g, gs) <= (1e-14 if storage == "fp64" else 1e-6))
+        assert abs(dt - dts[-1]) <= 1e-13 * dts[-1]
+        assert st["nonfinite_units"] == 0
+        g2, _, _ = run_gpu(b, storage=storage, n_steps=3, tuning={"fv_column": w, "fv_xcd_remap": remap})
+        np.testing.assert_array_equal(g, g2)
+
+
+@pytest.mark.parametrize("w", [1, 3])
+def test_column_runs_open_chains_cover_every_cell(w):
+    """8x8 columns of 3 patches of 16^3 whose bottom and top patches take
+    their outer z halo from themselves (open +z chains, not cycles).  The
+    output buffer starts as NaN, so a plane that no run marches stays NaN;
+    one step, then three, against the oracle."""
+    announce(f"column runs, open chains, w={w}")
+    b = I.config1(grid=(8, 8, 3))
+    layer, nz = 8 * 8, 3   # patch index = (z * ny + y) * nx + x
+    nbr = b.nbr.copy()
+    for k in range(b.K):
+        if k // layer == 0:
+            nbr[k, 4] = k
+        if k // layer == nz - 1:
+            nbr[k, 5] = k
+    b.nbr = nbr
+    for n_steps in (1, 3):
+        o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=n_steps)
+        g, dt, st = run_gpu(b, n_steps=n_steps, tuning={"fv_column": w}, poison=True)
+        assert np.all(np.isfinite(g))
+        assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+        assert abs(dt - dts[-1]) <= 1e-13 * dts[-1]
+        assert st["nonfinite_units"] == 0
+
+
 def test_ragged_patch_sizes():
     """Patches of p = 5 and p = 11 (not multiples of any tile) and p = 16 in
     one batch, each group periodic among itself."""
@@ -199,6 +251,9 @@ def test_ragged_patch_sizes():
                 state=state)
     o, dts, _ = oracle.fv_step(b, cfl=0.4, n_steps=3)
     g, dt, _ = run_gpu(b, n_steps=3, tuning={"fv_slab": 4, "fv_xcd_remap": 1})
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    # column runs: every patch is its own z cycle; 48 planes, so one run per plane
+    g, dt, _ = run_gpu(b, n_steps=3, tuning={"fv_column": 3, "fv_xcd_remap": 1})
     assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
 
 

@@ -30,8 +30,10 @@ def test_fv_autotune_euler3d():
     before, st0 = B.download(), B.stats()
     r = B.autotune("fv", cfl=0.4, trials=2)
     check_result(r, 16)
-    assert sorted({c["fv_slab"] for c, _ in r["candidates"] if not c["fv_persist"]}) == [2, 4, 8, 16]
-    assert {c["fv_persist"] for c, _ in r["candidates"]} == {0, 2, 3}
+    plain = [c for c, _ in r["candidates"] if not c["fv_persist"] and not c["fv_column"]]
+    assert sorted({c["fv_slab"] for c in plain}) == [4, 8, 16]
+    assert {c["fv_column"] for c, _ in r["candidates"]} == {0, 2, 3}
+    assert {c["fv_persist"] for c, _ in r["candidates"]} == {0, 3}
     assert {c["fv_dma"] for c, _ in r["candidates"]} == {0, 1}
     assert B.get_tuning() == r["best"]
     np.testing.assert_array_equal(B.download(), before)
