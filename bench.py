@@ -214,17 +214,22 @@ RETUNE = False
 MIN_WARMUP_S = 0.5
 
 
-def tune(B, kind, **kw):
+def tune(B, kind, euler=False, **kw):
     """the library's autotuner on batch B (outside any timed region): the
     cached choice for this workload if the tuning file holds one, else a
-    measured search; returns a summary of what was used"""
+    measured search; returns a summary of what was used (euler: the FD
+    candidates are the Euler stage kernel's column runs)"""
     r = B.autotune(kind, trials=3, use_cache=not RETUNE, **kw)
 
     def name(t):
         if kind == "fv":
+            if t.get("fv_column"):
+                return f"column{t['fv_column']}/remap{t['fv_xcd_remap']}"
             if t.get("fv_persist"):
                 return f"balanced{t['fv_persist']}/remap{t['fv_xcd_remap']}"
             return f"slab{t['fv_slab']}/remap{t['fv_xcd_remap']}/dma{t['fv_dma']}"
+        if euler:
+            return f"column{t['fd_column']}/remap{t['fd_xcd_remap']}"
         if t["fd_ws"]:
             return f"ws/remap{t['fd_xcd_remap']}"
         return f"remap{t['fd_xcd_remap']}/wg{t['fd_wg_per_cu']}"
@@ -273,7 +278,8 @@ def bench_fd(torch, pb, I, steps, warmup):
     cells = b.total_cells
     B = pb.PatchBatch(b)
     tuned = tune(B, "fd", cfl=0.5, sigma_ko=0.1)
-    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=warmup)
+    extra = warm_up(torch, B, lambda n: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n), warmup, MIN_WARMUP_S,
+                    chunk=5)
     # eager, with every stage launch timed by its own dispatch events
     B.profile(True)
     el_eager = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
@@ -293,7 +299,7 @@ def bench_fd(torch, pb, I, steps, warmup):
     return {"workload": "linear symmetric system N=58, 4096 patches {4^3,8^3,16^3} 1:2:1 shuffled "
                         f"({cells} cells), FD4 + KO6 (sigma 0.1) + RK4, CFL 0.5, FP64",
             "cell_updates_per_s": cells * steps / el, "ms_per_step": el * 1e3 / steps, "use_graph": True,
-            "ms_per_step_eager": el_eager * 1e3 / steps,
+            "ms_per_step_eager": el_eager * 1e3 / steps, "warmup_extra_steps": extra,
             "stage_kernel_avg_us": kern_ms * 1e3 / max(launches, 1), "nonfinite_units": st["nonfinite_units"],
             "hbm_frac": cells * bytes_cell / step_kernel_s / 1e9 / HBM_PEAK_GBS,
             "fp64_frac": cells * flop_cell / step_kernel_s / 1e12 / FP64_PEAK_TFLOPS,
@@ -306,7 +312,8 @@ def bench_fd_euler(torch, pb, I, steps, warmup):
     b = I.config1(seed=1, halo=3)
     cells = b.total_cells
     B = pb.PatchBatch(b)
-    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=warmup)
+    tuned = tune(B, "fd", euler=True, cfl=0.5, sigma_ko=0.1)
+    extra = warm_up(torch, B, lambda n: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=n), warmup, MIN_WARMUP_S)
     B.profile(True)
     el = timed(torch, lambda: B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=steps))
     kern_ms, launches = B.profile_read()
@@ -327,7 +334,7 @@ def bench_fd_euler(torch, pb, I, steps, warmup):
             "algorithmic_bytes_per_cell_step": bytes_cell,
             "kernel_GBs": cells * bytes_cell / step_kernel_s / 1e9,
             "hbm_frac": cells * bytes_cell / step_kernel_s / 1e9 / HBM_PEAK_GBS,
-            "nonfinite_units": st["nonfinite_units"]}
+            "nonfinite_units": st["nonfinite_units"], "warmup_extra_steps": extra, "autotune": tuned}
 
 
 KSWEEP_K = (1, 4, 16, 64, 256, 1024, 4096, 8694, 16384)
@@ -513,7 +520,7 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs):
     return res
 
 
-def warm_up(torch, B, step_fn, warmup, min_seconds):
+def warm_up(torch, B, step_fn, warmup, min_seconds, chunk=50):
     """W untimed steps, then further untimed steps until at least
     `min_seconds` of warm-up have passed: the first ~200 launches after an
     idle spell run about 15 % slower than the sustained rate (clock and power
@@ -524,9 +531,9 @@ def warm_up(torch, B, step_fn, warmup, min_seconds):
     torch.cuda.synchronize()
     extra = 0
     while time.perf_counter() - t0 < min_seconds:
-        step_fn(50)
+        step_fn(chunk)
         torch.cuda.synchronize()
-        extra += 50
+        extra += chunk
     return extra
 
 
@@ -686,7 +693,7 @@ def main():
             wl["linsym58_fd4_rk4"] = bench_fd(torch, pb, I, max(2, args.steps // 4), 1)
         if "fdeuler" in want:
             log("FD4 + KO6 + RK4, 3D Euler")
-            wl["euler3d_fd4_rk4"] = bench_fd_euler(torch, pb, I, max(2, args.steps // 4), 1)
+            wl["euler3d_fd4_rk4"] = bench_fd_euler(torch, pb, I, args.steps, 1)
         if "srhd" in want:
             log("SRHD plain / warm / learned con2prim")
             # 10 steps per guess (the configuration's step count): longer runs smooth

@@ -407,22 +407,32 @@ typedef struct {
                                  fails).  0 = off, the default.  Results
                                  differ from slab mode only where a run
                                  starts inside a patch, as at a slab seam. */
+    int32_t fd_column;        /* Euler FD (plane kernel): w in 1..8 = column
+                                 runs as for fv_column (links between patches
+                                 of one p >= 4; every run at least one whole
+                                 patch long), about w work-groups per CU;
+                                 0 = one work-group per patch.  Default 2
+                                 (the kernel holds two work-groups per CU).
+                                 Results are bitwise those of fd_column = 0.
+                                 Builds a small device table here (host call,
+                                 PB_EHIP if that fails). */
 } pb_tuning;
 
 pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t);
 pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out);
 
-/* The column runs that fv_column = w sets up for the 3D batch `desc` (its
- * host tables only; device pointers are not used) on a device of `cus`
- * compute units, in unit order (the order the XCD remap groups).  Host-only.
+/* The column runs that fv_column = w (kind 0) or fd_column = w (kind 1)
+ * sets up for the 3D batch `desc` (its host tables only; device pointers
+ * are not used) on a device of `cus` compute units, in unit order (the
+ * order the XCD remap groups).  Host-only.
  * runs: host [max_runs][4] receiving (patch, first plane, planes, 0): the
  * unit marches `planes` planes from `first plane` of `patch` on up its +z
  * chain.  *n_runs receives the number of runs even when it exceeds max_runs
  * (then PB_EINVAL and nothing is written; runs may be NULL with max_runs 0
  * to ask for the count).  PB_EINVAL also for an invalid desc, a 2D batch,
- * w outside [1, 8] or cus < 1. */
-pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, int32_t *runs, int32_t max_runs,
-                            int32_t *n_runs);
+ * kind other than 0 or 1, w outside [1, 8] or cus < 1. */
+pb_status pb_column_runs(const pb_batch_desc *desc, int32_t kind, int32_t w, int32_t cus, int32_t *runs,
+                         int32_t max_runs, int32_t *n_runs);
 
 /* ------------------------------------------------------------ autotuner -- */
 
@@ -432,7 +442,7 @@ pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, i
  *
  * kind 0 = the finite-volume step (fv_rusanov_step with the given cfl /
  * dt_fixed), kind 1 = one FD4+KO6 stage (fd_ko_step with sigma_ko; cfl /
- * dt_fixed as there).  Candidates:
+ * dt_fixed as there; the linear system or 3D Euler).  Candidates:
  *   FV 3D: fv_column {3, 2} x fv_xcd_remap {1, 0}, then fv_persist 3 x
  *          fv_xcd_remap {1, 0} (batches of one p), then fv_slab in
  *          {p_max, p_max/2, p_max/4} (>= 2) x fv_xcd_remap {1, 0}, then the
@@ -442,7 +452,9 @@ pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, i
  *          which has no launch-shape choice: one candidate, the current one;
  *   FV 2D: fv_xcd_remap {1, 0};
  *   FD:    fd_ws {2, 1} x fd_xcd_remap {1, 0}, then fd_ws 0 x fd_xcd_remap {1, 0}
- *          x fd_wg_per_cu {2, 1}.
+ *          x fd_wg_per_cu {2, 1};
+ *   Euler FD: fd_column {2, 4, 0} x fd_xcd_remap {1, 0}; a batch of one p
+ *          with p^3 <= 256 runs the small-patch kernel: one candidate.
  * Each candidate runs one untimed launch and then `trials` timed launches
  * (HIP events on the batch's stream), over two interleaved passes; its time
  * is the smaller of the two pass averages.  The trial launches read the
@@ -470,9 +482,10 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
                       int32_t use_cache, pb_autotune_result *out);
 
 /* The process-wide tuning cache as a text file, one entry per line:
- * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws> <fv_persist> <fv_column>"
- * (a line without the last field loads with fv_column = 0, one without the
- * last two also with fv_persist = 0).
+ * "<key> <fv_slab> <fv_xcd_remap> <fd_xcd_remap> <fd_wg_per_cu> <fv_dma> <fd_ws> <fv_persist> <fv_column>
+ *  <fd_column>"
+ * (the last three fields may be missing, from the end: they then load at
+ * their defaults fv_persist 0, fv_column 0, fd_column 2).
  * save writes every entry (replacing the file); load adds the file's entries
  * (a later entry of the same key wins) and stores their number in *n_loaded
  * (nullable).  Host-only; PB_EINVAL on a file that cannot be opened or a

@@ -57,7 +57,7 @@ class Stats(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("fv_slab", C.c_int32), ("fv_xcd_remap", C.c_int32), ("fd_xcd_remap", C.c_int32),
                 ("fd_wg_per_cu", C.c_int32), ("fv_dma", C.c_int32), ("fd_ws", C.c_int32),
-                ("fv_persist", C.c_int32), ("fv_column", C.c_int32)]
+                ("fv_persist", C.c_int32), ("fv_column", C.c_int32), ("fd_column", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,8 +101,8 @@ def lib():
         L.pb_last_error.restype = C.c_char_p
         L.pb_workspace_size.argtypes = [C.POINTER(BatchDesc), C.POINTER(C.c_size_t)]
         L.patch_batch_create.argtypes = [C.POINTER(BatchDesc), C.POINTER(vp)]
-        L.pb_fv_column_runs.argtypes = [C.POINTER(BatchDesc), C.c_int32, C.c_int32, vp, C.c_int32,
-                                        C.POINTER(C.c_int32)]
+        L.pb_column_runs.argtypes = [C.POINTER(BatchDesc), C.c_int32, C.c_int32, C.c_int32, vp, C.c_int32,
+                                     C.POINTER(C.c_int32)]
         L.patch_batch_destroy.argtypes = [vp]
         L.pb_batch_reset.argtypes = [vp, C.c_int32]
         L.pb_batch_stats.argtypes = [vp, C.POINTER(Stats)]
@@ -143,7 +143,7 @@ def lib():
                                          C.POINTER(OffloadTiming)]
         for name in ("pb_offload_create", "pb_offload_destroy", "pb_offload_fv_step"):
             getattr(L, name).restype = C.c_int
-        for name in ("pb_workspace_size", "pb_fv_column_runs", "patch_batch_create", "patch_batch_destroy", "pb_batch_reset",
+        for name in ("pb_workspace_size", "pb_column_runs", "patch_batch_create", "patch_batch_destroy", "pb_batch_reset",
                      "pb_batch_stats", "pb_batch_set_tuning", "pb_batch_get_tuning", "pb_autotune",
                      "pb_autotune_cache_save", "pb_autotune_cache_load", "pb_autotune_cache_clear", "pb_batch_set_c2p_guess", "pb_batch_profile",
                      "pb_batch_profile_read", "pb_stream_copy", "fv_rusanov_step",
@@ -174,16 +174,18 @@ def pb_workspace_size(desc: BatchDesc) -> int:
     return int(n.value)
 
 
-def pb_fv_column_runs(desc: BatchDesc, w: int, cus: int) -> np.ndarray:
+def pb_column_runs(desc: BatchDesc, kind: str, w: int, cus: int) -> np.ndarray:
     """the column runs [n, 4] (patch, first plane, planes, 0) that fv_column = w
-    sets up on a device of `cus` CUs (host-only)"""
+    (kind "fv") or fd_column = w (kind "fd") sets up on a device of `cus` CUs
+    (host-only)"""
+    k = {"fv": 0, "fd": 1}[kind]
     n = C.c_int32(0)
-    rc = lib().pb_fv_column_runs(C.byref(desc), w, cus, None, 0, C.byref(n))
+    rc = lib().pb_column_runs(C.byref(desc), k, w, cus, None, 0, C.byref(n))
     if rc != PB_OK and n.value == 0:
-        _check(rc, "pb_fv_column_runs")
+        _check(rc, "pb_column_runs")
     out = np.zeros((max(n.value, 1), 4), np.int32)
-    _check(lib().pb_fv_column_runs(C.byref(desc), w, cus, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
-           "pb_fv_column_runs")
+    _check(lib().pb_column_runs(C.byref(desc), k, w, cus, out.ctypes.data_as(C.c_void_p), n.value, C.byref(n)),
+           "pb_column_runs")
     return out[:n.value]
 
 
@@ -440,8 +442,8 @@ class PatchBatch:
         _check(lib().pb_batch_reset(self.handle, 0), "pb_batch_reset")
 
     def set_tuning(self, fv_slab=0, fv_xcd_remap=1, fd_xcd_remap=1, fd_wg_per_cu=2, fv_dma=0, fd_ws=1,
-                   fv_persist=0, fv_column=0):
-        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap, fd_wg_per_cu, fv_dma, fd_ws, fv_persist, fv_column)
+                   fv_persist=0, fv_column=0, fd_column=2):
+        t = Tuning(fv_slab, fv_xcd_remap, fd_xcd_remap, fd_wg_per_cu, fv_dma, fd_ws, fv_persist, fv_column, fd_column)
         _check(lib().pb_batch_set_tuning(self.handle, C.byref(t)), "pb_batch_set_tuning")
 
     def get_tuning(self):

@@ -279,8 +279,8 @@ pb_status pb_workspace_size(const pb_batch_desc *desc, size_t *bytes)
     PB_API_END
 }
 
-pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, int32_t *runs, int32_t max_runs,
-                            int32_t *n_runs)
+pb_status pb_column_runs(const pb_batch_desc *desc, int32_t kind, int32_t w, int32_t cus, int32_t *runs,
+                         int32_t max_runs, int32_t *n_runs)
 {
     PB_API_BEGIN
     if (!n_runs || (max_runs > 0 && !runs)) { set_error("NULL argument"); return PB_EINVAL; }
@@ -289,8 +289,9 @@ pb_status pb_fv_column_runs(const pb_batch_desc *desc, int32_t w, int32_t cus, i
     pb_status st = validate(desc, false, &cells, nullptr, nullptr);
     if (st != PB_OK) return st;
     if (desc->dim != 3) { set_error("column runs apply to 3D batches"); return PB_EINVAL; }
+    if (kind != 0 && kind != 1) { set_error("kind must be 0 (FV) or 1 (Euler FD)"); return PB_EINVAL; }
     if (w < 1 || w > 8 || cus < 1) { set_error("need w in [1, 8] and cus >= 1"); return PB_EINVAL; }
-    const std::vector<int4> r = fv_column_runs(desc->n_patches, desc->p, desc->neighbor, w, cus);
+    const std::vector<int4> r = column_runs(kind, desc->n_patches, desc->p, desc->neighbor, w, cus);
     *n_runs = (int32_t)r.size();
     if ((int32_t)r.size() > max_runs) { set_error("runs buffer too small"); return PB_EINVAL; }
     for (size_t i = 0; i < r.size(); ++i) {
@@ -358,6 +359,7 @@ pb_status patch_batch_create(const pb_batch_desc *d, pb_batch **out)
         return hip_fail(e, "patch_batch_create");
     }
     st = launch_ctrl_init(b, b->stream);
+    if (st == PB_OK) st = runs_prepare(b);   // the default tunings' run tables
     if (st != PB_OK) { patch_batch_destroy(b); return st; }
     *out = b;
     return PB_OK;
@@ -377,7 +379,8 @@ pb_status patch_batch_destroy(pb_batch *b)
     if (b->d_fd_ws_items) (void)hipFree(b->d_fd_ws_items);
     if (b->d_fd_B) (void)hipFree(b->d_fd_B);
     if (b->d_fd_A) (void)hipFree(b->d_fd_A);
-    if (b->d_fv_runs) (void)hipFree(b->d_fv_runs);
+    if (b->fv_runs.d) (void)hipFree(b->fv_runs.d);
+    if (b->fd_runs.d) (void)hipFree(b->fd_runs.d);
     delete b;
     return PB_OK;
     PB_API_END
@@ -403,6 +406,7 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     if (t->fd_wg_per_cu < 0 || t->fd_wg_per_cu > 2) { set_error("fd_wg_per_cu must be 0, 1 or 2"); return PB_EINVAL; }
     if (t->fv_persist < 0 || t->fv_persist > 8) { set_error("fv_persist must be in [0, 8]"); return PB_EINVAL; }
     if (t->fv_column < 0 || t->fv_column > 8) { set_error("fv_column must be in [0, 8]"); return PB_EINVAL; }
+    if (t->fd_column < 0 || t->fd_column > 8) { set_error("fd_column must be in [0, 8]"); return PB_EINVAL; }
     if (t->fd_ws < 0 || t->fd_ws > 2) { set_error("fd_ws must be 0, 1 or 2"); return PB_EINVAL; }
     b->fv_slab = t->fv_slab;
     b->fv_xcd_remap = t->fv_xcd_remap ? 1 : 0;
@@ -412,9 +416,10 @@ pb_status pb_batch_set_tuning(pb_batch *b, const pb_tuning *t)
     b->fd_ws = t->fd_ws;
     b->fv_persist = t->fv_persist;
     b->fv_column = t->fv_column;
+    b->fd_column = t->fd_column;
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
-    return fv_column_prepare(b);
+    return runs_prepare(b);
     PB_API_END
 }
 
@@ -430,6 +435,7 @@ pb_status pb_batch_get_tuning(const pb_batch *b, pb_tuning *out)
     out->fd_ws = b->fd_ws;
     out->fv_persist = b->fv_persist;
     out->fv_column = b->fv_column;
+    out->fd_column = b->fd_column;
     return PB_OK;
     PB_API_END
 }

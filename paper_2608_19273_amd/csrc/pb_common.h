@@ -252,9 +252,14 @@ struct pb_batch {
     int fv_dma = 0;
     int fv_persist = 0;   // FV 3D, one p: > 0 = balanced plane schedule over this many work-groups per CU
     int fv_column = 0;    // FV 3D: > 0 = column runs along +z chains, about this many work-groups per CU
-    void *d_fv_runs = nullptr;   // column runs (int4: patch, first plane, planes, 0), one per unit
-    int fv_n_runs = 0;
-    int fv_runs_w = 0;            // the fv_column the table was built for
+    int fd_column = 2;    // Euler FD: likewise (runs of whole patches at least); 0 = one work-group per patch
+    // column-run tables (int4: patch, first plane, planes, 0; one per unit)
+    // of the FV and the Euler FD plane kernels, and the w each was built for
+    struct RunTable {
+        void *d = nullptr;
+        int n = 0, w = 0;
+    };
+    RunTable fv_runs, fd_runs;
     // SRHD guess mode
     int guess = PB_GUESS_PLAIN;
     const pb_mlp *mlp = nullptr;
@@ -345,11 +350,15 @@ bool fv_dma_eligible(const pb_batch *b);
 constexpr size_t kFvSmallLds = 64 * 1024;
 bool fv_small_eligible(const pb_batch *b);
 // the column runs (patch, first plane, planes, 0) of a 3D batch with
-// neighbour table nbr [K][6], about w work-groups per CU on `cus` CUs
-std::vector<int4> fv_column_runs(int K, const int *p, const int *nbr, int w, int cus);
-// (re)builds the column-run table of the FV plane-march kernel for
-// b->fv_column (frees it when 0); host call, done when the tuning is set
-pb_status fv_column_prepare(pb_batch *b);
+// neighbour table nbr [K][6], about w work-groups per CU on `cus` CUs.
+// kind 0 (FV): links between patches of one p >= 2, runs of any length;
+// kind 1 (Euler FD, halo 3): links between patches of one p >= 4, runs of
+// whole patches at least.
+std::vector<int4> column_runs(int kind, int K, const int *p, const int *nbr, int w, int cus);
+// (re)builds the column-run tables for b->fv_column and b->fd_column (a
+// table is freed when its w is 0 or does not apply); host call, done when
+// the batch is created and when its tuning is set, never inside a capture
+pb_status runs_prepare(pb_batch *b);
 // dt of an FD step: dt_fixed if > 0, else cfl / sum_d (rho(B_d) / dx_min)
 double fd_dt(const pb_batch *b, double cfl, double dt_fixed);
 // uploads the FD work list and B_d (library-owned; done once, before any capture)

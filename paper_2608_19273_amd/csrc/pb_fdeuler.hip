@@ -86,11 +86,16 @@ __device__ __forceinline__ void load5(const double *__restrict__ base, unsigned 
 //   S = 3: acc += dt/6 R                              (acc = Q^{n+1})
 //   S = 4: acc = y + dt R                             (y = Q^n)
 // kLam: fold the speeds of the new state (last stage, CFL mode).
+// runs (non-null): unit u marches runs[u] = (patch, first plane, planes, 0)
+// up the patch's +z chain, crossing patch tops without a restart (the
+// column-run table of the FV kernel); else unit u is slab u % n_slabs of
+// patch u / n_slabs.
 template <int S, bool kLam>
 __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     const double *__restrict__ y, const double *__restrict__ q0, double *__restrict__ ynext,
     double *__restrict__ acc, const PatchDev *__restrict__ patches, int n_units, int n_slabs, int slab, int remap,
-    Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot, double dt_fixed, double gamma, double sigma)
+    const int4 *__restrict__ runs, Ctrl *__restrict__ ctrl, double *__restrict__ part, int slot, double dt_fixed,
+    double gamma, double sigma)
 {
     constexpr int N = kEN;
     constexpr bool kReadQ0 = S == 1 || S == 2;
@@ -102,24 +107,37 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
 
     const int t = threadIdx.x;
     const int unit = remap ? xcd_remap(blockIdx.x, n_units) : (int)blockIdx.x;
-    const int k = unit / n_slabs, sl = unit - k * n_slabs;
-    const PatchDev P = patches[k];
-    const int p = P.p;
+    int kc, z0, n;   // the unit's first patch and plane, and its planes
+    if (runs) {
+        const int4 r = runs[unit];
+        kc = r.x;
+        z0 = r.y;
+        n = r.z;
+    } else {
+        kc = unit / n_slabs;
+        const int sl = unit - kc * n_slabs;
+        z0 = sl * slab;
+        n = max(0, min(patches[kc].p, z0 + slab) - z0);
+    }
+    const int p = patches[kc].p;
     const unsigned C = (unsigned)(p * p * p), pp = (unsigned)(p * p);
-    // patch blocks: this patch in every buffer, the z neighbours in y
-    const double *yo = y + P.off * N, *ylo = y + patches[P.nbr[4]].off * N, *yhi = y + patches[P.nbr[5]].off * N;
-    const double *q0o = q0 + P.off * N, *acco = acc + P.off * N;
-    double *yno = ynext + P.off * N, *accw = acc + P.off * N;
-    const int z0 = sl * slab, z1 = min(p, z0 + slab);
+    // patch blocks of the current patch in every buffer and its z neighbours
+    // in y (they move up one patch when the march crosses a patch top)
+    const double *yo = y + patches[kc].off * N, *ylo = y + patches[patches[kc].nbr[4]].off * N;
+    int kn = patches[kc].nbr[5];
+    const double *yhi = y + patches[kn].off * N;
+    const double *q0o = q0 + patches[kc].off * N, *acco = acc + patches[kc].off * N;
+    double *yno = ynext + patches[kc].off * N, *accw = acc + patches[kc].off * N;
+    double inv_dx = patches[kc].inv_dx;
     // a slab can start beyond the last plane of a patch smaller than the
     // batch maximum: such a unit only takes part in the reductions
-    const bool work = z0 < p;
+    const bool work = n > 0;
     const bool active = work && t < p * p;
     const int x = active ? t % p : 0, yy = active ? t / p : 0;
     const unsigned cxy = (unsigned)(yy * p + x);
     const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot];
     const double gm1 = gamma - 1.0;
-    const double c4 = P.inv_dx / 12.0, cko = sigma * P.inv_dx / 64.0;
+    double c4 = inv_dx / 12.0, cko = sigma * inv_dx / 64.0;
     const Euler<3> ph{gamma};
     const int qs = q_slot(x, yy), fxs = fx_slot(x, yy), fys = fy_slot(x, yy);
 
@@ -129,9 +147,8 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     // branch: a load under one makes the compiler copy its target registers
     // at the join, which waits for the load there and then.
     const bool halo = work && t < 12 * p;
-    int hq, hf;
+    int hq, hf, hside, hcell;
     bool hflux, hx;
-    const double *hsrc;   // unknown 0 of the halo cell's source column, plane 0
     {
         const int th = halo ? t : 0;
         const int side = th / (3 * p), r = th - side * 3 * p, layer = r / p, j = r - layer * p;
@@ -140,15 +157,23 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         else if (side == 1) { dx_ = p + layer;  dy_ = j; sx = layer;         sy = j; }
         else if (side == 2) { dx_ = j; dy_ = -1 - layer; sx = j; sy = p - 1 - layer; }
         else                { dx_ = j; dy_ = p + layer;  sx = j; sy = layer; }
-        // (a select, not P.nbr[side]: a lane-varying index would send the
-        // patch record to scratch memory)
-        const int nb = side == 0 ? P.nbr[0] : side == 1 ? P.nbr[1] : side == 2 ? P.nbr[2] : P.nbr[3];
-        hsrc = y + patches[nb].off * N + (sy * p + sx);
+        hside = side;
+        hcell = sy * p + sx;
         hq = q_slot(dx_, dy_);
         hflux = layer < 2;
         hx = side < 2;
         hf = hx ? fx_slot(dx_, dy_) : fy_slot(dx_, dy_);
     }
+    // unknown 0 of the halo cell's source column, plane 0, for patch kk (a
+    // select over the record's entries, not nbr[side]: a lane-varying index
+    // would send the patch record to scratch memory)
+    auto halo_src = [&](int kk) -> const double * {
+        const PatchDev &Q = patches[kk];
+        const int nb = hside == 0 ? Q.nbr[0] : hside == 1 ? Q.nbr[1] : hside == 2 ? Q.nbr[2] : Q.nbr[3];
+        return y + patches[nb].off * N + hcell;
+    };
+    const double *hsrc = halo_src(kc);   // the current patch
+    const double *hsrcn = halo_src(kn);  // its +z neighbour (the run's next patch)
     // this thread's column on plane zz (zz in [-3, p + 3): the planes outside
     // the patch come from the z neighbours; the choice is uniform)
     auto col = [&](int zz, double *out) {
@@ -172,17 +197,19 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         load5(hsrc, (unsigned)z0 * pp, C, hr);
     }
 
+    int z = z0;   // the current plane, inside the current patch
 #pragma unroll 1
-    for (int z = z0; z < z1; ++z) {
+    for (int i = 0; i < n; ++i) {
         const unsigned own = (unsigned)z * pp + cxy;
         double q0v[N], accv[N];
         {
             // plane z+3 enters the window; the load of plane z+4 replaces it
-            // (at the slab's top a plane inside the window's reach is
-            // loaded again instead, unused)
+            // (near the run's top a plane inside the window's reach is
+            // loaded again instead, unused; p >= 4 keeps every plane read
+            // inside the current patch or the next)
 #pragma unroll
             for (int v = 0; v < N; ++v) qr[6][v] = rl[v];
-            col(min(z + 4, z1 + 2), rl);
+            col(z + min(4, n + 2 - i), rl);
             if (kReadQ0) load5(q0o, own, C, q0v);
             if (kReadAcc) load5(acco, own, C, accv);
             euler_ip(qr[5], gm1, ar[4]);
@@ -201,7 +228,10 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         double hv[N];
 #pragma unroll
         for (int v = 0; v < N; ++v) hv[v] = hr[v];
-        load5(hsrc, (unsigned)min(z + 1, z1 - 1) * pp, C, hr);
+        {
+            const int zh = z + min(1, n - 1 - i);   // the next plane of the run, or this one at its top
+            load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hr);
+        }
         if (halo) {
 #pragma unroll
             for (int v = 0; v < N; ++v) sQ[v][hq] = hv[v];
@@ -291,11 +321,31 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             }
             // slide the windows up one plane
 #pragma unroll
-            for (int i = 0; i < 6; ++i)
+            for (int w = 0; w < 6; ++w)
 #pragma unroll
-                for (int v = 0; v < N; ++v) qr[i][v] = qr[i + 1][v];
+                for (int v = 0; v < N; ++v) qr[w][v] = qr[w + 1][v];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { ar[i][0] = ar[i + 1][0]; ar[i][1] = ar[i + 1][1]; }
+            for (int w = 0; w < 4; ++w) { ar[w][0] = ar[w + 1][0]; ar[w][1] = ar[w + 1][1]; }
+        }
+        if (++z == p && i + 1 < n) {
+            // the run continues in the +z neighbour: every buffer's patch
+            // block moves up one patch (the window and the loads in flight
+            // already come from it)
+            z = 0;
+            const long long off = patches[kn].off;
+            ylo = yo;
+            yo = yhi;
+            q0o = q0 + off * N;
+            acco = acc + off * N;
+            yno = ynext + off * N;
+            accw = acc + off * N;
+            inv_dx = patches[kn].inv_dx;
+            c4 = inv_dx / 12.0;
+            cko = sigma * inv_dx / 64.0;
+            hsrc = hsrcn;
+            kn = patches[kn].nbr[5];
+            yhi = y + patches[kn].off * N;
+            hsrcn = halo_src(kn);
         }
     }
     if (kFinal) {
@@ -496,8 +546,8 @@ namespace {
 // G > 0: the small-patch kernel with G patches per work-group (n_units = work-groups)
 template <int S, bool kLam>
 void launch_s(dim3 g, hipStream_t s, const double *y, const double *q0, double *yn, double *acc, const pb_batch *b,
-              int n_units, int n_slabs, int slab, int G, Ctrl *ctrl, double *part, int slot, double dt_fixed,
-              double sigma)
+              int n_units, int n_slabs, int slab, const int4 *runs, int G, Ctrl *ctrl, double *part, int slot,
+              double dt_fixed, double sigma)
 {
     if (G > 0) {
         const int p = b->p[0];
@@ -506,7 +556,8 @@ void launch_s(dim3 g, hipStream_t s, const double *y, const double *q0, double *
                            b->d_patches, b->K, p, G, ctrl, part, slot, dt_fixed, b->params[0], sigma);
     } else {
         launch_main(b, fd_euler_stage_kernel<S, kLam>, g, dim3(kFvThreads), 0, s, y, q0, yn, acc, b->d_patches,
-                           n_units, n_slabs, slab, b->fd_xcd_remap, ctrl, part, slot, dt_fixed, b->params[0], sigma);
+                           n_units, n_slabs, slab, b->fd_xcd_remap, runs, ctrl, part, slot, dt_fixed, b->params[0],
+                           sigma);
     }
 }
 
@@ -525,7 +576,10 @@ pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const voi
         const size_t per = (size_t)kSmallW * (p * p * p + 18 * p * p) * sizeof(double);
         G = std::max(1, std::min(kFvThreads / (p * p * p), (int)(kFvSmallLds / per)));
     }
-    const int n_units = G > 0 ? (b->K + G - 1) / G : b->K * n_slabs;
+    // column runs along +z chains when the tuning asks for them (the table is
+    // built when the batch is created or its tuning set)
+    const int4 *runs = (G == 0 && b->fd_column > 0 && b->fd_runs.d) ? static_cast<const int4 *>(b->fd_runs.d) : nullptr;
+    const int n_units = G > 0 ? (b->K + G - 1) / G : runs ? b->fd_runs.n : b->K * n_slabs;
     Ctrl *ctrl = reinterpret_cast<Ctrl *>(b->ws);
     const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
     double *part = reinterpret_cast<double *>(b->ws + L.part);
@@ -535,7 +589,7 @@ pb_status launch_fd_euler_stage(pb_batch *b, int stage, int rk_stages, const voi
     const double *yi = static_cast<const double *>(y), *q0i = static_cast<const double *>(q0);
     double *yn = static_cast<double *>(ynext), *ac = static_cast<double *>(acc);
     const dim3 g(n_units);
-#define PB_FDE_ARGS g, s, yi, q0i, yn, ac, b, n_units, n_slabs, slab, G, ctrl, part, slot, dt_fixed, sigma
+#define PB_FDE_ARGS g, s, yi, q0i, yn, ac, b, n_units, n_slabs, slab, runs, G, ctrl, part, slot, dt_fixed, sigma
     switch (S) {
     case 0: launch_s<0, false>(PB_FDE_ARGS); break;
     case 1: launch_s<1, false>(PB_FDE_ARGS); break;

@@ -971,9 +971,9 @@ pb_status launch_typed(pb_batch *b, const Ph &ph, const void *qin, void *qout, i
     // once (uniform p)
     FvPlan plan{n_units, n_slabs, slab, b->fv_xcd_remap, 0, nullptr};
     auto plane_kernel = [&](auto kern) -> pb_status {
-        if (DIM == 3 && b->fv_column > 0 && b->d_fv_runs) {
-            plan.runs = static_cast<const int4 *>(b->d_fv_runs);
-            plan.n_units = b->fv_n_runs;
+        if (DIM == 3 && b->fv_column > 0 && b->fv_runs.d) {
+            plan.runs = static_cast<const int4 *>(b->fv_runs.d);
+            plan.n_units = b->fv_runs.n;
         } else if (DIM == 3 && b->fv_persist > 0 && b->uniform_p) {
             int cus = 0;
             pb_status st = device_cus(&cus);
@@ -1075,20 +1075,23 @@ pb_status dispatch(pb_batch *b, F &&f)
 }  // namespace
 
 // Column runs: the +z link k -> s = nbr[k][+z] holds where s's -z neighbour
-// is k and both patches have the same p >= 2 (the march then reads s's first
-// planes as the continuation of k's column).  Links form chains and cycles;
-// each gets a number of runs proportional to its planes (at least one, at
-// most one per plane), about fv_column work-groups per CU in total, and runs
-// of one chain split its planes as evenly as integers allow.  Units are
-// ordered chain after chain, chains by their smallest patch index, so that
-// with the XCD remap the runs of neighbouring chains of a grid in patch order
-// share an XCD (and its L2) and reach equal heights at about the same time.
-std::vector<int4> fv_column_runs(int K, const int *p, const int *nbr, int w, int cus)
+// is k and both patches have the same p (>= 2 for the FV march, >= 4 for the
+// FD march, whose window reaches 4 planes ahead), so the march reads s's
+// first planes as the continuation of k's column.  Links form chains and
+// cycles; each gets a number of runs proportional to its planes (at least
+// one; at most one per plane for FV, per patch for FD), about w work-groups
+// per CU in total, and runs of one chain split its planes as evenly as
+// integers allow.  Units are ordered chain after chain, chains by their
+// smallest patch index, so that with the XCD remap the runs of neighbouring
+// chains of a grid in patch order share an XCD (and its L2) and reach equal
+// heights at about the same time.
+std::vector<int4> column_runs(int kind, int K, const int *p, const int *nbr, int w, int cus)
 {
+    const int pmin = kind == 0 ? 2 : 4;
     std::vector<int> succ(K, -1), pred(K, -1);
     for (int k = 0; k < K; ++k) {
         const int s = nbr[6 * k + 5];
-        if (p[k] >= 2 && p[s] == p[k] && nbr[6 * s + 4] == k) {
+        if (p[k] >= pmin && p[s] == p[k] && nbr[6 * s + 4] == k) {
             succ[k] = s;
             pred[s] = k;
         }
@@ -1125,7 +1128,8 @@ std::vector<int4> fv_column_runs(int K, const int *p, const int *nbr, int w, int
         const std::vector<int> &c = chains[o.second];
         const int pc = p[c[0]];
         const long long planes = (long long)c.size() * pc;
-        const long long r = std::max(1LL, std::min(planes, std::llround(slots * (double)planes / (double)total)));
+        const long long rmax = kind == 0 ? planes : (long long)c.size();
+        const long long r = std::max(1LL, std::min(rmax, std::llround(slots * (double)planes / (double)total)));
         for (long long j = 0; j < r; ++j) {
             const long long s0 = j * planes / r, s1 = (j + 1) * planes / r;
             runs.push_back(make_int4(c[s0 / pc], (int)(s0 % pc), (int)(s1 - s0), 0));
@@ -1134,20 +1138,25 @@ std::vector<int4> fv_column_runs(int K, const int *p, const int *nbr, int w, int
     return runs;
 }
 
-pb_status fv_column_prepare(pb_batch *b)
+namespace {
+
+pb_status build_table(pb_batch *b, pb_batch::RunTable &tab, int kind, int w, bool applies)
 {
-    if (b->fv_column == b->fv_runs_w && (b->d_fv_runs || b->fv_column <= 0 || b->dim != 3)) return PB_OK;
-    b->fv_runs_w = 0;
-    if (b->d_fv_runs) {
-        PB_HIP(hipFree(b->d_fv_runs));
-        b->d_fv_runs = nullptr;
-        b->fv_n_runs = 0;
+    if (tab.w == w && (tab.d || w <= 0 || !applies)) return PB_OK;
+    tab.w = 0;
+    if (tab.d) {
+        PB_HIP(hipFree(tab.d));
+        tab.d = nullptr;
+        tab.n = 0;
     }
-    if (b->fv_column <= 0 || b->dim != 3) return PB_OK;
+    if (w <= 0 || !applies) {
+        tab.w = w;
+        return PB_OK;
+    }
     int cus = 0;
     pb_status st = device_cus(&cus);
     if (st != PB_OK) return st;
-    const std::vector<int4> runs = fv_column_runs(b->K, b->p.data(), b->nbr.data(), b->fv_column, cus);
+    const std::vector<int4> runs = column_runs(kind, b->K, b->p.data(), b->nbr.data(), w, cus);
     if ((long long)runs.size() > max_units(b->K)) { set_error("column runs exceed the partial buffers"); return PB_EINVAL; }
     void *d = nullptr;
     PB_HIP(hipMalloc(&d, runs.size() * sizeof(int4)));
@@ -1156,10 +1165,19 @@ pb_status fv_column_prepare(pb_batch *b)
         set_error("hipMemcpy of the column runs failed");
         return PB_EHIP;
     }
-    b->d_fv_runs = d;
-    b->fv_n_runs = (int)runs.size();
-    b->fv_runs_w = b->fv_column;
+    tab.d = d;
+    tab.n = (int)runs.size();
+    tab.w = w;
     return PB_OK;
+}
+
+}  // namespace
+
+pb_status runs_prepare(pb_batch *b)
+{
+    pb_status st = build_table(b, b->fv_runs, 0, b->fv_column, b->dim == 3);
+    if (st != PB_OK) return st;
+    return build_table(b, b->fd_runs, 1, b->fd_column, b->dim == 3 && b->pde == PB_PDE_EULER);
 }
 
 bool fv_small_eligible(const pb_batch *b)

@@ -49,6 +49,7 @@ pb_tuning current(const pb_batch *b)
     t.fd_ws = b->fd_ws;
     t.fv_persist = b->fv_persist;
     t.fv_column = b->fv_column;
+    t.fd_column = b->fd_column;
     return t;
 }
 
@@ -62,7 +63,8 @@ pb_status apply(pb_batch *b, const pb_tuning &t)
     b->fd_ws = t.fd_ws;
     b->fv_persist = t.fv_persist;
     b->fv_column = t.fv_column;
-    return fv_column_prepare(b);
+    b->fd_column = t.fd_column;
+    return runs_prepare(b);
 }
 
 std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
@@ -115,6 +117,18 @@ std::vector<pb_tuning> candidates(const pb_batch *b, int kind)
                     t.fv_dma = 1;
                     c.push_back(t);
                 }
+    } else if (b->pde == PB_PDE_EULER) {
+        if (b->uniform_p && b->p[0] * b->p[0] * b->p[0] <= 256) {
+            c.push_back(base);   // the small-patch kernel has no launch-shape choices
+        } else {
+            for (int w : {2, 4, 0})
+                for (int remap = 1; remap >= 0; --remap) {
+                    pb_tuning t = base;
+                    t.fd_column = w;
+                    t.fd_xcd_remap = remap;
+                    c.push_back(t);
+                }
+        }
     } else {
         for (int ws = 2; ws >= 1; --ws)
             for (int remap = 1; remap >= 0; --remap) {
@@ -142,6 +156,8 @@ pb_status trial(pb_batch *b, int kind, double cfl, double dt_fixed, double sigma
     void *qin = b->state[b->cur], *qout = b->state[b->cur ^ 1];
     if (kind == 0) return launch_fv_step(b, qin, qout, 0, 0, dt_fixed, cfl, s);
     const WsLayout L = ws_layout(b->pde, b->dim, b->h, b->total_cells, b->N, b->storage, b->K);
+    if (b->pde == PB_PDE_EULER)   // RK stage 1: reads Q^n, writes the stage value and the other state buffer
+        return launch_fd_euler_stage(b, 0, 4, qin, qin, b->ws + L.yA, qout, 0, dt_fixed, cfl, sigma, s);
     return launch_fd_stage(b, 0, 4, qin, qin, b->ws + L.yA, qout, fd_dt(b, cfl, dt_fixed), sigma, s);
 }
 
@@ -160,9 +176,14 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
     if (kind != 0 && kind != 1) { set_error("pb_autotune: kind must be 0 (FV) or 1 (FD)"); return PB_EINVAL; }
     if (trials < 1 || trials > 1000) { set_error("pb_autotune: trials must be in [1, 1000]"); return PB_EINVAL; }
     if (kind == 0 && b->pde == PB_PDE_LINSYM) { set_error("pb_autotune: the linear system has no FV step"); return PB_EINVAL; }
-    if (kind == 1 && b->pde != PB_PDE_LINSYM) {
-        set_error("pb_autotune: FD tuning applies to the linear system (the Euler FD kernels have no launch-shape choice)");
+    if (kind == 1 && b->pde != PB_PDE_LINSYM && b->pde != PB_PDE_EULER) {
+        set_error("pb_autotune: FD tuning applies to the linear system and to Euler");
         return PB_EINVAL;
+    }
+    if (kind == 1 && b->pde == PB_PDE_EULER &&
+        (b->dim != 3 || b->storage != PB_STORE_FP64 || b->pmax > kFvPmax || b->h < 3)) {
+        set_error("pb_autotune: the Euler FD step needs dim 3, FP64 storage, p <= 16 and a halo of 3");
+        return PB_EUNSUPPORTED;
     }
     if (kind == 0 && b->pde == PB_PDE_SRHD && b->storage != PB_STORE_FP64) { set_error("SRHD runs in FP64 storage"); return PB_EUNSUPPORTED; }
     if (kind == 0 && b->pmax > kFvPmax) { set_error("fv_rusanov_step: p > 16 is not supported"); return PB_EUNSUPPORTED; }
@@ -187,7 +208,7 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
             return pb_batch_set_tuning(b, &it->second);
         }
     }
-    if (kind == 1) {
+    if (kind == 1 && b->pde == PB_PDE_LINSYM) {
         pb_status st = fd_prepare(b);
         if (st != PB_OK) return st;
     }
@@ -204,6 +225,8 @@ pb_status pb_autotune(pb_batch *b, int32_t kind, double cfl, double dt_fixed, do
             st = launch_srhd_c2p(b, b->state[b->cur], 0, cfl_mode, cfl, s);
         else if (cfl_mode)
             st = launch_fv_lambda(b, b->state[b->cur], cfl, s);
+    } else if (b->pde == PB_PDE_EULER && cfl_mode) {
+        st = launch_fv_lambda(b, b->state[b->cur], cfl, s);   // dt of Q^n into slot 0, as a step's start
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (st == PB_OK && hipEventCreate(&e0) != hipSuccess) st = hip_fail(hipErrorUnknown, "hipEventCreate");
@@ -261,7 +284,7 @@ pb_status pb_autotune_cache_save(const char *path)
     for (auto &e : g_cache)
         f << e.first << ' ' << e.second.fv_slab << ' ' << e.second.fv_xcd_remap << ' ' << e.second.fd_xcd_remap << ' '
           << e.second.fd_wg_per_cu << ' ' << e.second.fv_dma << ' ' << e.second.fd_ws << ' ' << e.second.fv_persist
-          << ' ' << e.second.fv_column << '\n';
+          << ' ' << e.second.fv_column << ' ' << e.second.fd_column << '\n';
     if (!f) { set_error(std::string("write failed: ") + path); return PB_EINVAL; }
     return PB_OK;
     PB_API_END
@@ -284,14 +307,21 @@ pb_status pb_autotune_cache_load(const char *path, int32_t *n_loaded)
         pb_tuning t{};
         bool ok = (bool)(in >> key >> t.fv_slab >> t.fv_xcd_remap >> t.fd_xcd_remap >> t.fd_wg_per_cu >> t.fv_dma >>
                          t.fd_ws);
-        if (ok && !(in >> t.fv_persist)) {   // six-field line: slab mode
+        // shorter lines (written before the later fields existed) load those
+        // fields at their defaults: fv_persist 0, fv_column 0, fd_column 2
+        t.fd_column = 2;
+        if (ok && !(in >> t.fv_persist)) {
             t.fv_persist = 0;
             in.clear();
-        } else if (ok && !(in >> t.fv_column)) {   // seven-field line: no column runs
+        } else if (ok && !(in >> t.fv_column)) {
             t.fv_column = 0;
+            in.clear();
+        } else if (ok && !(in >> t.fd_column)) {
+            t.fd_column = 2;
             in.clear();
         }
         if (!ok || (in >> extra) || t.fv_persist < 0 || t.fv_persist > 8 || t.fv_column < 0 || t.fv_column > 8 ||
+            t.fd_column < 0 || t.fd_column > 8 ||
             t.fv_slab < 0 || t.fv_slab > kFvPmax || t.fv_xcd_remap < 0 || t.fv_xcd_remap > 1 ||
             t.fd_xcd_remap < 0 || t.fd_xcd_remap > 1 || t.fd_wg_per_cu < 0 || t.fd_wg_per_cu > 2 || t.fv_dma < 0 ||
             t.fv_dma > 1 || t.fd_ws < 0 || t.fd_ws > 2) {

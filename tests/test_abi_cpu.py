@@ -149,20 +149,21 @@ def test_autotune_rejects_bad_arguments_without_gpu():
 
 def test_autotune_cache_file_round_trip(tmp_path):
     """the tuning cache is host-side: entries load, save and reload unchanged
-    (a six-field line loads with fv_persist = fv_column = 0, a seven-field
-    line with fv_column = 0); a malformed line is rejected with the entries
-    before it kept"""
+    (lines of six, seven or eight fields load the missing ones at their
+    defaults: fv_persist 0, fv_column 0, fd_column 2); a malformed line is
+    rejected with the entries before it kept"""
     pb.pb_autotune_cache_clear()
     src = tmp_path / "in.txt"
     src.write_text("fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1\n\nfd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0\n"
-                   "fv/pde2/d3/N5/s0/h1/16x768 0 1 1 2 0 1 0 3\n")
-    assert pb.pb_autotune_cache_load(str(src)) == 3
+                   "fv/pde2/d3/N5/s0/h1/16x768 0 1 1 2 0 1 0 3\nfd/pde2/d3/N5/s0/h3/16x2048 0 1 1 2 0 1 0 0 4\n")
+    assert pb.pb_autotune_cache_load(str(src)) == 4
     out = tmp_path / "out.txt"
     pb.pb_autotune_cache_save(str(out))
     lines = sorted(out.read_text().splitlines())
-    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1 0",
-                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0 0 0",
-                            "fv/pde2/d3/N5/s0/h1/16x768 0 1 1 2 0 1 0 3"])
+    assert lines == sorted(["fv/pde2/d3/N5/s0/h1/16x2048 8 1 1 2 1 1 1 0 2",
+                            "fd/pde3/d3/N58/s0/h3/4x1024,8x2048,16x1024 0 1 0 1 0 0 0 0 2",
+                            "fv/pde2/d3/N5/s0/h1/16x768 0 1 1 2 0 1 0 3 2",
+                            "fd/pde2/d3/N5/s0/h3/16x2048 0 1 1 2 0 1 0 0 4"])
     bad = tmp_path / "bad.txt"
     bad.write_text("fv/x 4 1 1 2 1 1\nfv/y 99 1 1 2 1 1\nfv/z 4 1 1 2 1 1\n")
     with pytest.raises(pb.PbError, match="bad2.txt:1"):
@@ -175,8 +176,12 @@ def test_autotune_cache_file_round_trip(tmp_path):
         pb.pb_autotune_cache_load(str(bad3))
     with pytest.raises(pb.PbError, match="bad4.txt:1"):
         bad4 = tmp_path / "bad4.txt"
-        bad4.write_text("fv/u 4 1 1 2 1 1 0 3 1\n")
+        bad4.write_text("fv/u 4 1 1 2 1 1 0 3 9\n")
         pb.pb_autotune_cache_load(str(bad4))
+    with pytest.raises(pb.PbError, match="bad5.txt:1"):
+        bad5 = tmp_path / "bad5.txt"
+        bad5.write_text("fv/t 4 1 1 2 1 1 0 3 2 1\n")
+        pb.pb_autotune_cache_load(str(bad5))
     with pytest.raises(pb.PbError, match="bad.txt:2"):
         pb.pb_autotune_cache_load(str(bad))
     pb.pb_autotune_cache_save(str(out))
@@ -215,10 +220,10 @@ def test_offload_create_rejects_bad_descriptions():
     assert L.pb_offload_destroy(None) == pb.PB_EINVAL
 
 
-def _check_runs(b, runs, w, cus):
+def _check_runs(b, runs, w, cus, pmin=2):
     """every plane of every patch in exactly one run; inside a run the plane
     after a patch top is the +z neighbour's first plane, and only along a link
-    (the neighbour's -z neighbour is the patch, same p); about w * cus runs"""
+    (the neighbour's -z neighbour is the patch, same p >= pmin)"""
     count = [np.zeros(int(pk), np.int32) for pk in b.p]
     for k, z0, n, pad in runs:
         assert pad == 0 and n >= 1 and 0 <= z0 < b.p[k]
@@ -230,7 +235,7 @@ def _check_runs(b, runs, w, cus):
                 s = b.nbr[k, 5]
                 k_next, z = s, 0
                 if _ + 1 < n:   # the run continues: only along a link
-                    assert b.nbr[s, 4] == k and b.p[s] == b.p[k] >= 2
+                    assert b.nbr[s, 4] == k and b.p[s] == b.p[k] >= pmin
                 k = k_next
     for c in count:
         np.testing.assert_array_equal(c, 1)
@@ -241,13 +246,13 @@ def _check_runs(b, runs, w, cus):
 @pytest.mark.parametrize("grid,w", [((16, 16, 8), 3), ((8, 8, 3), 1), ((8, 8, 3), 3), ((4, 4, 2), 2),
                                     ((16, 16, 3), 2)])
 def test_column_runs_cover_every_plane(grid, w):
-    """The column-run schedule (pb_fv_column_runs, the table fv_column = w
+    """The column-run schedule (pb_column_runs, the table fv_column = w
     uploads): z-periodic grids give one cycle per column; the runs of a
     column split its planes evenly and, with enough planes, number about
     w * 256 in total; chains come in order of their smallest patch."""
     b = I.make_uniform_batch(grid, 16, 1, "euler", [1.4], 5, 1.0 / 16)
     d, keep = desc_for(b)
-    runs = pb.pb_fv_column_runs(d, w, 256)
+    runs = pb.pb_column_runs(d, "fv", w, 256)
     _check_runs(b, runs, w, 256)
     nx, ny, nz = grid
     columns = nx * ny
@@ -275,7 +280,7 @@ def test_column_runs_open_chains_and_ragged():
             b.nbr[k, 5] = k
     d, keep = desc_for(b)
     for w in (1, 3, 8):
-        runs = pb.pb_fv_column_runs(d, w, 4)
+        runs = pb.pb_column_runs(d, "fv", w, 4)
         _check_runs(b, runs, w, 4)
         # 16 chains of 24 planes, 4 w slots: runs per chain round(w / 4), at least 1
         assert len(runs) == 16 * max(1, round(w * 4 / 16))
@@ -286,14 +291,40 @@ def test_column_runs_open_chains_and_ragged():
     rb = I.Batch(dim=3, p=ps, dx=1.0 / ps, nbr=nbr, halo=1, pde="euler", params=np.array([1.4]), n_unknowns=5,
                  state=np.zeros(5 * int((ps.astype(np.int64) ** 3).sum())))
     d2, keep2 = desc_for(rb)
-    runs = pb.pb_fv_column_runs(d2, 3, 256)
+    runs = pb.pb_column_runs(d2, "fv", 3, 256)
     _check_runs(rb, runs, 3, 256)
     assert len(runs) == int(ps.sum())   # more slots than planes: one run per plane
     n = C.c_int32(-1)
-    assert pb.lib().pb_fv_column_runs(C.byref(d2), 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert pb.lib().pb_column_runs(C.byref(d2), 0, 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
     assert n.value == len(runs)
-    assert pb.lib().pb_fv_column_runs(C.byref(d2), 0, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
-    assert pb.lib().pb_fv_column_runs(C.byref(d2), 9, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert pb.lib().pb_column_runs(C.byref(d2), 0, 0, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert pb.lib().pb_column_runs(C.byref(d2), 0, 9, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
     b2 = I.config0()
     d3, keep3 = desc_for(b2)
-    assert pb.lib().pb_fv_column_runs(C.byref(d3), 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert pb.lib().pb_column_runs(C.byref(d3), 0, 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+    assert pb.lib().pb_column_runs(C.byref(d2), 2, 3, 256, None, 0, C.byref(n)) == pb.PB_EINVAL
+
+
+@pytest.mark.parametrize("grid,w,per_col", [((16, 16, 8), 2, 2), ((16, 16, 8), 4, 4), ((8, 8, 3), 2, 3),
+                                            ((4, 4, 2), 8, 2)])
+def test_fd_column_runs_whole_patches(grid, w, per_col):
+    """The Euler FD rule (fd_column): runs are whole patches at least, so a
+    column of nz patches gets at most nz runs, and the halo of 3 needs
+    p >= 4 for a link: a batch of 3^3 patches has no links (one run per
+    patch)."""
+    b = I.make_uniform_batch(grid, 16, 3, "euler", [1.4], 5, 1.0 / 16)
+    d, keep = desc_for(b)
+    runs = pb.pb_column_runs(d, "fd", w, 256)
+    _check_runs(b, runs, w, 256, pmin=4)
+    nx, ny, nz = grid
+    assert len(runs) == nx * ny * per_col
+    assert np.all(runs[:, 2] >= 16)
+    b3 = I.make_uniform_batch((4, 4, 4), 3, 3, "euler", [1.4], 5, 1.0 / 3)
+    d3, keep3 = desc_for(b3)
+    runs3 = pb.pb_column_runs(d3, "fd", 2, 256)
+    _check_runs(b3, runs3, 2, 256, pmin=4)
+    assert len(runs3) == b3.K and np.all(runs3[:, 1] == 0) and np.all(runs3[:, 2] == 3)
+    # the FV rule links p = 3 patches (one chain per column of 4) and splits finer
+    runs3v = pb.pb_column_runs(d3, "fv", 2, 256)
+    _check_runs(b3, runs3v, 2, 256)
+    assert len(runs3v) > b3.K

@@ -13,9 +13,11 @@ from gpu_helpers import announce, need_gpu, rel_err
 pytestmark = pytest.mark.gpu
 
 
-def run_fd(batch, n_steps=1, cfl=0.5, dt_fixed=0.0, sigma=0.1, rk=4, use_graph=False):
+def run_fd(batch, n_steps=1, cfl=0.5, dt_fixed=0.0, sigma=0.1, rk=4, use_graph=False, tuning=None):
     need_gpu()
     B = pb.PatchBatch(batch)
+    if tuning:
+        B.set_tuning(**tuning)
     dt = B.fd_ko_step(cfl=cfl, dt_fixed=dt_fixed, sigma_ko=sigma, rk_stages=rk, n_steps=n_steps,
                       use_graph=use_graph, want_dt=True)
     g = B.download()
@@ -67,6 +69,26 @@ def test_forward_euler_fixed_dt(sigma):
     g, dt, _ = run_fd(b, n_steps=2, dt_fixed=2e-4, sigma=sigma, rk=1)
     assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
     assert dt == 2e-4
+
+
+@pytest.mark.parametrize("grid", [(16, 16, 3), (16, 16, 2)])
+def test_column_runs_bitwise(grid):
+    """Column runs (fd_column, the default 2) against one work-group per
+    patch (fd_column 0): 8^3 patches in columns of 3 or 2, where one run
+    climbs a whole column (w = 1: two or one patch tops crossed) or two runs
+    split it mid-patch (w = 2 on columns of 3).  Every schedule gives the
+    same bits over three RK4 steps, and one step matches the oracle."""
+    announce(f"fd euler column runs {grid}")
+    b = I.config1(grid=grid, p=8, halo=3, seed=71)
+    ref, dt_ref, _ = run_fd(b, n_steps=3, tuning={"fd_column": 0})
+    for w, remap in ((1, 1), (2, 1), (2, 0), (4, 1)):
+        g, dt, st = run_fd(b, n_steps=3, tuning={"fd_column": w, "fd_xcd_remap": remap})
+        np.testing.assert_array_equal(g, ref)
+        assert dt == dt_ref and st["nonfinite_units"] == 0
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=1)
+    g, dt, _ = run_fd(b, n_steps=1, tuning={"fd_column": 1})
+    assert np.all(rel_err(b, g, o) <= 1e-12), rel_err(b, g, o)
+    assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
 
 
 def test_ragged_components():

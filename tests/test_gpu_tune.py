@@ -82,6 +82,38 @@ def test_fd_autotune_is_bitwise_neutral():
     pb.pb_autotune_cache_clear()
 
 
+def test_euler_fd_autotune():
+    """Euler FD: the column-run candidates (2 and 4 work-groups per CU, and
+    one work-group per patch) x XCD remap; the state and the statistics are
+    untouched, and the steps after tuning equal the default tuning's bits."""
+    announce("autotune fd euler")
+    need_gpu()
+    pb.pb_autotune_cache_clear()
+    b = I.config1(grid=(8, 8, 2), p=8, halo=3, seed=12)
+    B = pb.PatchBatch(b)
+    before, st0 = B.download(), B.stats()
+    r = B.autotune("fd", cfl=0.5, sigma_ko=0.1, trials=2)
+    check_result(r, 6)
+    assert {c["fd_column"] for c, _ in r["candidates"]} == {0, 2, 4}
+    assert B.get_tuning() == r["best"]
+    np.testing.assert_array_equal(B.download(), before)
+    assert B.stats() == st0
+    B.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
+    g = B.download()
+    B.close()
+    B0 = pb.PatchBatch(b)
+    B0.fd_ko_step(cfl=0.5, sigma_ko=0.1, n_steps=2)
+    np.testing.assert_array_equal(g, B0.download())
+    B0.close()
+    # a batch of 4^3 patches runs the small-patch kernel: one candidate
+    bs = I.config1(grid=(2, 2, 2), p=4, halo=3, seed=13)
+    Bs = pb.PatchBatch(bs)
+    rs = Bs.autotune("fd", cfl=0.5, sigma_ko=0.1, trials=2)
+    check_result(rs, 1)
+    Bs.close()
+    pb.pb_autotune_cache_clear()
+
+
 def test_srhd_autotune_then_step():
     announce("autotune fv srhd")
     need_gpu()
@@ -90,7 +122,7 @@ def test_srhd_autotune_then_step():
     B = pb.PatchBatch(b)
     before, st0 = B.download(), B.stats()
     r = B.autotune("fv", cfl=0.4, trials=2)
-    check_result(r, 12)   # SRHD has no DMA-fed kernel: balanced (2, 3 per CU) and slabs, x remap
+    check_result(r, 12)   # SRHD has no DMA-fed kernel: columns (3, 2 per CU), balanced (3) and 3 slabs, x remap
     assert {c["fv_dma"] for c, _ in r["candidates"]} == {0}
     np.testing.assert_array_equal(B.download(), before)
     assert B.stats() == st0
