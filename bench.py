@@ -204,8 +204,9 @@ def attainable_copy(torch, pb):
     """the library's streaming copy, 512 MiB read + 512 MiB written per launch"""
     src = torch.ones(64 << 20, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
-    pb.pb_stream_copy(src, dst)
-    reps = 5
+    for _ in range(5):
+        pb.pb_stream_copy(src, dst)
+    reps = 20
     el = timed(torch, lambda: [pb.pb_stream_copy(src, dst) for _ in range(reps)])
     return 2 * src.numel() * 8 * reps / el / 1e9
 
