@@ -49,7 +49,39 @@ __device__ __forceinline__ C2pIn c2p_setup(double D, double Sx, double Sy, doubl
     return in;
 }
 
-// Newton from p0 (p0 outside (lo, hi] or NaN -> the plain guess hi)
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (within an ulp or two of the correctly rounded quotient; x finite, nonzero)
+__device__ __forceinline__ double c2p_recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// sqrt(a) and 1/sqrt(a) together, for 0 < a <= 1: Goldschmidt's coupled
+// iteration g -> sqrt(a), h -> 1/(2 sqrt(a)) from the hardware reciprocal-
+// square-root estimate, two steps, then one correction of the root
+// (g + (a - g^2) h)
+__device__ __forceinline__ double c2p_sqrt_rsqrt(double a, double &rs)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double g = a * y, h = 0.5 * y;
+    double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    rs = h + h;
+    return fma(fma(-g, g, a), h, g);
+}
+
+// Newton from p0 (p0 outside (lo, hi] or NaN -> the plain guess hi).  Per
+// step one reciprocal of E + p, one coupled root (sqrt(1 - v^2) and the
+// Lorentz factor W = 1/sqrt(1 - v^2)) and one reciprocal of f'; the
+// divisions of the closed forms become products with these.
 __device__ __forceinline__ C2pOut c2p_solve(const C2pIn &in, double gam, double tol, int maxit, double p0)
 {
     C2pOut o;
@@ -64,12 +96,13 @@ __device__ __forceinline__ C2pOut c2p_solve(const C2pIn &in, double gam, double 
     double p = (p0 > lo && p0 <= hi) ? p0 : hi;
     for (int it = 0;; ++it) {
         const double Ep = in.E + p;
-        const double iEp = 1.0 / Ep;
+        const double iEp = c2p_recip(Ep);
         const double v2 = in.s2 * iEp * iEp;
-        const double sq = sqrt(1.0 - v2);
+        double W;
+        const double sq = c2p_sqrt_rsqrt(1.0 - v2, W);
         const double f = g1 * (in.E - in.s2 * iEp - in.D * sq) - p;
-        const double df = g1 * v2 * (1.0 - in.D * iEp / sq) - 1.0;
-        const double step = f / df;
+        const double df = g1 * v2 * (1.0 - in.D * iEp * W) - 1.0;
+        const double step = f * c2p_recip(df);
         if (fabs(f) <= tol * g1 * Ep) {
             const double pp = p - step;
             if (pp > lo && pp <= hi) p = pp;
