@@ -343,7 +343,10 @@ pb_status pb_mlp_train_epoch(pb_mlp *m, const void *x, const void *t, int64_t n,
  * of later eager calls by a HIP event pair that the kernel's own dispatch sets
  * to its start and end (the dt reduction and launch gaps are not included).
  * Step calls with use_graph != 0 fail with PB_EINVAL while it is on; on == 0
- * stops it and drops what was recorded. */
+ * stops it and drops what was recorded.  Turning it on creates the event
+ * pairs of 1,024 launches here (a call with more launches than the pool
+ * holds grows it first), so that recording allocates nothing in the calls
+ * being timed.  PB_EHIP if an event cannot be created. */
 pb_status pb_batch_profile(pb_batch *b, int32_t on);
 /* Sum of the recorded launch durations (ms) and the number of launches since
  * the last read; synchronises the batch stream and clears the record. */

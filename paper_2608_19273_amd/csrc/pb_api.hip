@@ -548,10 +548,22 @@ static pb_status finish_call(pb_batch *b, int n, double dt_fixed, double *dt_las
     return PB_OK;
 }
 
+static constexpr int kProfPool = 1024;   // launches recorded without growing the event pool
+
 pb_status pb_batch_profile(pb_batch *b, int32_t on)
 {
     PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
+    if (on) {
+        // create the event pool now, so that a profiled call spends no time
+        // creating events (the pool still grows for a call of more launches)
+        for (int w = 0; w < 2; ++w)
+            while (b->prof_ev[w].size() < (size_t)kProfPool) {
+                hipEvent_t ev;
+                PB_HIP(hipEventCreate(&ev));
+                b->prof_ev[w].push_back(ev);
+            }
+    }
     b->profiling = on != 0;
     b->prof_n = 0;
     return PB_OK;
