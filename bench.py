@@ -242,7 +242,9 @@ def bench_euler3d(torch, pb, b, storage, steps, warmup):
     B = pb.PatchBatch(b, storage=storage)
     tuned = tune(B, "fv", cfl=0.4)
     extra = warm_up(torch, B, lambda n: B.fv_rusanov_step(cfl=0.4, n_steps=n), warmup, MIN_WARMUP_S)
-    B.profile(True)
+    # one event pair over the call's back-to-back step launches (span mode):
+    # a pair per launch costs the stream a few microseconds per step
+    B.profile(True, span=True)
     el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.4, n_steps=steps))
     kern_ms, launches = B.profile_read()
     B.profile(False)
@@ -452,7 +454,7 @@ def bench_adv_var(torch, pb, I, steps, warmup):
     cells = b.total_cells
     B = pb.PatchBatch(b)
     B.fv_rusanov_step(cfl=0.5, n_steps=warmup)
-    B.profile(True)
+    B.profile(True, span=True)
     el = timed(torch, lambda: B.fv_rusanov_step(cfl=0.5, n_steps=steps))
     kern_ms, launches = B.profile_read()
     B.profile(False)
@@ -665,6 +667,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel, "avg_launch_us": h["kernel_avg_us"],
+                     "avg_launch_timing": "HIP events: the first step launch's start to the last's end, "
+                                          "over the launch count (the launches follow each other directly)",
                      "launches": h["launches"], "algorithmic_bytes_per_launch": cells * h["bytes_per_cell"],
                      "attainable_copy_GBs": copy_gbs, "frac_of_attainable": achieved / copy_gbs,
                      "kernel_source_sha": sha},

@@ -339,17 +339,25 @@ pb_status pb_mlp_train_epoch(pb_mlp *m, const void *x, const void *t, int64_t n,
 
 /* ---------------------------------------------------------- measurement -- */
 
-/* on != 0: time every step kernel launch (FV step kernel; FD stage kernel)
+/* on == 1: time every step kernel launch (FV step kernel; FD stage kernel)
  * of later eager calls by a HIP event pair that the kernel's own dispatch sets
  * to its start and end (the dt reduction and launch gaps are not included).
- * Step calls with use_graph != 0 fail with PB_EINVAL while it is on; on == 0
- * stops it and drops what was recorded.  Turning it on creates the event
- * pairs of 1,024 launches here (a call with more launches than the pool
- * holds grows it first), so that recording allocates nothing in the calls
- * being timed.  PB_EHIP if an event cannot be created. */
+ * on == 2 (span): the same, except that the step launches of one FV call on a
+ * PDE other than SRHD, which follow each other on the stream with nothing in
+ * between, share one pair: the first launch sets its start, the last its end.
+ * The elapsed time over the launch count is then their average period (the
+ * duration plus whatever gap separates them), recorded with two events per
+ * call instead of two per launch, which costs the stream a few microseconds
+ * each.  Step calls with use_graph != 0 fail with PB_EINVAL while it is on;
+ * on == 0 stops it and drops what was recorded; any other value is PB_EINVAL.
+ * Turning it on creates the event pairs of 1,024 launches here (a call with
+ * more launches than the pool holds grows it first), so that recording
+ * allocates nothing in the calls being timed.  PB_EHIP if an event cannot be
+ * created. */
 pb_status pb_batch_profile(pb_batch *b, int32_t on);
-/* Sum of the recorded launch durations (ms) and the number of launches since
- * the last read; synchronises the batch stream and clears the record. */
+/* Sum of the recorded pairs' elapsed times (ms) and the number of launches
+ * they cover, since the last read; synchronises the batch stream and clears
+ * the record. */
 pb_status pb_batch_profile_read(pb_batch *b, double *total_ms, int64_t *launches);
 
 /* Plain streaming copy of `bytes` (multiple of 32, 32-byte aligned device

@@ -456,11 +456,14 @@ class PatchBatch:
         and the measured candidates"""
         return pb_autotune(self.handle, kind, cfl, dt_fixed, sigma_ko, trials, use_cache)
 
-    def profile(self, on=True):
-        _check(lib().pb_batch_profile(self.handle, int(on)), "pb_batch_profile")
+    def profile(self, on=True, span=False):
+        """on: time each step kernel launch with an event pair; span: one pair
+        over the back-to-back step launches of an FV call (not SRHD)"""
+        _check(lib().pb_batch_profile(self.handle, (2 if span else 1) if on else 0), "pb_batch_profile")
 
     def profile_read(self):
-        """(total ms, launches) of the step kernels recorded since the last read"""
+        """(total ms, launches) of the step kernels recorded since the last read
+        (in span mode the ms are the span of the launches they cover)"""
         ms = C.c_double(0.0)
         n = C.c_int64(0)
         _check(lib().pb_batch_profile_read(self.handle, C.byref(ms), C.byref(n)), "pb_batch_profile_read")

@@ -160,18 +160,32 @@ static pb_status validate(const pb_batch_desc *d, bool need_buffers, long long *
     return PB_OK;
 }
 
-// profiling: hand the next pair of events to the next main-kernel launch
-// (launch_main), then count it once the launch has been enqueued
-static void arm_events(pb_batch *b)
+// profiling: hand the next pair's start event (first launch of the pair)
+// and end event (last launch) to the next main-kernel launch (launch_main),
+// then count the launch once it has been enqueued and the pair once its end
+// is on the stream
+static void arm_events(pb_batch *b, bool first = true, bool last = true)
 {
     if (!b->profiling) return;
-    b->kev[0] = b->prof_ev[0][b->prof_n];
-    b->kev[1] = b->prof_ev[1][b->prof_n];
+    b->kev[0] = first ? b->prof_ev[0][b->prof_n] : nullptr;
+    b->kev[1] = last ? b->prof_ev[1][b->prof_n] : nullptr;
 }
 
 static pb_status disarm_events(pb_batch *b, pb_status st)
 {
-    if (b->kev[0] && st == PB_OK) ++b->prof_n;
+    if (b->profiling) {
+        if (st != PB_OK) {
+            b->prof_pending = 0;   // an unfinished pair is dropped
+        } else {
+            if (b->kev[0]) b->prof_pending = 0;
+            ++b->prof_pending;
+            if (b->kev[1]) {
+                ++b->prof_n;
+                b->prof_launches += b->prof_pending;
+                b->prof_pending = 0;
+            }
+        }
+    }
     b->kev[0] = b->kev[1] = nullptr;
     return st;
 }
@@ -184,11 +198,17 @@ static pb_status enqueue_fv(pb_batch *b, double cfl, double dt_fixed, int n, hip
     const bool cfl_mode = !(dt_fixed > 0.0);
     if (cfl_mode && b->pde != PB_PDE_SRHD)
         if ((st = launch_fv_lambda(b, b->state[cur], cfl, s)) != PB_OK) return st;
+    // span mode: without the con2prim pass the n step launches follow each
+    // other with nothing in between, so one pair brackets all of them
+    const bool span = b->prof_span && b->pde != PB_PDE_SRHD;
     for (int i = 0; i < n; ++i) {
         const int slot = i & 1;
         if (b->pde == PB_PDE_SRHD)
             if ((st = launch_srhd_c2p(b, b->state[cur], slot, cfl_mode, cfl, s)) != PB_OK) return st;
-        arm_events(b);
+        if (span)
+            arm_events(b, i == 0, i == n - 1);
+        else
+            arm_events(b);
         st = disarm_events(b, launch_fv_step(b, b->state[cur], b->state[cur ^ 1], slot, i, dt_fixed, cfl, s));
         if (st != PB_OK) return st;
         cur ^= 1;
@@ -554,6 +574,7 @@ pb_status pb_batch_profile(pb_batch *b, int32_t on)
 {
     PB_API_BEGIN
     if (!b) { set_error("batch is NULL"); return PB_EINVAL; }
+    if (on < 0 || on > 2) { set_error("profile mode must be 0, 1 or 2"); return PB_EINVAL; }
     if (on) {
         // create the event pool now, so that a profiled call spends no time
         // creating events (the pool still grows for a call of more launches)
@@ -565,7 +586,9 @@ pb_status pb_batch_profile(pb_batch *b, int32_t on)
             }
     }
     b->profiling = on != 0;
+    b->prof_span = on == 2;
     b->prof_n = 0;
+    b->prof_launches = b->prof_pending = 0;
     return PB_OK;
     PB_API_END
 }
@@ -582,8 +605,9 @@ pb_status pb_batch_profile_read(pb_batch *b, double *total_ms, int64_t *launches
         sum += ms;
     }
     *total_ms = sum;
-    *launches = b->prof_n;
+    *launches = b->prof_launches;
     b->prof_n = 0;
+    b->prof_launches = b->prof_pending = 0;
     return PB_OK;
     PB_API_END
 }

@@ -281,12 +281,16 @@ struct pb_batch {
     std::vector<GraphEntry> graphs;
     hipStream_t capture_stream = nullptr;
     int last_slot = 0;
-    // per-launch event timing of the step kernels (eager mode only)
-    bool profiling = false;
-    int prof_n = 0;
+    // event timing of the step kernels (eager mode only): one event pair per
+    // launch, or in span mode one pair per run of back-to-back launches of
+    // the FV step kernel (the first launch's start, the last launch's end)
+    bool profiling = false, prof_span = false;
+    int prof_n = 0;                 // completed event pairs
+    long long prof_launches = 0;    // launches those pairs cover
+    long long prof_pending = 0;     // launches of the pair still open
     std::vector<hipEvent_t> prof_ev[2];
     // events the next main-kernel launch sets from its own start and end
-    // (null when not profiling)
+    // (null: that end is not recorded)
     hipEvent_t kev[2] = {nullptr, nullptr};
 };
 
@@ -311,9 +315,9 @@ inline long long max_units(int K) { return (long long)K * kFvPmax; }
 
 // launches a step's main kernel (the FV step, an FD stage) with its arguments
 // converted to the kernel's parameter types; when the batch is profiling, the
-// dispatch itself sets the two events to its start and end
-// (hipExtLaunchKernel), so their elapsed time is the kernel alone, without the
-// launch gap or the dt reduction that may follow it on the stream
+// dispatch itself sets the events it is given to its start and end
+// (hipExtLaunchKernel), so a pair on one launch times the kernel alone,
+// without the launch gap or the dt reduction that may follow it on the stream
 template <typename... P, typename... Args>
 inline void launch_main(const pb_batch *b, void (*kern)(P...), dim3 grid, dim3 block, size_t lds, hipStream_t s,
                         Args... args)
@@ -322,7 +326,7 @@ inline void launch_main(const pb_batch *b, void (*kern)(P...), dim3 grid, dim3 b
     std::tuple<P...> a{static_cast<P>(args)...};
     void *ptrs[sizeof...(P)];
     std::apply([&ptrs](auto &...x) { int i = 0; ((ptrs[i++] = static_cast<void *>(&x)), ...); }, a);
-    if (b->kev[0])
+    if (b->kev[0] || b->kev[1])
         (void)hipExtLaunchKernel(reinterpret_cast<const void *>(kern), grid, block, ptrs, lds, s, b->kev[0],
                                  b->kev[1], 0);
     else

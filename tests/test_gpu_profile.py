@@ -2,7 +2,10 @@
 per FV step and per FD stage, each timed by the kernel's own dispatch (so the
 sum stays below the wall-clock time of the steps, which also holds the dt
 reductions and launch gaps), results bitwise equal to an unprofiled run, and
-profiling refused in graph mode."""
+profiling refused in graph mode.  Span mode: one event pair over the
+back-to-back FV step launches of a call (its span covers at least the sum of
+the launches' own durations and stays below the wall-clock time), per-launch
+pairs where the con2prim pass separates the launches (SRHD) and in FD."""
 import time
 
 import numpy as np
@@ -80,4 +83,47 @@ def test_profile_refused_in_graph_mode():
         B.fv_rusanov_step(cfl=0.4, n_steps=2, use_graph=True)
     B.profile(False)
     B.fv_rusanov_step(cfl=0.4, n_steps=2, use_graph=True)
+    B.close()
+
+
+@pytest.mark.parametrize("case", ["fv-euler3d", "fv-euler3d-p4", "fv-srhd", "fd-euler3d"])
+def test_profile_span_mode(case):
+    announce(f"profile span {case}")
+    torch = need_gpu()
+    make, step, per_step = CASES[case]
+    b = make()
+    R = pb.PatchBatch(b)
+    step(R, 11)
+    ref = R.download()
+    R.close()
+    B = pb.PatchBatch(b)
+    step(B, 1)
+    torch.cuda.synchronize()
+    B.profile(True)
+    step(B, 5)
+    each_ms, each_n = B.profile_read()
+    B.profile(True, span=True)
+    t0 = time.perf_counter()
+    step(B, 5)
+    torch.cuda.synchronize()
+    wall_ms = (time.perf_counter() - t0) * 1e3
+    ms, launches = B.profile_read()
+    B.profile(False)
+    g = B.download()
+    B.close()
+    assert each_n == launches == 5 * per_step
+    assert 0.0 < ms < wall_ms, (ms, wall_ms)
+    if case.startswith("fv-euler"):
+        # the span holds the five kernels and the four gaps between them
+        assert ms >= 0.8 * each_ms, (ms, each_ms)
+    np.testing.assert_array_equal(g, ref)
+
+
+def test_profile_mode_out_of_range():
+    announce("profile mode out of range")
+    need_gpu()
+    B = pb.PatchBatch(I.config1(grid=(2, 2, 1)))
+    for bad in (3, -1):
+        with pytest.raises(pb.PbError, match="profile mode"):
+            pb._check(pb.lib().pb_batch_profile(B.handle, bad), "pb_batch_profile")
     B.close()
