@@ -104,6 +104,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     __shared__ double sQ[N][kPlaneQ];
     __shared__ double sFx[N][kPlaneF];
     __shared__ double sFy[N][kPlaneF];
+    __shared__ double sH[3][N][12 * kFvPmax];   // halo ring: the halo cells of run planes i .. i+2
 
     const int t = threadIdx.x;
     const int unit = remap ? xcd_remap(blockIdx.x, n_units) : (int)blockIdx.x;
@@ -184,7 +185,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
 
     double qr[7][N];    // Q of planes z-3 .. z+3
     double ar[5][2];    // 1/rho and p of planes z-2 .. z+2
-    double rl[N], hr[N];   // loads in flight: own plane z+3, halo cell of plane z
+    double rl[N], hr[N];   // loads in flight: own plane z+3, halo cell of plane z+3
     double lm[3] = {0.0, 0.0, 0.0};
     bool bad = false;
 
@@ -194,8 +195,23 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         col(z0 + 3, rl);
 #pragma unroll
         for (int i = 0; i < 4; ++i) euler_ip(qr[1 + i], gm1, ar[i]);
-        load5(hsrc, (unsigned)z0 * pp, C, hr);
+        // the halo cells of run planes 0..2 go to the ring, plane 3 stays in
+        // flight (clamped to the run's last plane, a plane past the patch top
+        // comes from the +z neighbour: p >= 4 keeps it inside that one)
+#pragma unroll 1
+        for (int k = 0; k < 3; ++k) {
+            const int zh = z0 + min(k, n - 1);
+            double hv[N];
+            load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hv);
+            if (halo) {
+#pragma unroll
+                for (int v = 0; v < N; ++v) sH[k][v][t] = hv[v];
+            }
+        }
+        const int zh = z0 + min(3, n - 1);
+        load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hr);
     }
+    int hs = 0;   // ring slot of the current run plane (i % 3)
 
     int z = z0;   // the current plane, inside the current patch
 #pragma unroll 1
@@ -225,11 +241,23 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 sFy[v][fys] = fy[v];
             }
         }
+        // The halo cells of this plane come from the ring; the cells of run
+        // plane i + 3 (loaded one plane ago) take their slot, and the load of
+        // plane i + 4 is issued: halo strips are read four planes ahead, at
+        // the time the neighbour's own work-group loads that plane into its
+        // window, so the strips are still in L2 (read one plane ahead, three
+        // planes after the neighbour, they had mostly left it).  Each thread
+        // reads back only what it wrote: no barrier.
         double hv[N];
+        if (halo) {
 #pragma unroll
-        for (int v = 0; v < N; ++v) hv[v] = hr[v];
+            for (int v = 0; v < N; ++v) hv[v] = sH[hs][v][t];
+#pragma unroll
+            for (int v = 0; v < N; ++v) sH[hs][v][t] = hr[v];
+        }
+        hs = hs == 2 ? 0 : hs + 1;
         {
-            const int zh = z + min(1, n - 1 - i);   // the next plane of the run, or this one at its top
+            const int zh = z + min(4, n - 1 - i);   // run plane i + 4, or the run's last plane near its top
             load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hr);
         }
         if (halo) {
