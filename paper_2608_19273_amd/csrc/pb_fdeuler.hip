@@ -43,6 +43,7 @@ constexpr int kQS = kFvPmax + 6;            // row stride of the Q plane: x in [
 constexpr int kFxS = kFvPmax + 4;           // row stride of F_x: x in [-2, p + 2)
 constexpr int kPlaneQ = kQS * kQS;          // Q plane slots (corners unused)
 constexpr int kPlaneF = kFvPmax * kFxS;     // F_x and F_y plane slots
+constexpr int kHaloRing = 3;                 // halo ring slots: halo loads run kHaloRing + 1 planes ahead
 
 __device__ __forceinline__ int q_slot(int x, int y) { return (y + 3) * kQS + x + 3; }
 __device__ __forceinline__ int fx_slot(int x, int y) { return y * kFxS + x + 2; }
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     __shared__ double sQ[N][kPlaneQ];
     __shared__ double sFx[N][kPlaneF];
     __shared__ double sFy[N][kPlaneF];
-    __shared__ double sH[3][N][12 * kFvPmax];   // halo ring: the halo cells of run planes i .. i+2
+    __shared__ double sH[kHaloRing][N][12 * kFvPmax];   // halo ring: the halo cells of run planes i .. i+kHaloRing-1
 
     const int t = threadIdx.x;
     const int unit = remap ? xcd_remap(blockIdx.x, n_units) : (int)blockIdx.x;
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         // flight (clamped to the run's last plane, a plane past the patch top
         // comes from the +z neighbour: p >= 4 keeps it inside that one)
 #pragma unroll 1
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < kHaloRing; ++k) {
             const int zh = z0 + min(k, n - 1);
             double hv[N];
             load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hv);
@@ -208,10 +209,10 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 for (int v = 0; v < N; ++v) sH[k][v][t] = hv[v];
             }
         }
-        const int zh = z0 + min(3, n - 1);
+        const int zh = z0 + min(kHaloRing, n - 1);
         load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hr);
     }
-    int hs = 0;   // ring slot of the current run plane (i % 3)
+    int hs = 0;   // ring slot of the current run plane (i % kHaloRing)
 
     int z = z0;   // the current plane, inside the current patch
 #pragma unroll 1
@@ -255,9 +256,9 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
 #pragma unroll
             for (int v = 0; v < N; ++v) sH[hs][v][t] = hr[v];
         }
-        hs = hs == 2 ? 0 : hs + 1;
+        hs = hs == kHaloRing - 1 ? 0 : hs + 1;
         {
-            const int zh = z + min(4, n - 1 - i);   // run plane i + 4, or the run's last plane near its top
+            const int zh = z + min(kHaloRing + 1, n - 1 - i);   // run plane i + kHaloRing + 1, or the run's last plane near its top
             load5(zh >= p ? hsrcn : hsrc, (unsigned)(zh >= p ? zh - p : zh) * pp, C, hr);
         }
         if (halo) {
