@@ -116,48 +116,9 @@ __device__ __forceinline__ C2pOut solve_cell_i(const C2pIn &in, double gam, doub
     return o;
 }
 
-// plain (0) or warm (2: pres holds the previous pressure) guess, one cell per lane
-template <int GUESS>
-__global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
-    const double *__restrict__ q, double *__restrict__ pres, const PatchDev *__restrict__ patches,
-    int chunks, int n_units, double *__restrict__ part, double gam, double tol, int maxit)
-{
-    const int unit = blockIdx.x;
-    const int k = unit / chunks, ch = unit - k * chunks;
-    const PatchDev P = patches[k];
-    const long long C = (long long)P.p * P.p * P.p;
-    const long long c = (long long)ch * kC2pThreads + threadIdx.x;
-    const bool active = c < C;
-    C2pStats s = {{0.0, 0.0, 0.0}, 0.0, 0.0, 0.0, 0.0, 0.0};
-    double qv[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
-    if (active) {
-        const double *base = q + P.off * 5 + c;
-#pragma unroll
-        for (int v = 0; v < 5; ++v) qv[v] = base[(long long)v * C];
-    }
-    const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
-    if (active) {
-        const double p0 = GUESS == 2 ? pres[P.off + c] : in.hi;
-        const C2pOut o = solve_cell(in, gam, tol, maxit, p0, GUESS != 0, s.fallbacks);
-        pres[P.off + c] = o.p;
-        const Srhd ph{gam};
-        double a[Srhd::A], e[1] = {o.p};
-        ph.aux(qv, e, a);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) s.lam[d] = a[4 + d];
-        add_cell(s, o);
-    }
-    reduce_stats(s);
-    if (threadIdx.x == 0) {
-        const double v[8] = {s.lam[0], s.lam[1], s.lam[2], s.iters, s.fails, s.maxit, s.fallbacks, s.cells};
-#pragma unroll
-        for (int r = 0; r < 8; ++r) part[(long long)r * n_units + unit] = v[r];
-    }
-}
-
-// The learned pass: each work-group copies the network to LDS once and walks
-// kLearnChunks chunks of 256 cells of its patch (the next chunk's state is
-// loaded while the current one is solved).
+// Chunks of 256 cells a work-group of the con2prim passes walks: the
+// learned pass copies the network to LDS once per work-group, and every
+// pass reduces its statistics once per work-group.
 constexpr int kLearnChunks = 8;
 
 // the same LDS object behind an offset the compiler cannot see through: keeps
@@ -193,23 +154,38 @@ __device__ __forceinline__ const MlpPack &mlp_lane_setup(const MlpPack *__restri
     return sp;
 }
 
-__global__ __launch_bounds__(kC2pThreads, 4) void srhd_c2p_learned_kernel(
-    const double *__restrict__ q, double *__restrict__ pres, const PatchDev *__restrict__ patches, int gchunks,
-    int n_units, double *__restrict__ part, double gam, double tol, int maxit, const MlpPack *__restrict__ pack)
+// The con2prim pass of one work-group: kLearnChunks chunks of 256 cells of
+// its patch, the next chunk's state (and, for the warm start, the previous
+// pressure) loaded while the current one is solved, one statistics
+// reduction for all of them.  GUESS: PB_GUESS_PLAIN (Newton from p_hi),
+// PB_GUESS_WARM (from the previous pressure in pres), PB_GUESS_LEARNED (from
+// the network, evaluated here on the matrix cores; `pack` is the inference
+// blob, copied to LDS once).  A guessed start that does not converge is
+// redone from p_hi.  The speeds of the recovered state feed only the next
+// dt, so they are formed with the refined hardware estimates (aux_fast).
+template <int GUESS>
+__device__ __forceinline__ void c2p_pass(const double *__restrict__ q, double *__restrict__ pres,
+                                         const PatchDev *__restrict__ patches, int gchunks, int n_units,
+                                         double *__restrict__ part, double gam, double tol, int maxit,
+                                         const MlpPack *__restrict__ pack)
 {
+    constexpr bool kLearned = GUESS == PB_GUESS_LEARNED, kWarm = GUESS == PB_GUESS_WARM;
     MlpLane L;
-    const MlpPack &sp = mlp_lane_setup(pack, L);
+    const MlpPack *sp = nullptr;
+    if constexpr (kLearned) sp = &mlp_lane_setup(pack, L);
     const int unit = blockIdx.x;
     const int k = unit / gchunks, gc = unit - k * gchunks;
     const PatchDev P = patches[k];
     const long long C = (long long)P.p * P.p * P.p;
     const double *base = q + P.off * 5;
+    double *pb = pres + P.off;
     CellAcc acc;
     const long long c0 = (long long)gc * kLearnChunks * kC2pThreads + threadIdx.x;
-    double nx[5] = {1.0, 0.0, 0.0, 0.0, 1.0};
+    double nx[5] = {1.0, 0.0, 0.0, 0.0, 1.0}, npv = 0.0;
     if (c0 < C) {
 #pragma unroll
         for (int v = 0; v < 5; ++v) nx[v] = base[(long long)v * C + c0];
+        if (kWarm) npv = pb[c0];
     }
 #pragma unroll 1
     for (int gi = 0; gi < kLearnChunks; ++gi) {
@@ -219,19 +195,25 @@ __global__ __launch_bounds__(kC2pThreads, 4) void srhd_c2p_learned_kernel(
         double qv[5];
 #pragma unroll
         for (int v = 0; v < 5; ++v) qv[v] = nx[v];
+        const double pprev = npv;
         const long long cn = c + kC2pThreads;
         if (gi + 1 < kLearnChunks && cn < C) {
 #pragma unroll
             for (int v = 0; v < 5; ++v) nx[v] = base[(long long)v * C + cn];
+            if (kWarm) npv = pb[cn];
         }
         const C2pIn in = c2p_setup(qv[0], qv[1], qv[2], qv[3], qv[4], gam);
-        const double p0 = mlp_guess(lds_fresh(sp), L.xm, L.xi, L.ym, L.ys, in);   // whole wave
+        double p0 = in.hi;
+        if constexpr (kLearned) p0 = mlp_guess(lds_fresh(*sp), L.xm, L.xi, L.ym, L.ys, in);   // whole wave
+        if constexpr (kWarm) p0 = pprev;
         if (active) {
-            const C2pOut o = solve_cell_i(in, gam, tol, maxit, p0, acc.fallbacks);
-            pres[P.off + c] = o.p;
+            C2pOut o;
+            if constexpr (GUESS == PB_GUESS_PLAIN) o = c2p_solve(in, gam, tol, maxit, p0);
+            else o = solve_cell_i(in, gam, tol, maxit, p0, acc.fallbacks);
+            pb[c] = o.p;
             const Srhd ph{gam};
             double a[Srhd::A], e[1] = {o.p};
-            ph.aux(qv, e, a);
+            ph.aux_fast(qv, e, a);
 #pragma unroll
             for (int d = 0; d < 3; ++d) acc.lam[d] = fmax(acc.lam[d], a[4 + d]);
             acc.add(o);
@@ -244,6 +226,22 @@ __global__ __launch_bounds__(kC2pThreads, 4) void srhd_c2p_learned_kernel(
 #pragma unroll
         for (int r = 0; r < 8; ++r) part[(long long)r * n_units + unit] = v[r];
     }
+}
+
+// plain (GUESS 0) or warm (GUESS 2) start
+template <int GUESS>
+__global__ __launch_bounds__(kC2pThreads) void srhd_c2p_kernel(
+    const double *__restrict__ q, double *__restrict__ pres, const PatchDev *__restrict__ patches, int gchunks,
+    int n_units, double *__restrict__ part, double gam, double tol, int maxit)
+{
+    c2p_pass<GUESS>(q, pres, patches, gchunks, n_units, part, gam, tol, maxit, nullptr);
+}
+
+__global__ __launch_bounds__(kC2pThreads, 4) void srhd_c2p_learned_kernel(
+    const double *__restrict__ q, double *__restrict__ pres, const PatchDev *__restrict__ patches, int gchunks,
+    int n_units, double *__restrict__ part, double gam, double tol, int maxit, const MlpPack *__restrict__ pack)
+{
+    c2p_pass<PB_GUESS_LEARNED>(q, pres, patches, gchunks, n_units, part, gam, tol, maxit, pack);
 }
 
 // standalone con2prim, one cell of SoA arrays: primitives out
@@ -347,25 +345,24 @@ pb_status launch_srhd_c2p(pb_batch *b, const void *q, int slot_out, bool want_dt
     int guess = b->guess;
     if (guess == PB_GUESS_WARM && !b->pres_valid) guess = PB_GUESS_PLAIN;
     const double *qd = static_cast<const double *>(q);
-    int n_units = b->K * chunks;
+    const int gchunks = (chunks + kLearnChunks - 1) / kLearnChunks;
+    const int n_units = b->K * gchunks;
     switch (guess) {
     case PB_GUESS_PLAIN:
-        hipLaunchKernelGGL(srhd_c2p_kernel<0>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, chunks,
-                           n_units, part, gam, tol, maxit);
+        hipLaunchKernelGGL(srhd_c2p_kernel<PB_GUESS_PLAIN>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres,
+                           b->d_patches, gchunks, n_units, part, gam, tol, maxit);
         break;
     case PB_GUESS_LEARNED: {
         MlpDev md{};
         pb_status st = mlp_device_view(b->mlp, &md);
         if (st != PB_OK) return st;
-        const int gchunks = (chunks + kLearnChunks - 1) / kLearnChunks;
-        n_units = b->K * gchunks;
         hipLaunchKernelGGL(srhd_c2p_learned_kernel, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches,
                            gchunks, n_units, part, gam, tol, maxit, md.pack);
         break;
     }
     default:
-        hipLaunchKernelGGL(srhd_c2p_kernel<2>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres, b->d_patches, chunks,
-                           n_units, part, gam, tol, maxit);
+        hipLaunchKernelGGL(srhd_c2p_kernel<PB_GUESS_WARM>, dim3(n_units), dim3(kC2pThreads), 0, s, qd, pres,
+                           b->d_patches, gchunks, n_units, part, gam, tol, maxit);
     }
     PB_HIP(hipGetLastError());
     b->pres_valid = true;
