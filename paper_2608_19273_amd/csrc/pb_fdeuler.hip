@@ -22,7 +22,10 @@
 //      the 12p face-halo cells of the plane (three layers per side, read
 //      straight from the face neighbours' interiors: the halo gather of
 //      Sec. II, Eq. (2), fused into the stage) and, for the two inner
-//      layers, their F_x or F_y, so every x and y flux is evaluated once;
+//      layers, their F_x or F_y, so every x and y flux is evaluated once.
+//      The halo cells are loaded four planes ahead, when the neighbour's
+//      own work-group loads that plane (so they are still in L2), and wait
+//      in a small LDS ring until their plane comes;
 //   3. after a barrier each thread forms R of its cell, meets the others at
 //      a second barrier (the LDS is single-buffered: 45 KB, two work-groups
 //      per CU), applies the RK stage update and stores.
