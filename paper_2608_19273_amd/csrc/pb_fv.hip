@@ -1081,10 +1081,15 @@ pb_status dispatch(pb_batch *b, F &&f)
 // cycles; each gets a number of runs proportional to its planes (at least
 // one; at most one per plane for FV, per patch for FD), about w work-groups
 // per CU in total, and runs of one chain split its planes as evenly as
-// integers allow.  Units are ordered chain after chain, chains by their
-// smallest patch index, so that with the XCD remap the runs of neighbouring
-// chains of a grid in patch order share an XCD (and its L2) and reach equal
-// heights at about the same time.
+// integers allow.  Units are ordered layer-major: the lowest run of every
+// chain (chains by their smallest patch index), then every chain's second
+// run, and so on.  With the XCD remap an XCD then holds the runs of one
+// height layer over a block of neighbouring chains of a grid in patch order
+// (several whole rows of them), which start at equal heights, march in step
+// and find their x and y neighbours' planes in the same L2.  (Chain after
+// chain gave each XCD every layer of fewer chains, two rows on the headline
+// grid, so half the y-halo strips came from other XCDs: HBM reads 1.48x
+// the algorithmic reads instead of 1.16x.)
 std::vector<int4> column_runs(int kind, int K, const int *p, const int *nbr, int w, int cus)
 {
     const int pmin = kind == 0 ? 2 : 4;
@@ -1123,18 +1128,26 @@ std::vector<int4> column_runs(int kind, int K, const int *p, const int *nbr, int
     long long total = 0;
     for (const auto &c : chains) total += (long long)c.size() * p[c[0]];
     const double slots = (double)w * cus;
-    std::vector<int4> runs;
+    std::vector<std::vector<int4>> per;   // the runs of each chain, bottom to top
+    size_t rm = 0;
     for (const auto &o : order) {
         const std::vector<int> &c = chains[o.second];
         const int pc = p[c[0]];
         const long long planes = (long long)c.size() * pc;
         const long long rmax = kind == 0 ? planes : (long long)c.size();
         const long long r = std::max(1LL, std::min(rmax, std::llround(slots * (double)planes / (double)total)));
+        per.emplace_back();
         for (long long j = 0; j < r; ++j) {
             const long long s0 = j * planes / r, s1 = (j + 1) * planes / r;
-            runs.push_back(make_int4(c[s0 / pc], (int)(s0 % pc), (int)(s1 - s0), 0));
+            per.back().push_back(make_int4(c[s0 / pc], (int)(s0 % pc), (int)(s1 - s0), 0));
         }
+        rm = std::max(rm, per.back().size());
     }
+    // layer-major: the first run of every chain, then every second run, ...
+    std::vector<int4> runs;
+    for (size_t j = 0; j < rm; ++j)
+        for (const auto &v : per)
+            if (j < v.size()) runs.push_back(v[j]);
     return runs;
 }
 

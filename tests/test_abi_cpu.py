@@ -249,7 +249,8 @@ def test_column_runs_cover_every_plane(grid, w):
     """The column-run schedule (pb_column_runs, the table fv_column = w
     uploads): z-periodic grids give one cycle per column; the runs of a
     column split its planes evenly and, with enough planes, number about
-    w * 256 in total; chains come in order of their smallest patch."""
+    w * 256 in total; the table is layer-major: the lowest run of every
+    chain (chains in order of their smallest patch), then the second, ..."""
     b = I.make_uniform_batch(grid, 16, 1, "euler", [1.4], 5, 1.0 / 16)
     d, keep = desc_for(b)
     runs = pb.pb_column_runs(d, "fv", w, 256)
@@ -259,9 +260,9 @@ def test_column_runs_cover_every_plane(grid, w):
     planes_per_col = nz * 16
     per_col = max(1, min(planes_per_col, round(w * 256 * planes_per_col / (columns * planes_per_col))))
     assert len(runs) == columns * per_col
-    # column c (patches c, c + nx ny, ...) owns units [c per_col, (c + 1) per_col), split evenly
+    # run j of column c (patches c, c + nx ny, ...) is unit j columns + c; a column's runs split it evenly
     for c in range(columns):
-        rc = runs[c * per_col:(c + 1) * per_col]
+        rc = runs[c::columns]
         starts = [(k // columns) * 16 + z0 for k, z0, n, _ in rc]
         assert all(k % columns == c for k, _, _, _ in rc)
         assert starts == [j * planes_per_col // per_col for j in range(per_col)]
