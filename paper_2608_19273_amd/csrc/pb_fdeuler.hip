@@ -81,6 +81,14 @@ __device__ __forceinline__ void load5(const double *__restrict__ base, unsigned 
     for (int v = 0; v < kEN; ++v) out[v] = base[o + v * C];
 }
 
+// the same, as streaming loads (read once, no halo reuse: they should not
+// displace the stage input's lines from L2)
+__device__ __forceinline__ void load5_nt(const double *__restrict__ base, unsigned o, unsigned C, double *out)
+{
+#pragma unroll
+    for (int v = 0; v < kEN; ++v) out[v] = __builtin_nontemporal_load(base + o + v * C);
+}
+
 }  // namespace
 
 // S: RK4 stage 0..3, or 4 for the single forward-Euler stage.
@@ -230,8 +238,8 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
 #pragma unroll
             for (int v = 0; v < N; ++v) qr[6][v] = rl[v];
             col(z + min(4, n + 2 - i), rl);
-            if (kReadQ0) load5(q0o, own, C, q0v);
-            if (kReadAcc) load5(acco, own, C, accv);
+            if (kReadQ0) load5_nt(q0o, own, C, q0v);
+            if (kReadAcc) load5_nt(acco, own, C, accv);
             euler_ip(qr[5], gm1, ar[4]);
         }
         if (active) {
@@ -325,20 +333,20 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             for (int v = 0; v < N; ++v) {
                 const unsigned g = own + v * C;
                 if (S == 0) {
-                    yno[g] = qr[3][v] + (0.5 * dt) * R[v];
+                    __builtin_nontemporal_store(qr[3][v] + (0.5 * dt) * R[v], &yno[g]);
                     nv[v] = qr[3][v] + (dt / 6.0) * R[v];
                 } else if (S == 1) {
-                    yno[g] = q0v[v] + (0.5 * dt) * R[v];
+                    __builtin_nontemporal_store(q0v[v] + (0.5 * dt) * R[v], &yno[g]);
                     nv[v] = accv[v] + (dt / 3.0) * R[v];
                 } else if (S == 2) {
-                    yno[g] = q0v[v] + dt * R[v];
+                    __builtin_nontemporal_store(q0v[v] + dt * R[v], &yno[g]);
                     nv[v] = accv[v] + (dt / 3.0) * R[v];
                 } else if (S == 3) {
                     nv[v] = accv[v] + (dt / 6.0) * R[v];
                 } else {
                     nv[v] = qr[3][v] + dt * R[v];
                 }
-                accw[g] = nv[v];
+                __builtin_nontemporal_store(nv[v], &accw[g]);
             }
             if (kFinal) {
 #pragma unroll
