@@ -190,31 +190,10 @@ struct Srhd {
     static constexpr int N = 5, A = 7, E = 1, M = 0, DIMS = 3;
     static constexpr bool kFlux = true, kNcp = false, kSrc = false;
     double gam;
+    // The reciprocals and roots come from the refined hardware estimates
+    // (recip, root: within an ulp or two of the correctly rounded values);
+    // the primitives feed the fluxes of the step and the speeds its dt.
     __device__ __forceinline__ void aux(const double *q, const double *e, double *a) const
-    {
-        const double p = e[0];
-        const double iEp = 1.0 / (q[4] + q[0] + p);
-        const double v[3] = {q[1] * iEp, q[2] * iEp, q[3] * iEp};
-        const double v2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-        const double rho = q[0] * sqrt(1.0 - v2);
-        const double rhoh = rho + gam / (gam - 1.0) * p;
-        const double cs2 = gam * p / rhoh;
-        const double cs = sqrt(cs2);
-        const double iden = 1.0 / (1.0 - v2 * cs2);
-        a[0] = p;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            a[1 + d] = v[d];
-            const double root = sqrt((1.0 - v2) * (1.0 - v2 * cs2 - v[d] * v[d] * (1.0 - cs2)));
-            const double lp = (v[d] * (1.0 - cs2) + cs * root) * iden;
-            const double lm = (v[d] * (1.0 - cs2) - cs * root) * iden;
-            a[4 + d] = fmax(fabs(lp), fabs(lm));
-        }
-    }
-    // the same values from the refined hardware estimates of the reciprocals
-    // and roots (within an ulp or two: only the largest speeds, for dt, are
-    // taken from here)
-    __device__ __forceinline__ void aux_fast(const double *q, const double *e, double *a) const
     {
         const double p = e[0];
         const double iEp = recip(q[4] + q[0] + p);
@@ -235,6 +214,7 @@ struct Srhd {
             a[4 + d] = fmax(fabs(lp), fabs(lm));
         }
     }
+    __device__ __forceinline__ void aux_fast(const double *q, const double *e, double *a) const { aux(q, e, a); }
     template <int D> __device__ __forceinline__ double eig(const double *, const double *a) const
     {
         return a[4 + D];
