@@ -552,7 +552,9 @@ def bench_srhd(torch, pb, I, steps, mlp_epochs, mlp_pairs, rounds=12, min_warmup
     for g in guesses:
         s1, sn = st1[g], stn[g]
         res[g] = {"step1_ms": float(np.mean(t1[g])), "step1_ms_min": float(np.min(t1[g])),
-                  "run_ms_per_step": float(np.mean(tn[g])) / steps, "run_steps": steps,
+                  "step1_ms_median": float(np.median(t1[g])),
+                  "run_ms_per_step": float(np.mean(tn[g])) / steps,
+                  "run_ms_per_step_median": float(np.median(tn[g])) / steps, "run_steps": steps,
                   "cell_updates_per_s_step1": cells / (float(np.mean(t1[g])) * 1e-3),
                   "cell_updates_per_s_run": cells * steps / (float(np.mean(tn[g])) * 1e-3),
                   "newton_mean_step1": s1["c2p_iterations"] / max(s1["c2p_cells"], 1),
