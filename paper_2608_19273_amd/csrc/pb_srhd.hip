@@ -161,8 +161,7 @@ __device__ __forceinline__ const MlpPack &mlp_lane_setup(const MlpPack *__restri
 // PB_GUESS_WARM (from the previous pressure in pres), PB_GUESS_LEARNED (from
 // the network, evaluated here on the matrix cores; `pack` is the inference
 // blob, copied to LDS once).  A guessed start that does not converge is
-// redone from p_hi.  The speeds of the recovered state feed only the next
-// dt, so they are formed with the refined hardware estimates (aux_fast).
+// redone from p_hi.  The speeds of the recovered state feed the next dt.
 template <int GUESS>
 __device__ __forceinline__ void c2p_pass(const double *__restrict__ q, double *__restrict__ pres,
                                          const PatchDev *__restrict__ patches, int gchunks, int n_units,
