@@ -195,8 +195,14 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         load5(b, (unsigned)zl * pp + cxy, C, out);
     };
 
-    double qr[7][N];    // Q of planes z-3 .. z+3
-    double ar[5][2];    // 1/rho and p of planes z-2 .. z+2
+    // The window of planes z-3 .. z+3 (slots w = 0..6) lives in seven
+    // register sets that rotate instead of sliding: the plane loop is
+    // unrolled over the seven phases, and at phase PH slot w is set
+    // (w + PH) % 7, so the plane entering at slot 6 takes the set of the
+    // plane leaving slot 0 and no value is copied (a slide moved 38 doubles
+    // per plane).  ar holds 1/rho and p of the same sets (slots 1..5 live).
+    double qr[7][N];
+    double ar[7][2];
     double rl[N], hr[N];   // loads in flight: own plane z+3, halo cell of plane z+3
     double lm[3] = {0.0, 0.0, 0.0};
     bool bad = false;
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         for (int i = 0; i < 6; ++i) col(z0 - 3 + i, qr[i]);
         col(z0 + 3, rl);
 #pragma unroll
-        for (int i = 0; i < 4; ++i) euler_ip(qr[1 + i], gm1, ar[i]);
+        for (int i = 0; i < 4; ++i) euler_ip(qr[1 + i], gm1, ar[1 + i]);
         // the halo cells of run planes 0..2 go to the ring, plane 3 stays in
         // flight (clamped to the run's last plane, a plane past the patch top
         // comes from the +z neighbour: p >= 4 keeps it inside that one)
@@ -226,8 +232,11 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     int hs = 0;   // ring slot of the current run plane (i % kHaloRing)
 
     int z = z0;   // the current plane, inside the current patch
-#pragma unroll 1
-    for (int i = 0; i < n; ++i) {
+    int i = 0;    // the current run plane
+    auto plane = [&](auto phase) __attribute__((always_inline)) {
+        constexpr int PH = decltype(phase)::value;
+        auto Q = [&](int w) -> double * { return qr[(w + PH) % 7]; };
+        auto A = [&](int w) -> double * { return ar[(w + PH) % 7]; };
         const unsigned own = (unsigned)z * pp + cxy;
         double q0v[N], accv[N];
         {
@@ -236,19 +245,19 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             // loaded again instead, unused; p >= 4 keeps every plane read
             // inside the current patch or the next)
 #pragma unroll
-            for (int v = 0; v < N; ++v) qr[6][v] = rl[v];
+            for (int v = 0; v < N; ++v) Q(6)[v] = rl[v];
             col(z + min(4, n + 2 - i), rl);
             if (kReadQ0) load5_nt(q0o, own, C, q0v);
             if (kReadAcc) load5_nt(acco, own, C, accv);
-            euler_ip(qr[5], gm1, ar[4]);
+            euler_ip(Q(5), gm1, A(5));
         }
         if (active) {
             double fx[N], fy[N];
-            ph.flux<0>(qr[3], ar[2], fx);
-            ph.flux<1>(qr[3], ar[2], fy);
+            ph.flux<0>(Q(3), A(3), fx);
+            ph.flux<1>(Q(3), A(3), fy);
 #pragma unroll
             for (int v = 0; v < N; ++v) {
-                sQ[v][qs] = qr[3][v];
+                sQ[v][qs] = Q(3)[v];
                 sFx[v][fxs] = fx[v];
                 sFy[v][fys] = fy[v];
             }
@@ -296,17 +305,17 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             // components of F_z are formed per unknown below
             double uz[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int w = i < 2 ? i + 1 : i + 2;
-                uz[i] = qr[w][3] * ar[w - 1][0];
+            for (int k = 0; k < 4; ++k) {
+                const int w = k < 2 ? k + 1 : k + 2;
+                uz[k] = Q(w)[3] * A(w)[0];
             }
-            auto fzv = [&](int i, int v) -> double {
-                const int w = i < 2 ? i + 1 : i + 2;
-                const double pr = ar[w - 1][1];
-                if (v == 0) return qr[w][3];
-                if (v == 3) return qr[w][3] * uz[i] + pr;
-                if (v == 4) return (qr[w][4] + pr) * uz[i];
-                return qr[w][v] * uz[i];
+            auto fzv = [&](int k, int v) -> double {
+                const int w = k < 2 ? k + 1 : k + 2;
+                const double pr = A(w)[1];
+                if (v == 0) return Q(w)[3];
+                if (v == 3) return Q(w)[3] * uz[k] + pr;
+                if (v == 4) return (Q(w)[4] + pr) * uz[k];
+                return Q(w)[v] * uz[k];
             };
 #pragma unroll
             for (int v = 0; v < N; ++v) {
@@ -315,11 +324,11 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 const double dfy = d4(fyv[fys - 2 * kFvPmax], fyv[fys - kFvPmax], fyv[fys + kFvPmax],
                                       fyv[fys + 2 * kFvPmax]);
                 const double dfz = d4(fzv(0, v), fzv(1, v), fzv(2, v), fzv(3, v));
-                const double c = qr[3][v];
+                const double c = Q(3)[v];
                 const double kx = ko6(u[qs - 3], u[qs - 2], u[qs - 1], c, u[qs + 1], u[qs + 2], u[qs + 3]);
                 const double ky = ko6(u[qs - 3 * kQS], u[qs - 2 * kQS], u[qs - kQS], c, u[qs + kQS],
                                       u[qs + 2 * kQS], u[qs + 3 * kQS]);
-                const double kz = ko6(qr[0][v], qr[1][v], qr[2][v], c, qr[4][v], qr[5][v], qr[6][v]);
+                const double kz = ko6(Q(0)[v], Q(1)[v], Q(2)[v], c, Q(4)[v], Q(5)[v], Q(6)[v]);
                 R[v] = cko * ((kx + ky) + kz) - c4 * ((dfx + dfy) + dfz);
                 // one unknown's 20 LDS reads at a time: hoisting all of them
                 // would not fit the register budget
@@ -333,8 +342,8 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             for (int v = 0; v < N; ++v) {
                 const unsigned g = own + v * C;
                 if (S == 0) {
-                    __builtin_nontemporal_store(qr[3][v] + (0.5 * dt) * R[v], &yno[g]);
-                    nv[v] = qr[3][v] + (dt / 6.0) * R[v];
+                    __builtin_nontemporal_store(Q(3)[v] + (0.5 * dt) * R[v], &yno[g]);
+                    nv[v] = Q(3)[v] + (dt / 6.0) * R[v];
                 } else if (S == 1) {
                     __builtin_nontemporal_store(q0v[v] + (0.5 * dt) * R[v], &yno[g]);
                     nv[v] = accv[v] + (dt / 3.0) * R[v];
@@ -344,7 +353,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                 } else if (S == 3) {
                     nv[v] = accv[v] + (dt / 6.0) * R[v];
                 } else {
-                    nv[v] = qr[3][v] + dt * R[v];
+                    nv[v] = Q(3)[v] + dt * R[v];
                 }
                 __builtin_nontemporal_store(nv[v], &accw[g]);
             }
@@ -359,13 +368,6 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
                     lm[2] = fmax(lm[2], ph.eig<2>(nv, a));
                 }
             }
-            // slide the windows up one plane
-#pragma unroll
-            for (int w = 0; w < 6; ++w)
-#pragma unroll
-                for (int v = 0; v < N; ++v) qr[w][v] = qr[w + 1][v];
-#pragma unroll
-            for (int w = 0; w < 4; ++w) { ar[w][0] = ar[w + 1][0]; ar[w][1] = ar[w + 1][1]; }
         }
         if (++z == p && i + 1 < n) {
             // the run continues in the +z neighbour: every buffer's patch
@@ -387,6 +389,23 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             yhi = y + patches[kn].off * N;
             hsrcn = halo_src(kn);
         }
+    };
+    // the plane of phase PH is run plane i with i % 7 == PH
+    while (i < n) {
+        plane(std::integral_constant<int, 0>());
+        if (++i == n) break;
+        plane(std::integral_constant<int, 1>());
+        if (++i == n) break;
+        plane(std::integral_constant<int, 2>());
+        if (++i == n) break;
+        plane(std::integral_constant<int, 3>());
+        if (++i == n) break;
+        plane(std::integral_constant<int, 4>());
+        if (++i == n) break;
+        plane(std::integral_constant<int, 5>());
+        if (++i == n) break;
+        plane(std::integral_constant<int, 6>());
+        ++i;
     }
     if (kFinal) {
         if (__syncthreads_or(bad) && t == 0) atomicAdd(&ctrl->nonfinite, 1ull);
