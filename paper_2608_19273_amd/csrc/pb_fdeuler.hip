@@ -81,12 +81,37 @@ __device__ __forceinline__ void load5(const double *__restrict__ base, unsigned 
     for (int v = 0; v < kEN; ++v) out[v] = base[o + v * C];
 }
 
-// the same, as streaming loads (read once, no halo reuse: they should not
-// displace the stage input's lines from L2)
-__device__ __forceinline__ void load5_nt(const double *__restrict__ base, unsigned o, unsigned C, double *out)
+// The plane kernel's own-column accesses: base is the same for the whole
+// wave (unknown 0 of a plane of a patch block) and ob the lane's byte offset
+// in the plane, below 2 KB.  The per-unknown base then stays in scalar
+// registers and every access takes the scalar-base + 32-bit vector-offset
+// form, with no per-lane 64-bit address arithmetic.
+// The empty asm hands the offset over as a fresh 32-bit value at each access
+// (one 32-bit register copy): otherwise the compiler hoists its widening to
+// 64 bits out of the plane loop and forms 64-bit vector addresses again.
+__device__ __forceinline__ const double *at(const double *base, unsigned ob)
+{
+    __asm__ volatile("" : "+v"(ob));
+    return reinterpret_cast<const double *>(reinterpret_cast<const char *>(base) + ob);
+}
+__device__ __forceinline__ double *at(double *base, unsigned ob)
+{
+    __asm__ volatile("" : "+v"(ob));
+    return reinterpret_cast<double *>(reinterpret_cast<char *>(base) + ob);
+}
+
+__device__ __forceinline__ void load5u(const double *__restrict__ base, unsigned ob, unsigned C, double *out)
 {
 #pragma unroll
-    for (int v = 0; v < kEN; ++v) out[v] = __builtin_nontemporal_load(base + o + v * C);
+    for (int v = 0; v < kEN; ++v) out[v] = *at(base + (size_t)v * C, ob);
+}
+
+// the same, as streaming loads (read once, no halo reuse: they should not
+// displace the stage input's lines from L2)
+__device__ __forceinline__ void load5u_nt(const double *__restrict__ base, unsigned ob, unsigned C, double *out)
+{
+#pragma unroll
+    for (int v = 0; v < kEN; ++v) out[v] = __builtin_nontemporal_load(at(base + (size_t)v * C, ob));
 }
 
 }  // namespace
@@ -147,7 +172,7 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     const bool work = n > 0;
     const bool active = work && t < p * p;
     const int x = active ? t % p : 0, yy = active ? t / p : 0;
-    const unsigned cxy = (unsigned)(yy * p + x);
+    const unsigned cxy = (unsigned)(yy * p + x), cxy8 = 8u * cxy;
     const double dt = dt_fixed > 0.0 ? dt_fixed : ctrl->dt[slot];
     const double gm1 = gamma - 1.0;
     double c4 = inv_dx / 12.0, cko = sigma * inv_dx / 64.0;
@@ -189,10 +214,10 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
     const double *hsrcn = halo_src(kn);  // its +z neighbour (the run's next patch)
     // this thread's column on plane zz (zz in [-3, p + 3): the planes outside
     // the patch come from the z neighbours; the choice is uniform)
-    auto col = [&](int zz, double *out) {
+    auto col = [&](int zz, unsigned o8, double *out) {
         const double *b = zz < 0 ? ylo : (zz >= p ? yhi : yo);
         const int zl = zz < 0 ? zz + p : (zz >= p ? zz - p : zz);
-        load5(b, (unsigned)zl * pp + cxy, C, out);
+        load5u(b + (size_t)zl * pp, o8, C, out);
     };
 
     // The window of planes z-3 .. z+3 (slots w = 0..6) lives in seven
@@ -209,8 +234,8 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
 
     if (work) {
 #pragma unroll
-        for (int i = 0; i < 6; ++i) col(z0 - 3 + i, qr[i]);
-        col(z0 + 3, rl);
+        for (int i = 0; i < 6; ++i) col(z0 - 3 + i, cxy8, qr[i]);
+        col(z0 + 3, cxy8, rl);
 #pragma unroll
         for (int i = 0; i < 4; ++i) euler_ip(qr[1 + i], gm1, ar[1 + i]);
         // the halo cells of run planes 0..2 go to the ring, plane 3 stays in
@@ -237,7 +262,8 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
         constexpr int PH = decltype(phase)::value;
         auto Q = [&](int w) -> double * { return qr[(w + PH) % 7]; };
         auto A = [&](int w) -> double * { return ar[(w + PH) % 7]; };
-        const unsigned own = (unsigned)z * pp + cxy;
+        const size_t zo = (size_t)z * pp;   // the plane's first cell in the patch block
+        const unsigned ob = cxy8;
         double q0v[N], accv[N];
         {
             // plane z+3 enters the window; the load of plane z+4 replaces it
@@ -246,9 +272,9 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             // inside the current patch or the next)
 #pragma unroll
             for (int v = 0; v < N; ++v) Q(6)[v] = rl[v];
-            col(z + min(4, n + 2 - i), rl);
-            if (kReadQ0) load5_nt(q0o, own, C, q0v);
-            if (kReadAcc) load5_nt(acco, own, C, accv);
+            col(z + min(4, n + 2 - i), ob, rl);
+            if (kReadQ0) load5u_nt(q0o + zo, ob, C, q0v);
+            if (kReadAcc) load5u_nt(acco + zo, ob, C, accv);
             euler_ip(Q(5), gm1, A(5));
         }
         if (active) {
@@ -340,22 +366,22 @@ __global__ __launch_bounds__(kFvThreads, 2) void fd_euler_stage_kernel(
             double nv[N];
 #pragma unroll
             for (int v = 0; v < N; ++v) {
-                const unsigned g = own + v * C;
+                double *const yg = at(yno + zo + (size_t)v * C, ob), *const ag = at(accw + zo + (size_t)v * C, ob);
                 if (S == 0) {
-                    __builtin_nontemporal_store(Q(3)[v] + (0.5 * dt) * R[v], &yno[g]);
+                    __builtin_nontemporal_store(Q(3)[v] + (0.5 * dt) * R[v], yg);
                     nv[v] = Q(3)[v] + (dt / 6.0) * R[v];
                 } else if (S == 1) {
-                    __builtin_nontemporal_store(q0v[v] + (0.5 * dt) * R[v], &yno[g]);
+                    __builtin_nontemporal_store(q0v[v] + (0.5 * dt) * R[v], yg);
                     nv[v] = accv[v] + (dt / 3.0) * R[v];
                 } else if (S == 2) {
-                    __builtin_nontemporal_store(q0v[v] + dt * R[v], &yno[g]);
+                    __builtin_nontemporal_store(q0v[v] + dt * R[v], yg);
                     nv[v] = accv[v] + (dt / 3.0) * R[v];
                 } else if (S == 3) {
                     nv[v] = accv[v] + (dt / 6.0) * R[v];
                 } else {
                     nv[v] = Q(3)[v] + dt * R[v];
                 }
-                __builtin_nontemporal_store(nv[v], &accw[g]);
+                __builtin_nontemporal_store(nv[v], ag);
             }
             if (kFinal) {
 #pragma unroll
