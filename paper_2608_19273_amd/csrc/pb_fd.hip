@@ -461,7 +461,10 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
                                             double sigma)
 {
     constexpr int R = WsLds<NCH>::R;
-    const int t = threadIdx.x - 256, pw = t >> 6, l = t & 63;
+    // pw (the producer wave) is the same in every lane: as a scalar, the
+    // chunk's unknown and every offset derived from it stay on the scalar
+    // unit instead of costing 64-bit vector multiplies per step
+    const int t = threadIdx.x - 256, pw = __builtin_amdgcn_readfirstlane(t >> 6), l = t & 63;
     const int cx = l % kT, cy = (l / kT) % kT, cz = l / (kT * kT);
     const int sc = foot_slot(cx, cy, cz);
     int sy[6], sz[6];
@@ -510,7 +513,8 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
             ubase = T.off * N + ((long long)(T.tz + uz) * p + (T.ty + uy)) * p + (T.tx + ux);
         }
         const int v0 = ch * kCh + uv, v = v0 < N ? v0 : N - 1;
-        return *reinterpret_cast<const f64x2_t *>(usrc + ubase + (long long)v * uC);
+        // v < 64 and uC = p^3 <= 4096: a 24-bit product
+        return *reinterpret_cast<const f64x2_t *>(usrc + ubase + __umul24((unsigned)v, (unsigned)uC));
     };
     auto stage_upd = [&](int c, const f64x2_t &U) {
         if (c < S) *reinterpret_cast<f64x2_t *>(&L.u[c % R][us][uv][uc]) = U;
@@ -532,7 +536,7 @@ __device__ __forceinline__ void ws_producer(WsLds<NCH> &L, const double *__restr
         if (v < N && (us == 0 || write_y)) {
             const f64x2_t r = *reinterpret_cast<const f64x2_t *>(&L.u[c % R][us][uv][uc]);
             double *dst = us ? ynext : acc;
-            *reinterpret_cast<f64x2_t *>(dst + obase + (long long)v * oC) = r;
+            *reinterpret_cast<f64x2_t *>(dst + obase + __umul24((unsigned)v, (unsigned)oC)) = r;
         }
     };
     auto grad = [&](int c) {
