@@ -17,7 +17,9 @@
 //      plane earlier; its division happens once, as it enters the flux
 //      window), so the z derivatives need no LDS; F_z is re-formed from the
 //      window per unknown (a multiplication or two each, cheaper in
-//      registers than a window of fluxes);
+//      registers than a window of fluxes).  The window's seven register sets
+//      rotate with the plane (the loop body is instantiated for the seven
+//      phases), so no value moves from set to set;
 //   2. the work-group writes Q, F_x and F_y of plane z to LDS, together with
 //      the 12p face-halo cells of the plane (three layers per side, read
 //      straight from the face neighbours' interiors: the halo gather of
@@ -27,8 +29,9 @@
 //      own work-group loads that plane (so they are still in L2), and wait
 //      in a small LDS ring until their plane comes;
 //   3. after a barrier each thread forms R of its cell, meets the others at
-//      a second barrier (the LDS is single-buffered: 45 KB, two work-groups
-//      per CU), applies the RK stage update and stores.
+//      a second barrier (the plane LDS is single-buffered: 45 KB, 68 KB with
+//      the halo ring, two work-groups per CU), applies the RK stage update
+//      and stores.
 // The last stage of a step also folds the largest characteristic speeds of
 // the new state into per-unit partials for the next step's dt, and counts
 // non-finite results.
