@@ -91,6 +91,25 @@ def test_column_runs_bitwise(grid):
     assert abs(dt - dts[-1]) <= 1e-14 * dts[-1]
 
 
+def test_window_phases_multiple_of_seven():
+    """The plane loop runs in seven phases (the window's register sets
+    rotate), so a run whose length is a multiple of 7 ends on the last phase:
+    7^3 patches on a (16, 16, 2) grid, one work-group per patch (runs of 7
+    planes), fd_column 1 (256 runs of 14 planes, each crossing a patch top
+    at phase 0) and fd_column 2 (runs of 7), bitwise equal to each other
+    and to the oracle at 1e-12."""
+    announce("fd euler p=7 window phases")
+    b = I.config1(grid=(16, 16, 2), p=7, halo=3, seed=77)
+    o, dts = oracle.fd_step(b, cfl=0.5, sigma=0.1, n_steps=2)
+    ref, dt_ref, _ = run_fd(b, n_steps=2, tuning={"fd_column": 0})
+    assert np.all(rel_err(b, ref, o) <= 1e-12), rel_err(b, ref, o)
+    assert abs(dt_ref - dts[-1]) <= 1e-14 * dts[-1]
+    for w in (1, 2):
+        g, dt, st = run_fd(b, n_steps=2, tuning={"fd_column": w})
+        np.testing.assert_array_equal(g, ref)
+        assert dt == dt_ref and st["nonfinite_units"] == 0
+
+
 def test_ragged_components():
     """Patch sizes 3 (the smallest a halo of 3 allows), 5, 11 and 16 in one
     batch: two 5^3 patches joined along x, the others periodic on
